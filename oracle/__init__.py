@@ -1,0 +1,499 @@
+"""FP64 CPU oracle of the CUBE2 force computation (arXiv 2512.12629).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  It shares no
+code with the HIP path (``paper_2512_12629_amd``) and neither imports the
+other; the two meet only through the seeded inputs of ``synthetic``.
+
+The oracle follows the paper's steps in order, in FP64:
+
+* quantise positions to in-cell integer offsets (IOS, section 2.3);
+* per PM level: CIC mass assignment (section 2.1.2, the CIC kernel in place
+  of the paper's TSC), FFT, multiply by the optimized Green's function
+  (eq. 11 with eqs. 9, 10, 12, 13), inverse FFT, the 4-point finite
+  difference (eq. 7) and CIC interpolation with the same weights;
+* the PP sum of eq. (4d) with the short-range softening handed over by the
+  finest PM level;
+* leapfrog kick and drift (sections 2.2.3 and 2.3);
+* the adjoints of all of the above (not in the paper; derived in the module
+  docstrings and pinned by finite differences in the tests).
+
+The loops live in ``cube2_oracle.c`` (plain C, built with gcc); the FFT is
+numpy's (a library primitive used as one step).
+
+Parity pins: see tests/test_oracle_*.py.  The IOS velocity codec is not
+implemented here (parity unpinned in the paper's terms).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cube2_oracle.c")
+_LIB = os.path.join(_HERE, "_build", "liboracle.so")
+
+FRAC_BITS = 15           # in-cell fraction of a fine cell: 2^-15
+IOS_RATIO = 2            # IOS cell = 2 fine cells (= H_p in every workload)
+TILE_CELLS = 8           # IOS cells per tile side in the particle order
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle's C part with gcc (no fast-math, no contraction)."""
+    os.makedirs(os.path.dirname(_LIB), exist_ok=True)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+               "-fno-fast-math", "-ffp-contract=off", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        d, i, i64, p = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+        sig = {
+            "orc_profile": (d, [d, d]),
+            "orc_refforce": (d, [d, d]),
+            "orc_refforce_dr": (d, [d, d]),
+            "orc_profile_k": (d, [d, d]),
+            "orc_green_point": (d, [i, i, i, i, d, d, i, i]),
+            "orc_green_table": (None, [i, d, d, i, i, p]),
+            "orc_alias_w2_1d": (d, [d, i, i]),
+            "orc_deposit_fx": (None, [i64, p, i, d, p]),
+            "orc_deposit": (None, [i64, p, i, d, i, p]),
+            "orc_fd_force": (None, [i, p, p]),
+            "orc_fd_force_adjoint": (None, [i, p, p]),
+            "orc_interp": (None, [i64, p, i, d, i, p, p]),
+            "orc_interp_adjoint_mesh": (None, [i64, p, i, d, i, p, p]),
+            "orc_interp_adjoint_pos": (None, [i64, p, i, d, i, p, p, p]),
+            "orc_deposit_adjoint_pos": (None, [i64, p, i, d, i, p, p]),
+            "orc_pp_g": (d, [d, d, d]),
+            "orc_pp_dg": (d, [d, d, d]),
+            "orc_pp_brute": (None, [i64, p, d, d, d, p]),
+            "orc_pp": (None, [i64, p, d, d, d, p]),
+            "orc_pp_subset": (None, [i64, p, d, d, d, i64, p, p]),
+            "orc_pp_count": (i64, [i64, p, d, d]),
+            "orc_pp_adjoint": (None, [i64, p, d, d, d, p, p]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# Parameters
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Params:
+    """Force parameters in fine-cell units (section 2.1.1, 2.2).
+
+    coarse_ratio = 0: one PM level with softening b_fine (b_0 = infinity).
+    coarse_ratio = H: a coarse level of spacing H fine cells with softening
+    b_coarse (untruncated) and a fine level with softening b_fine truncated
+    at b_coarse (eq. 4a, 4b); PP softening b_pp, cutoff b_fine (eq. 4d).
+    """
+    n_fine: int
+    coarse_ratio: int = 0
+    b_coarse: float = 14.0
+    b_fine: float = 2.0
+    b_pp: float = 0.2
+    m_p: float = 1.0
+    G_N: float = 1.0
+    alias_nmax: int = 2
+
+    def levels(self):
+        """[(H, n, b_alpha, b_prev)] in fine-cell units; b_prev=inf for PM1."""
+        if self.coarse_ratio:
+            H = self.coarse_ratio
+            return [(H, self.n_fine // H, self.b_coarse, math.inf),
+                    (1, self.n_fine, self.b_fine, self.b_coarse)]
+        return [(1, self.n_fine, self.b_fine, math.inf)]
+
+
+# ---------------------------------------------------------------------------
+# Closed forms (eqs. 1, 2, 13) and the Green's function (eq. 11)
+# ---------------------------------------------------------------------------
+
+def profile(r, b):
+    return lib().orc_profile(float(r), float(b))
+
+
+def refforce(r, b):
+    return lib().orc_refforce(float(r), float(b))
+
+
+def refforce_dr(r, b):
+    return lib().orc_refforce_dr(float(r), float(b))
+
+
+def profile_k(k, b):
+    return lib().orc_profile_k(float(k), -1.0 if math.isinf(b) else float(b))
+
+
+def pp_g(r, b_pp, b_f):
+    return lib().orc_pp_g(float(r), float(b_pp), float(b_f))
+
+
+def pp_dg(r, b_pp, b_f):
+    return lib().orc_pp_dg(float(r), float(b_pp), float(b_f))
+
+
+def alias_w2_1d(k, nmax, p):
+    return lib().orc_alias_w2_1d(float(k), int(nmax), int(p))
+
+
+def _b(b):
+    return -1.0 if math.isinf(b) else float(b)
+
+
+def green_point(n, m, b_a, b_prev, nmax=2, p=2):
+    """G at integer wave vector m (level units: b in level cells)."""
+    return lib().orc_green_point(int(n), int(m[0]), int(m[1]), int(m[2]),
+                                 float(b_a), _b(b_prev), int(nmax), int(p))
+
+
+def green_table(n, b_a, b_prev, nmax=2, p=2):
+    """Octant table G[m3][m2][m1], m_d in [0, n/2], level units."""
+    h = n // 2 + 1
+    out = np.zeros((h, h, h))
+    lib().orc_green_table(int(n), float(b_a), _b(b_prev), int(nmax), int(p), _p(out))
+    return out
+
+
+def green_full(table, n):
+    """Expand the octant table to numpy's rfftn layout [kz, ky, kx]."""
+    m = np.minimum(np.arange(n), n - np.arange(n))
+    h = n // 2 + 1
+    return table[m[:, None, None], m[None, :, None], np.arange(h)[None, None, :]]
+
+
+# ---------------------------------------------------------------------------
+# Positions: quantisation and the IOS particle order (section 2.3)
+# ---------------------------------------------------------------------------
+
+def quantize(x_box: np.ndarray, n_fine: int) -> np.ndarray:
+    """Box-unit positions -> integer positions q in units of 2^-15 fine cells.
+
+    q = floor(x * n_fine * 2^15) mod (n_fine * 2^15), exact in FP64.
+    """
+    span = n_fine << FRAC_BITS
+    q = np.floor(np.asarray(x_box, dtype=np.float64) * span).astype(np.int64)
+    return np.mod(q, span)
+
+
+def q_to_fine(q: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(q.astype(np.float64) / float(1 << FRAC_BITS))
+
+
+def ios_cell_key(q: np.ndarray, n_fine: int) -> np.ndarray:
+    """Tile-major IOS cell index of each particle.
+
+    IOS cell c_d = q_d >> 16 (2 fine cells); tiles of 8^3 IOS cells are laid
+    out x-fastest, and so are the cells inside a tile.
+    """
+    n_ios = n_fine // IOS_RATIO
+    nt = n_ios // TILE_CELLS
+    c = q >> (FRAC_BITS + 1)
+    t = c // TILE_CELLS
+    u = c % TILE_CELLS
+    tile = (t[2] * nt + t[1]) * nt + t[0]
+    inner = (u[2] * TILE_CELLS + u[1]) * TILE_CELLS + u[0]
+    return tile * TILE_CELLS ** 3 + inner
+
+
+def ios_order(q: np.ndarray, n_fine: int):
+    """Stable sort by IOS cell: returns (perm, cell_start, offsets uint16).
+
+    perm[i] is the input index of the i-th sorted particle; cell_start has
+    n_ios^3 + 1 entries; offsets = q & 0xFFFF in sorted order.
+    """
+    key = ios_cell_key(q, n_fine)
+    perm = np.argsort(key, kind="stable")
+    n_cells = (n_fine // IOS_RATIO) ** 3
+    counts = np.bincount(key, minlength=n_cells)
+    cell_start = np.zeros(n_cells + 1, dtype=np.int64)
+    np.cumsum(counts, out=cell_start[1:])
+    off = (q[:, perm] & 0xFFFF).astype(np.uint16)
+    return perm, cell_start.astype(np.uint32), off
+
+
+# ---------------------------------------------------------------------------
+# PM steps
+# ---------------------------------------------------------------------------
+
+def deposit_fx(xf: np.ndarray, n: int, H: float) -> np.ndarray:
+    """Exact integer CIC deposit (uint64), weights in units of 2^-45."""
+    xf = np.ascontiguousarray(xf, dtype=np.float64)
+    out = np.zeros((n, n, n), dtype=np.uint64)
+    lib().orc_deposit_fx(xf.shape[1], _p(xf), int(n), float(H), _p(out))
+    return out
+
+
+def density_f32(acc: np.ndarray) -> np.ndarray:
+    """FP32 density: the integer accumulator rounded to nearest, times 2^-45."""
+    return (acc.astype(np.float32) * np.float32(2.0 ** -45)).astype(np.float32)
+
+
+def deposit(xf: np.ndarray, n: int, H: float, quant: bool = True) -> np.ndarray:
+    xf = np.ascontiguousarray(xf, dtype=np.float64)
+    out = np.zeros((n, n, n))
+    lib().orc_deposit(xf.shape[1], _p(xf), int(n), float(H), int(quant), _p(out))
+    return out
+
+
+def potential(rho: np.ndarray, G_table: np.ndarray) -> np.ndarray:
+    """phi = IFFT(G * FFT(rho)), forward unnormalised, inverse 1/n^3."""
+    n = rho.shape[0]
+    return np.fft.irfftn(np.fft.rfftn(rho) * green_full(G_table, n), s=(n, n, n), axes=(0, 1, 2))
+
+
+def fd_force(phi: np.ndarray) -> np.ndarray:
+    n = phi.shape[0]
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    E = np.zeros((3, n, n, n))
+    lib().orc_fd_force(int(n), _p(phi), _p(E))
+    return E
+
+
+def fd_force_adjoint(Eb: np.ndarray) -> np.ndarray:
+    n = Eb.shape[1]
+    Eb = np.ascontiguousarray(Eb, dtype=np.float64)
+    out = np.zeros((n, n, n))
+    lib().orc_fd_force_adjoint(int(n), _p(Eb), _p(out))
+    return out
+
+
+def interp(xf: np.ndarray, E: np.ndarray, H: float, quant: bool = True) -> np.ndarray:
+    xf = np.ascontiguousarray(xf, dtype=np.float64)
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    n = E.shape[1]
+    acc = np.zeros((3, xf.shape[1]))
+    lib().orc_interp(xf.shape[1], _p(xf), int(n), float(H), int(quant), _p(E), _p(acc))
+    return acc
+
+
+class Oracle:
+    """The force computation for one parameter set, with cached G tables."""
+
+    def __init__(self, params: Params, quant: bool = True):
+        self.p = params
+        self.quant = quant
+        self._G = {}
+
+    def green(self, level: int) -> np.ndarray:
+        if level not in self._G:
+            H, n, b_a, b_prev = self.p.levels()[level]
+            self._G[level] = green_table(n, b_a / H, b_prev / H, self.p.alias_nmax, 2)
+        return self._G[level]
+
+    # -- forward ------------------------------------------------------------
+    def level_mesh(self, xf, level):
+        """(rho, phi, E) of one level, unit particle mass."""
+        H, n, _, _ = self.p.levels()[level]
+        rho = deposit(xf, n, H, self.quant)
+        phi = potential(rho, self.green(level))
+        return rho, phi, fd_force(phi)
+
+    def pm_level_accel(self, xf, level):
+        """Acceleration of one PM level in fine-cell units (G m included)."""
+        H = self.p.levels()[level][0]
+        _, _, E = self.level_mesh(xf, level)
+        return interp(xf, E, H, self.quant) * (self.p.G_N * self.p.m_p / H ** 2)
+
+    def pm_accel(self, xf):
+        return sum(self.pm_level_accel(xf, l) for l in range(len(self.p.levels())))
+
+    def pp_accel(self, xf, brute: bool = False):
+        xf = np.ascontiguousarray(xf, dtype=np.float64)
+        acc = np.zeros((3, xf.shape[1]))
+        f = lib().orc_pp_brute if brute else lib().orc_pp
+        f(xf.shape[1], _p(xf), float(self.p.n_fine), float(self.p.b_pp),
+          float(self.p.b_fine), _p(acc))
+        return acc * (self.p.G_N * self.p.m_p)
+
+    def pp_accel_subset(self, xf, idx):
+        xf = np.ascontiguousarray(xf, dtype=np.float64)
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        acc = np.zeros((3, len(idx)))
+        lib().orc_pp_subset(xf.shape[1], _p(xf), float(self.p.n_fine), float(self.p.b_pp),
+                            float(self.p.b_fine), len(idx), _p(idx), _p(acc))
+        return acc * (self.p.G_N * self.p.m_p)
+
+    def pp_pair_count(self, xf):
+        xf = np.ascontiguousarray(xf, dtype=np.float64)
+        return int(lib().orc_pp_count(xf.shape[1], _p(xf), float(self.p.n_fine),
+                                      float(self.p.b_fine)))
+
+    def accel(self, xf, pp: bool = True):
+        a = self.pm_accel(xf)
+        if pp:
+            a = a + self.pp_accel(xf)
+        return a
+
+    # -- adjoints -------------------------------------------------------------
+    def pm_level_adjoint(self, xf, level, abar):
+        """x-bar of one PM level for the acceleration cotangent abar (3, N).
+
+        With a_i = c sum_n W(y_i - n) E(n), E = -D phi, phi = K rho and
+        rho(n) = sum_j W(y_j - n), c = G m / H^2:
+          Abar = c * sum_i W(y_i - n) abar_i          (scatter)
+          phibar = +D . Abar                          (FD transpose, D^T = -D)
+          rhobar = K phibar                           (G real, even: K^T = K)
+          xbar_i = c grad_x W . (abar_i . E) + grad_x W . rhobar
+        """
+        H = self.p.levels()[level][0]
+        n = self.p.levels()[level][1]
+        c = self.p.G_N * self.p.m_p / H ** 2
+        xf = np.ascontiguousarray(xf, dtype=np.float64)
+        N = xf.shape[1]
+        abar = np.ascontiguousarray(abar, dtype=np.float64)
+        _, _, E = self.level_mesh(xf, level)
+        xbar = np.zeros((3, N))
+        ab_c = np.ascontiguousarray(abar * c)
+        lib().orc_interp_adjoint_pos(N, _p(xf), int(n), float(H), int(self.quant),
+                                     _p(np.ascontiguousarray(E)), _p(ab_c), _p(xbar))
+        Eb = np.zeros((3, n, n, n))
+        lib().orc_interp_adjoint_mesh(N, _p(xf), int(n), float(H), int(self.quant),
+                                      _p(ab_c), _p(Eb))
+        phibar = fd_force_adjoint(Eb)
+        rhobar = np.ascontiguousarray(potential(phibar, self.green(level)))
+        lib().orc_deposit_adjoint_pos(N, _p(xf), int(n), float(H), int(self.quant),
+                                      _p(rhobar), _p(xbar))
+        return xbar
+
+    def pm_adjoint(self, xf, abar):
+        return sum(self.pm_level_adjoint(xf, l, abar) for l in range(len(self.p.levels())))
+
+    def pp_adjoint(self, xf, abar):
+        """xbar_k = G m sum_j J(D_kj) (abar_j - abar_k), J = g I + g' D D^T / r."""
+        xf = np.ascontiguousarray(xf, dtype=np.float64)
+        ab = np.ascontiguousarray(abar, dtype=np.float64)
+        xbar = np.zeros((3, xf.shape[1]))
+        lib().orc_pp_adjoint(xf.shape[1], _p(xf), float(self.p.n_fine), float(self.p.b_pp),
+                             float(self.p.b_fine), _p(ab), _p(xbar))
+        return xbar * (self.p.G_N * self.p.m_p)
+
+    def accel_adjoint(self, xf, abar, pp: bool = True):
+        xb = self.pm_adjoint(xf, abar)
+        if pp:
+            xb = xb + self.pp_adjoint(xf, abar)
+        return xb
+
+    def deposit_adjoint(self, xf, rhobar, level=None):
+        """x-bar of the unit-mass density of the finest level for rhobar."""
+        if level is None:
+            level = len(self.p.levels()) - 1
+        H, n, _, _ = self.p.levels()[level]
+        xf = np.ascontiguousarray(xf, dtype=np.float64)
+        xbar = np.zeros((3, xf.shape[1]))
+        lib().orc_deposit_adjoint_pos(xf.shape[1], _p(xf), int(n), float(H), int(self.quant),
+                                      _p(np.ascontiguousarray(rhobar, dtype=np.float64)),
+                                      _p(xbar))
+        return xbar
+
+
+# ---------------------------------------------------------------------------
+# Time stepping (leapfrog kick-drift, sections 2.2.3 and 2.3)
+# ---------------------------------------------------------------------------
+
+def kick_drift_q(q: np.ndarray, v: np.ndarray, a: np.ndarray, kick: float, drift: float,
+                 n_fine: int):
+    """One kick-drift step on integer positions.
+
+    v' = v + kick * a (FP64, stored FP32); q' = q + rint(drift * v' * 2^15)
+    (round half to even), wrapped into [0, n_fine * 2^15).
+    Velocities are in fine cells per unit time.
+    """
+    v64 = v.astype(np.float64) + float(kick) * a.astype(np.float64)
+    v32 = v64.astype(np.float32)
+    dq = np.rint(float(drift) * v64 * float(1 << FRAC_BITS)).astype(np.int64)
+    span = n_fine << FRAC_BITS
+    return np.mod(q + dq, span), v32
+
+
+def ewald_accel(xf: np.ndarray, L: float, alpha: float | None = None, n_real: int = 2,
+                n_k: int = 12) -> np.ndarray:
+    """Periodic 1/r^2 acceleration of unit point masses by Ewald summation.
+
+    Textbook Ewald split with a neutralising background (no k = 0 term):
+      a_i = sum_j sum_n [erfc(a r)/r^2 + 2a/sqrt(pi) exp(-a^2 r^2)/r] r_hat
+          + (4 pi / V) sum_{k != 0} k/k^2 exp(-k^2/4a^2) sin(k . (x_j - x_i)),
+    with r = x_j - x_i + n L.  For small N (it is O(N^2)).
+    """
+    from scipy.special import erfc
+    xf = np.asarray(xf, dtype=np.float64)
+    N = xf.shape[1]
+    if alpha is None:
+        alpha = 4.0 / L
+    acc = np.zeros((3, N))
+    D = xf[:, None, :] - xf[:, :, None]           # D[:, i, j] = x_j - x_i
+    rng_ = range(-n_real, n_real + 1)
+    for a0 in rng_:
+        for a1 in rng_:
+            for a2 in rng_:
+                s = np.array([a0, a1, a2], dtype=np.float64)[:, None, None] * L
+                R = D + s
+                r = np.sqrt(np.sum(R * R, axis=0))
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    f = (erfc(alpha * r) / r ** 2
+                         + 2 * alpha / math.sqrt(math.pi) * np.exp(-(alpha * r) ** 2) / r) / r
+                f[r == 0.0] = 0.0
+                acc += np.sum(f[None] * R, axis=2)
+    V = L ** 3
+    ks = np.arange(-n_k, n_k + 1)
+    kz, ky, kx = np.meshgrid(ks, ks, ks, indexing="ij")
+    kv = np.stack([kx.ravel(), ky.ravel(), kz.ravel()]).astype(np.float64) * (2 * math.pi / L)
+    k2 = np.sum(kv * kv, axis=0)
+    keep = k2 > 0
+    kv, k2 = kv[:, keep], k2[keep]
+    coef = 4 * math.pi / V * np.exp(-k2 / (4 * alpha ** 2)) / k2
+    phase = kv.T @ xf                              # (K, N)
+    c, s = np.cos(phase), np.sin(phase)
+    Sc, Ss = c.sum(axis=1), s.sum(axis=1)          # structure factor
+    # sum_j sin(k.(x_j - x_i)) = Ss cos(k.x_i) - Sc sin(k.x_i)
+    t = coef[:, None] * (Ss[:, None] * c - Sc[:, None] * s)   # (K, N)
+    acc += kv @ t
+    return acc
+
+
+def reference_accel(xf: np.ndarray, params: Params) -> np.ndarray:
+    """Exact periodic force of softened particles R(r, b_pp) (eq. 3 total).
+
+    Ewald sum of point masses plus the softening correction
+    [R(r, b_pp) - 1/r^2] r_hat for the (minimum-image) pairs with r < b_pp.
+    """
+    L = float(params.n_fine)
+    acc = ewald_accel(xf, L)
+    xf = np.asarray(xf, dtype=np.float64)
+    D = xf[:, None, :] - xf[:, :, None]
+    D = D - L * np.round(D / L)
+    r = np.sqrt(np.sum(D * D, axis=0))
+    N = xf.shape[1]
+    for i in range(N):
+        for j in range(N):
+            if i != j and 0 < r[i, j] < params.b_pp:
+                rr = r[i, j]
+                acc[:, i] += (refforce(rr, params.b_pp) - 1.0 / rr ** 2) * D[:, i, j] / rr
+    return acc * (params.G_N * params.m_p)

@@ -1,0 +1,317 @@
+"""Pins of the oracle's force pipeline against invariants, brute force and
+exact results (none of them re-types the oracle's own formulas)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+
+
+def _fine(x_box, n_f):
+    return oracle.q_to_fine(oracle.quantize(x_box, n_f))
+
+
+# ---------------------------------------------------------------- deposit --
+
+def test_deposit_conserves_mass_exactly():
+    n_f = 32
+    xf = _fine(synthetic.uniform(5000, 11), n_f)
+    for H in (1, 4):
+        acc = oracle.deposit_fx(xf, n_f // H, H)
+        assert int(acc.sum(dtype=np.uint64)) == 5000 * 2 ** 45
+
+
+def test_deposit_particle_on_node_and_fraction():
+    n = 16
+    xf = np.array([[3.0], [5.0], [7.0]])           # exactly on node (3,5,7)
+    acc = oracle.deposit_fx(xf, n, 1)
+    assert acc[7, 5, 3] == 2 ** 45 and acc.sum() == 2 ** 45
+    # quarter cell along x: 3/4 to node 3, 1/4 to node 4 (exact fixed point)
+    xf = np.array([[3.25], [5.0], [7.0]])
+    acc = oracle.deposit_fx(xf, n, 1)
+    assert acc[7, 5, 3] == 3 * 2 ** 43 and acc[7, 5, 4] == 2 ** 43
+    # wrap-around: a particle in the last cell feeds node 0
+    xf = np.array([[15.5], [0.0], [0.0]])
+    acc = oracle.deposit_fx(xf, n, 1)
+    assert acc[0, 0, 15] == 2 ** 44 and acc[0, 0, 0] == 2 ** 44
+
+
+def test_deposit_coarse_fraction_truncated_to_15_bits():
+    # On a level of spacing 4, the fraction has 17 bits; the fixed-point
+    # reading keeps the top 15.
+    q = np.array([[(5 << 17) + 0b101], [0], [0]], dtype=np.int64)   # 5 coarse cells + 5/2^17
+    xf = oracle.q_to_fine(q)
+    acc = oracle.deposit_fx(xf, 8, 4)
+    f = 0b101 >> 2
+    assert acc[0, 0, 5] == (2 ** 15 - f) * 2 ** 30 and acc[0, 0, 6] == f * 2 ** 30
+
+
+def test_deposit_translation_permutes_mesh():
+    n = 16
+    xf = _fine(synthetic.uniform(300, 12), n)
+    a0 = oracle.deposit_fx(xf, n, 1)
+    shift = np.array([[3.0], [1.0], [5.0]])
+    a1 = oracle.deposit_fx(np.mod(xf + shift, n), n, 1)
+    assert np.array_equal(np.roll(a0, (5, 1, 3), axis=(0, 1, 2)), a1)
+
+
+def test_integer_and_float_deposit_agree():
+    n = 16
+    xf = _fine(synthetic.uniform(1000, 13), n)
+    acc = oracle.deposit_fx(xf, n, 1)
+    rho = oracle.deposit(xf, n, 1, quant=True)
+    assert np.allclose(acc.astype(np.float64) * 2.0 ** -45, rho, rtol=1e-15, atol=0)
+
+
+def test_deposit_brute_force_small():
+    # every node value from the definition W = prod (1 - |x_d - n_d|)_+
+    n = 8
+    xf = _fine(synthetic.uniform(20, 14), n)
+    rho = oracle.deposit(xf, n, 1, quant=True)
+    ref = np.zeros((n, n, n))
+    for i in range(xf.shape[1]):
+        for z in range(n):
+            for y in range(n):
+                for x in range(n):
+                    w = 1.0
+                    for d, node in enumerate((x, y, z)):
+                        dd = abs(xf[d, i] - node)
+                        dd = min(dd, n - dd)
+                        w *= max(0.0, 1 - dd)
+                    ref[z, y, x] += w
+    assert np.allclose(rho, ref, atol=1e-13)
+
+
+# ---------------------------------------------------------------- PM force --
+
+@pytest.fixture(scope="module")
+def oracle64():
+    return oracle.Oracle(oracle.Params(n_fine=64))
+
+
+def test_single_particle_has_no_self_force(oracle64):
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        xf = rng.random((3, 1)) * 64
+        a = oracle64.pm_accel(xf)
+        assert np.abs(a).max() < 1e-12
+
+
+def test_pair_forces_are_equal_and_opposite(oracle64):
+    rng = np.random.default_rng(4)
+    for _ in range(5):
+        xf = rng.random((3, 2)) * 64
+        a = oracle64.accel(xf)
+        assert np.abs(a[:, 0] + a[:, 1]).max() < 1e-12 * max(1.0, np.abs(a).max())
+
+
+def test_momentum_conservation(oracle64):
+    xf = _fine(synthetic.uniform(4096, 15), 64)
+    a = oracle64.accel(xf)
+    assert np.abs(a.sum(axis=1)).max() < 1e-10 * np.abs(a).max() * 4096
+
+
+def test_pair_force_newtonian_far_field(oracle64):
+    # r >> b: the PM force of a pair is the periodic point-mass force.
+    rng = np.random.default_rng(5)
+    for r in (10.0, 20.0):
+        for _ in range(4):
+            c = rng.random(3) * 64
+            u = rng.standard_normal(3)
+            u /= np.linalg.norm(u)
+            xf = np.mod(np.stack([c, c + r * u], axis=1), 64)
+            a = oracle64.accel(xf)[:, 0]
+            ref = oracle.ewald_accel(xf, 64.0)[:, 0]
+            assert np.linalg.norm(a - ref) / np.linalg.norm(ref) < 0.06
+
+
+def test_attractive(oracle64):
+    xf = np.array([[10.0, 13.0], [20.0, 20.0], [30.0, 30.0]])
+    a = oracle64.accel(xf)
+    assert a[0, 0] > 0 and a[0, 1] < 0
+
+
+def test_two_level_sum_matches_single_level_far_field():
+    # The coarse level (b_c) plus the truncated fine level add up to the
+    # force softened at b_f; for r >> b_c both equal the Newtonian force.
+    p2 = oracle.Params(n_fine=64, coarse_ratio=4, b_coarse=14.0, b_fine=2.0)
+    o2 = oracle.Oracle(p2)
+    rng = np.random.default_rng(6)
+    for _ in range(3):
+        c = rng.random(3) * 64
+        u = rng.standard_normal(3)
+        u /= np.linalg.norm(u)
+        xf = np.mod(np.stack([c, c + 24.0 * u], axis=1), 64)
+        a = o2.accel(xf)[:, 0]
+        ref = oracle.ewald_accel(xf, 64.0)[:, 0]
+        assert np.linalg.norm(a - ref) / np.linalg.norm(ref) < 0.05
+        # the fine level is truncated at b_c: no force at r = 24 > b_c
+        af = o2.pm_level_accel(xf, 1)[:, 0]
+        assert np.linalg.norm(af) < 0.05 * np.linalg.norm(ref)
+
+
+def test_total_force_against_ewald():
+    # Exact periodic force of softened particles vs PM+PP.  With beta = 6 the
+    # method's error is a few percent; the error profile for the production
+    # setting (CIC, b_f = 2) is reported by the benchmark, not gated.
+    p = oracle.Params(n_fine=32, b_fine=6.0, b_pp=0.6)
+    xf = _fine(synthetic.uniform(256, 16), 32)
+    a = oracle.Oracle(p).accel(xf)
+    ref = oracle.reference_accel(xf, p)
+    err = np.linalg.norm(a - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert np.median(err) < 0.03
+    rel_rms = np.linalg.norm(a - ref) / np.linalg.norm(ref)
+    assert rel_rms < 0.05
+
+
+def test_ewald_alpha_independent():
+    xf = synthetic.uniform(40, 17).astype(np.float64) * 16
+    a1 = oracle.ewald_accel(xf, 16.0, alpha=3.0 / 16, n_real=2, n_k=10)
+    a2 = oracle.ewald_accel(xf, 16.0, alpha=5.0 / 16, n_real=2, n_k=16)
+    assert np.abs(a1 - a2).max() < 1e-10 * np.abs(a1).max()
+
+
+def test_ewald_short_range_is_newtonian():
+    xf = np.array([[5.0, 5.01], [5.0, 5.0], [5.0, 5.0]])
+    a = oracle.ewald_accel(xf, 16.0)
+    assert a[0, 0] == pytest.approx(1 / 0.01 ** 2, rel=1e-6)
+
+
+# ---------------------------------------------------------------------- PP --
+
+def test_pp_cell_list_matches_brute_force():
+    p = oracle.Params(n_fine=32)
+    o = oracle.Oracle(p)
+    x = synthetic.clustered(16, 0.25, 2, 400, 0.5 / 32, 18)
+    xf = _fine(x, 32)
+    a1 = o.pp_accel(xf)
+    a2 = o.pp_accel(xf, brute=True)
+    assert np.abs(a1 - a2).max() <= 1e-12 * np.abs(a2).max()
+    sub = np.arange(0, xf.shape[1], 7)
+    a3 = o.pp_accel_subset(xf, sub)
+    assert np.abs(a3 - a2[:, sub]).max() <= 1e-12 * np.abs(a2).max()
+
+
+def test_pp_pair_law():
+    p = oracle.Params(n_fine=32)
+    o = oracle.Oracle(p)
+    for r in (0.05, 0.15, 0.5, 1.5, 2.5):
+        xf = np.array([[3.0, 3.0 + r], [4.0, 4.0], [5.0, 5.0]])
+        a = o.pp_accel(xf)
+        want = 0.0 if r >= 2 else oracle.refforce(r, 0.2) - oracle.refforce(r, 2.0)
+        assert a[0, 0] == pytest.approx(want, rel=1e-14, abs=1e-300)
+        assert a[0, 1] == pytest.approx(-want, rel=1e-14, abs=1e-300)
+
+
+def test_pp_coincident_particles_give_zero():
+    p = oracle.Params(n_fine=32)
+    xf = np.array([[3.0, 3.0], [4.0, 4.0], [5.0, 5.0]])
+    assert np.all(oracle.Oracle(p).pp_accel(xf) == 0.0)
+
+
+# ----------------------------------------------------------------- adjoints --
+
+def _away_from_faces(xf, Hs, margin):
+    ok = np.ones(xf.shape[1], dtype=bool)
+    for H in Hs:
+        fr = np.mod(xf / H, 1.0)
+        ok &= np.all((fr > margin) & (fr < 1 - margin), axis=0)
+    return ok
+
+
+@pytest.mark.parametrize("two_level", [False, True])
+def test_force_adjoint_matches_finite_differences(two_level):
+    # <xbar, v> = d/de sum(abar . a(x + e v)) by FP64 central differences on
+    # the continuous-position forward (no quantisation).
+    p = oracle.Params(n_fine=32, coarse_ratio=4 if two_level else 0, b_coarse=14.0)
+    o = oracle.Oracle(p, quant=False)
+    rng = np.random.default_rng(21)
+    xf = rng.random((3, 200)) * 32
+    keep = _away_from_faces(xf, [1, 4], 0.02)
+    xf = np.ascontiguousarray(xf[:, keep])
+    N = xf.shape[1]
+    abar = rng.standard_normal((3, N))
+    xbar = o.accel_adjoint(xf, abar)
+    for _ in range(3):
+        v = rng.standard_normal((3, N))
+        h = 1e-5
+        fp = np.sum(abar * o.accel(xf + h * v))
+        fm = np.sum(abar * o.accel(xf - h * v))
+        fd = (fp - fm) / (2 * h)
+        assert np.sum(xbar * v) == pytest.approx(fd, rel=2e-6)
+
+
+def test_deposit_adjoint_matches_finite_differences():
+    o = oracle.Oracle(oracle.Params(n_fine=16), quant=False)
+    rng = np.random.default_rng(22)
+    xf = rng.random((3, 100)) * 16
+    xf = np.ascontiguousarray(xf[:, _away_from_faces(xf, [1], 0.02)])
+    rhobar = rng.standard_normal((16, 16, 16))
+    xbar = o.deposit_adjoint(xf, rhobar)
+    v = rng.standard_normal(xf.shape)
+    h = 1e-6
+    f = lambda y: np.sum(rhobar * oracle.deposit(y, 16, 1, quant=False))
+    fd = (f(xf + h * v) - f(xf - h * v)) / (2 * h)
+    assert np.sum(xbar * v) == pytest.approx(fd, rel=1e-7)
+
+
+def test_pp_adjoint_is_symmetric_jacobian():
+    # brute-force dense Jacobian by FD on a tiny clustered set
+    p = oracle.Params(n_fine=16)
+    o = oracle.Oracle(p, quant=False)
+    rng = np.random.default_rng(23)
+    xf = 5.0 + rng.random((3, 12)) * 1.5
+    N = xf.shape[1]
+    abar = rng.standard_normal((3, N))
+    xbar = o.pp_adjoint(xf, abar)
+    h = 1e-7
+    J = np.zeros((3 * N, 3 * N))
+    for k in range(3 * N):
+        e = np.zeros(3 * N)
+        e[k] = h
+        e = e.reshape(3, N)
+        J[:, k] = ((o.pp_accel(xf + e) - o.pp_accel(xf - e)) / (2 * h)).ravel()
+    assert np.allclose(xbar.ravel(), J.T @ abar.ravel(), rtol=1e-5, atol=1e-6 * np.abs(xbar).max())
+
+
+# --------------------------------------------------------------- kick-drift --
+
+def test_kick_drift_constant_acceleration_is_quadratic():
+    n_f = 64
+    q = np.array([[10 << 15], [20 << 15], [30 << 15]], dtype=np.int64)
+    v = np.zeros((3, 1), dtype=np.float32)
+    a = np.array([[0.5], [-0.25], [0.0]], dtype=np.float32)
+    dt = 0.125
+    for _ in range(8):
+        q, v = oracle.kick_drift_q(q, v, a, dt, dt, n_f)
+    # leapfrog KD with constant a: x_n = x_0 + a dt^2 n(n+1)/2 (exact here)
+    n = 8
+    expect = np.array([10, 20, 30]) + np.array([0.5, -0.25, 0]) * dt * dt * n * (n + 1) / 2
+    assert np.allclose(q[:, 0] / 2.0 ** 15, expect, atol=0)
+    assert np.allclose(v[:, 0], np.array([0.5, -0.25, 0]) * dt * n)
+
+
+def test_kick_drift_wraps():
+    n_f = 16
+    span = n_f << 15
+    q = np.array([[span - 1], [0], [5]], dtype=np.int64)
+    v = np.array([[1.0], [-1.0], [0.0]], dtype=np.float32)
+    q2, _ = oracle.kick_drift_q(q, v, np.zeros((3, 1), np.float32), 0.0, 1.0, n_f)
+    assert q2[0, 0] == (span - 1 + (1 << 15)) % span and q2[1, 0] == span - (1 << 15)
+
+
+def test_ios_order_is_a_stable_permutation():
+    n_f = 32
+    q = oracle.quantize(synthetic.uniform(3000, 24), n_f)
+    perm, cs, off = oracle.ios_order(q, n_f)
+    assert np.array_equal(np.sort(perm), np.arange(3000))
+    key = oracle.ios_cell_key(q, n_f)[perm]
+    assert np.all(np.diff(key) >= 0)
+    same = np.diff(key) == 0
+    assert np.all(np.diff(perm)[same] > 0)             # stable
+    assert cs[0] == 0 and cs[-1] == 3000
+    assert np.array_equal(np.diff(cs.astype(np.int64)), np.bincount(key, minlength=len(cs) - 1))
+    # offsets plus the cell of each particle give back its position
+    assert np.array_equal(off.astype(np.int64), q[:, perm] & 0xFFFF)
