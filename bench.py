@@ -1,0 +1,236 @@
+"""Benchmark of the CUBE2 force step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload clu512]
+
+Times K force evaluations (two-level PM + PP, inputs resident in HBM) with HIP
+events on the stream the library launches on, then the full step (force +
+kick-drift + IOS re-sort), the adjoint (PM + PP backward) and the stages, and
+prints one JSON line.  value = N / t_force (particles per second per force
+step).  A CPU baseline (the FP64 oracle, on a bounded sample of the same
+workload recipe) is timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synthetic  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+# FP32 VALU without packed math: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA)
+VALU_FP32_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12   # 78.64
+
+WORKLOADS = {
+    "clu512": dict(n_fine=1024, coarse_ratio=4,
+                   desc="512^3 particles, Zel'dovich k^-2 (rms 0.25 H_p) + 8000 Plummer spheres "
+                        "x 2048 (a = 0.5 fine cell); fine mesh 1024^3, coarse 256^3; "
+                        "b_c=14, b_f=2 (PP cutoff), b_pp=0.2 fine cells"),
+    "clu256": dict(n_fine=512, coarse_ratio=4,
+                   desc="256^3 particles, Zel'dovich + 1000 Plummer spheres x 2048; fine 512^3, "
+                        "coarse 128^3"),
+    "zel128": dict(n_fine=256, coarse_ratio=0,
+                   desc="128^3 particles, Zel'dovich k^-2; single-level 256^3 mesh"),
+}
+
+# Algorithmic FP32 flops (FMA = 2) of one in-cutoff PP pair as the pair law
+# is written: 3 differences, r^2 (5), rsqrt (1), r and t (2), the fine
+# polynomial branch (12), scale (1), r^-3 (2), difference (1), 3 FMA (6).
+PP_FLOPS_PER_PAIR = 33
+
+
+def pair_counts():
+    path = os.path.join(ROOT, "tests", "golden", "pair_counts.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def fft_bytes_reference(n: int, pitch: int) -> float:
+    """Traffic of the 5-sweep FFT-G-IFFT pipeline of one level, bytes.
+
+    x pass: read n^3 reals, write n*n*pitch complex; y pass, z pass (with G),
+    inverse y: read+write the spectrum; G octant read once; inverse x: read
+    the spectrum, write n^3 reals."""
+    spec = n * n * pitch * 8.0
+    real = n ** 3 * 4.0
+    h = n // 2 + 1
+    return (real + spec) + 2 * spec + (2 * spec + h ** 3 * 4.0) + 2 * spec + (spec + real)
+
+
+def cpu_baseline(workload: str):
+    """Oracle (FP64, as is) on a bounded sample: the same recipe at 1/64 of
+    the volume (n_p = 128, same sphere density), full PM + PP force."""
+    import oracle
+    w = WORKLOADS[workload]
+    scale = 4 if workload == "clu512" else 2
+    n_p = synthetic.WORKLOADS[workload]["n_p"] // scale
+    n_f = w["n_fine"] // scale
+    x = synthetic.make(workload, n_p=n_p)
+    p = oracle.Params(n_fine=n_f, coarse_ratio=w["coarse_ratio"])
+    o = oracle.Oracle(p)
+    for lvl in range(len(p.levels())):
+        o.green(lvl)                      # tables are built before the timing
+    q = oracle.quantize(x, n_f)
+    xf = oracle.q_to_fine(q)
+    t0 = time.perf_counter()
+    o.accel(xf)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": x.shape[1] / dt, "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "sample": f"{workload} recipe at 1/{scale ** 3} volume: {x.shape[1]} particles, "
+                      f"fine mesh {n_f}^3, full FP64 PM+PP force, {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="clu512", choices=list(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time only the force step (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is a design, not a build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2512_12629_amd as m
+
+    torch.cuda.set_device(0)
+    w = WORKLOADS[args.workload]
+    t_gen = time.perf_counter()
+    x_np = synthetic.make(args.workload)
+    N = x_np.shape[1]
+    print(f"[bench] inputs {args.workload}: N={N} in {time.perf_counter() - t_gen:.1f}s",
+          file=sys.stderr, flush=True)
+    cfg = m.Config(n_fine=w["n_fine"], coarse_ratio=w["coarse_ratio"])
+    t_init = time.perf_counter()
+    c = m.Cube2(cfg, n_max=N)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t_init
+    x = torch.from_numpy(x_np).cuda()
+    del x_np
+    pos, cs, _ = c.pack(x)
+    del x
+    vel = torch.zeros((3, N), dtype=torch.float32, device="cuda")
+    acc = torch.empty((3, N), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def force():
+        m.cube2_pm_force(c.ctx, pos, cs, acc, c.work)
+        m.cube2_pp_force(c.ctx, pos, cs, acc, c.work, accumulate=True)
+
+    def timed(fn, k):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(k)]
+        torch.cuda.synchronize()
+        for a, b in evs:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in evs]
+
+    for _ in range(args.warmup):
+        force()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ts = timed(force, args.steps)
+    wall = time.perf_counter() - t0
+    print(f"[bench] force: {np.median(ts):.3f} ms median over {args.steps}", file=sys.stderr,
+          flush=True)
+    status = c.status()
+    ms = float(np.mean(ts))
+    out = {
+        "metric": "particles/sec per full PM+PP force step",
+        "value": N / (ms * 1e-3),
+        "unit": "particles/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "description": w["desc"], "particles": N,
+                   "n_fine": w["n_fine"], "coarse_ratio": w["coarse_ratio"]},
+        "force_ms_median": float(np.median(ts)),
+        "wall_s_timed": wall, "table_init_s": t_init, "status": status,
+    }
+    if not args.no_extras:
+        # stages (each is one C-ABI entry point on the same stream)
+        n_f, pitch_f = c.level_shape(0)
+        rho = c.deposit(pos, cs, 0)
+        t_pm = timed(lambda: m.cube2_pm_force(c.ctx, pos, cs, acc, c.work), args.steps)
+        t_pp = timed(lambda: m.cube2_pp_force(c.ctx, pos, cs, acc, c.work), args.steps)
+        t_pot = timed(lambda: m.cube2_potential(c.ctx, 0, rho, rho, c.work), args.steps)
+        t_dep = timed(lambda: m.cube2_deposit(c.ctx, pos, cs, 0, rho, None, c.work), args.steps)
+        stages = {"pm_force": float(np.mean(t_pm)), "pp_force": float(np.mean(t_pp)),
+                  "potential_fine": float(np.mean(t_pot)), "deposit_fine": float(np.mean(t_dep))}
+        # full step: force + kick-drift + IOS re-sort (ping-pong state)
+        st = [pos, cs, vel]
+        bufs = [torch.empty_like(pos), torch.empty_like(cs), torch.empty_like(vel)]
+        perm = torch.empty(N, dtype=torch.int32, device="cuda")
+
+        def full_step():
+            m.cube2_pm_force(c.ctx, st[0], st[1], acc, c.work)
+            m.cube2_pp_force(c.ctx, st[0], st[1], acc, c.work, accumulate=True)
+            m.cube2_kick_drift(c.ctx, st[0], st[1], st[2], acc, 1e-3, 1e-3, bufs[0], bufs[1],
+                               bufs[2], perm, c.work)
+            for i in range(3):
+                st[i], bufs[i] = bufs[i], st[i]
+
+        t_full = timed(full_step, max(2, args.steps // 2))
+        # adjoint of the force (PM + PP), same positions
+        abar = torch.randn((3, N), dtype=torch.float32, device="cuda")
+        xbar = torch.empty_like(abar)
+
+        def backward():
+            m.cube2_pm_force_backward(c.ctx, st[0], st[1], abar, xbar, c.work)
+            m.cube2_pp_force_backward(c.ctx, st[0], st[1], abar, xbar, c.work, accumulate=True)
+
+        t_bwd = timed(backward, max(2, args.steps // 2))
+        stages["kick_drift_resort"] = float(np.mean(t_full)) - ms
+        out["full_step_ms"] = float(np.mean(t_full))
+        out["backward_ms"] = float(np.mean(t_bwd))
+        out["backward_forward_ratio"] = float(np.mean(t_bwd)) / ms
+        out["stages_ms"] = stages
+
+        # roofline of the dominant kernel
+        counts = pair_counts()
+        pairs = counts.get(args.workload)
+        t_pp_s = stages["pp_force"] * 1e-3
+        fft_bytes = fft_bytes_reference(n_f, pitch_f)
+        t_fft_s = stages["potential_fine"] * 1e-3
+        if stages["pp_force"] >= stages["potential_fine"] and pairs:
+            ach = pairs * PP_FLOPS_PER_PAIR / t_pp_s / 1e12
+            out["roofline"] = {"kernel": "pp_kernel", "bound": "alu", "achieved": ach,
+                               "peak": VALU_FP32_TFLOPS, "unit": "TFLOP/s",
+                               "frac": ach / VALU_FP32_TFLOPS, "traffic": None,
+                               "pairs": pairs, "flops_per_pair": PP_FLOPS_PER_PAIR}
+        else:
+            ach = fft_bytes / t_fft_s / 1e9
+            out["roofline"] = {"kernel": "fine potential (5 FFT sweeps)", "bound": "hbm",
+                               "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": ach / HBM_PEAK_GBS, "traffic": None}
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(args.workload)
+        except Exception as e:  # the baseline is reported, not required
+            out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

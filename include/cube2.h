@@ -1,0 +1,241 @@
+/*
+ * cube2.h -- C ABI of the MI355X (gfx950) implementation of the CUBE2 force
+ * computation (Yu et al., "CUBE2: A Parallel N-Body Simulation Code for
+ * Scalability, Accuracy, and Memory Efficiency", arXiv 2512.12629).
+ *
+ * What is computed (section 2.1, eqs. 3-4): the gravitational acceleration of
+ * N equal-mass particles in a periodic cube, split into
+ *   - a coarse PM level with softening b_coarse (eq. 4a, untruncated),
+ *   - a fine PM level with softening b_fine truncated at b_coarse (eq. 4b),
+ *   - a short-range particle-particle (PP) sum, softening b_pp, cut off at
+ *     b_fine (eq. 4d with the finest PM level's softening as the cutoff),
+ * where each PM level assigns mass with the cloud-in-cell kernel, solves
+ * Poisson's equation by FFT with the optimized Green's function of eq. (11),
+ * differentiates with the 4-point stencil of eq. (7) and interpolates with
+ * the assignment kernel (section 2.1.2).  Leapfrog kick and drift act on
+ * integer in-cell positions (IOS storage, section 2.3).  The *_backward
+ * entry points are the adjoints (vector-Jacobian products) of the forward
+ * ones; the paper has none, they are derived from the forward definitions.
+ *
+ * Units.  Inside the library lengths are in fine mesh cells (the fine mesh
+ * has n_fine cells per side; the box side is n_fine).  Positions are integers
+ * q in units of 2^-15 fine cells, q in [0, n_fine * 2^15).  The particle
+ * "IOS" form stores, for particles sorted by their IOS cell (2x2x2 fine
+ * cells), the low 16 bits of q per axis (uint16 SoA, pos[d*n + i]) and the
+ * exclusive prefix count of particles per IOS cell (cell_start).  IOS cells
+ * are ordered tile-major: tiles of 8^3 IOS cells, x fastest, and x fastest
+ * inside a tile.  Velocities are fine cells per unit time, accelerations
+ * fine cells per unit time^2, FP32 SoA (v[d*n + i]) in the particle order.
+ *
+ * Memory.  The caller owns all device memory.  cube2_sizes() gives the byte
+ * sizes of two buffers: `tables` (persistent: Green's-function tables,
+ * twiddles, the device status word; must outlive every call) and `work`
+ * (scratch reused by every call; its contents are undefined between calls).
+ * The library never allocates device memory.  Pointers marked (device) are
+ * device addresses; pointers marked (host) are host addresses.
+ *
+ * Streams.  Every call enqueues work on `stream` (a hipStream_t, 0 = the
+ * default stream) and returns without synchronising, except cube2_status
+ * and cube2_reduce's host read-back.  One context must not be used from two
+ * streams at once; calls sharing one `work` buffer must be serialised.
+ *
+ * Errors.  Every call returns 0 (CUBE2_OK) or a negative code.  Argument
+ * errors are detected on the host before anything is enqueued.  Device-side
+ * conditions (a deposit accumulator that could overflow) set bits in the
+ * device status word, which cube2_status() reports and clears.  Nothing is
+ * printed and no exception crosses the ABI.
+ */
+#ifndef CUBE2_H
+#define CUBE2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* hipStream_t without requiring the HIP headers. */
+typedef struct ihipStream_t *cube2_stream_t;
+
+enum cube2_status_code {
+    CUBE2_OK = 0,
+    CUBE2_EINVAL = -1,        /* bad argument (null pointer, size, level) */
+    CUBE2_EUNSUPPORTED = -2,  /* configuration outside the supported set */
+    CUBE2_EWORKSPACE = -3,    /* tables or work buffer too small */
+    CUBE2_EOVERFLOW = -4,     /* deposit accumulator could overflow (status) */
+    CUBE2_EHIP = -5,          /* a HIP runtime call failed */
+    CUBE2_ESTATE = -6         /* tables not initialised */
+};
+
+enum cube2_flags {
+    CUBE2_PP_OFF = 1          /* cube2_pp_force becomes a no-op (paper, sec. 4:
+                                 PP may be disabled for fast runs) */
+};
+
+/* Force parameters (section 2.1.1 and 2.2.2).  All lengths in fine cells. */
+typedef struct cube2_config {
+    int32_t n_fine;        /* fine cells per side: power of two, 16..1024 */
+    int32_t coarse_ratio;  /* 0 = one PM level; else the coarse spacing in fine
+                              cells: 2, 4 or 8, with n_fine/coarse_ratio >= 8 */
+    double  b_coarse;      /* coarse softening b_1 (ignored with one level) */
+    double  b_fine;        /* fine softening, also the PP cutoff; (0, 2] so
+                              that PP pairs lie in adjacent IOS cells */
+    double  b_pp;          /* PP softening b_PP, 0 < b_pp < b_fine */
+    double  m_p;           /* particle mass */
+    double  g_newton;      /* coupling constant G */
+    int32_t alias_nmax;    /* alias sum |n_d| <= alias_nmax in eq. (11); the
+                              paper truncates at 2 (section 2.1.2); 0..4 */
+    int32_t flags;         /* cube2_flags */
+} cube2_config;
+
+typedef struct cube2_ctx cube2_ctx;
+
+/* Validate `cfg` and create a host-side context (no device work).
+ * Returns CUBE2_EUNSUPPORTED for sizes or ratios outside the set above and
+ * CUBE2_EINVAL for non-positive softenings or b_pp >= b_fine. */
+int cube2_create(const cube2_config *cfg, cube2_ctx **out);
+
+/* Free a context (host memory only; device buffers belong to the caller). */
+void cube2_destroy(cube2_ctx *ctx);
+
+/* Byte sizes of the tables buffer and of the work buffer needed for up to
+ * n_max particles. (host) outputs. */
+int cube2_sizes(const cube2_ctx *ctx, int64_t n_max, size_t *table_bytes, size_t *work_bytes);
+
+/* Mesh geometry of level 0 (fine) or 1 (coarse): cells per side and the
+ * complex row pitch P (in complex elements) of the half-spectrum layout
+ * [kz][ky][kx], kx in [0, n/2] padded to P. */
+int cube2_level_shape(const cube2_ctx *ctx, int level, int32_t *n, int32_t *pitch);
+
+/* Build the Green's-function tables (eq. 11 with CIC W, eq. 10 D, eq. 12 R,
+ * eq. 13 S; alias sum over |n_d| <= alias_nmax) in FP64 on the device and
+ * store them in FP32 octant form, G[|mz|][|my|][mx], plus FFT twiddles, into
+ * `tables` (device, table_bytes from cube2_sizes).  Runs once; the context
+ * keeps the pointer. */
+int cube2_init_tables(cube2_ctx *ctx, void *tables, size_t table_bytes, cube2_stream_t stream);
+
+/* Copy the level's Green's table (FP32, (n/2+1)^3, [mz][my][mx]) to `out`
+ * (device). */
+int cube2_green_table(const cube2_ctx *ctx, int level, float *out, cube2_stream_t stream);
+
+/* Quantise FP32 box-unit positions x (device, x[d*n+i] in [0,1)) to the
+ * IOS form (section 2.3): q = floor(x * n_fine * 2^15) mod (n_fine * 2^15),
+ * then sort stably by IOS cell.  Outputs (device): pos (3*n uint16 in-cell
+ * offsets), cell_start ((n_fine/2)^3 + 1 prefix counts) and perm (n int32;
+ * perm[i] = input index of sorted particle i). */
+int cube2_pack(cube2_ctx *ctx, const float *x, int64_t n, uint16_t *pos, uint32_t *cell_start,
+               int32_t *perm, void *work, size_t work_bytes, cube2_stream_t stream);
+
+/* CIC mass assignment of one level (section 2.1.2 step 1, CIC kernel):
+ * acc(node) = sum_i prod_d w_d, w = (2^15 - f, f), f the 15-bit in-cell
+ * fraction of the particle on that level, summed exactly in uint64; the
+ * FP32 density (particle masses per level cell) is acc rounded to nearest
+ * times 2^-45.  level 0 = fine (n_fine^3), 1 = coarse.  rho (device,
+ * [z][y][x]) receives the FP32 density; rho_fx (device, optional, may be
+ * NULL) receives the integer accumulator.  Bit-exact and order independent.
+ * Sets CUBE2_EOVERFLOW in the status word if a tile holds 2^16 or more
+ * particles (an accumulator could then exceed 64 bits). */
+int cube2_deposit(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                  int level, float *rho, uint64_t *rho_fx, void *work, size_t work_bytes,
+                  cube2_stream_t stream);
+
+/* Forward unnormalised real-to-complex 3D FFT of a level mesh (device, n^3
+ * FP32) into `spec` (device, n*n*P complex64 [kz][ky][kx]); entries beyond
+ * kx = n/2 are zero.  Exposed for testing the transform. */
+int cube2_fft_r2c(cube2_ctx *ctx, int level, const float *mesh, float *spec, void *work,
+                  size_t work_bytes, cube2_stream_t stream);
+
+/* Potential of a level (section 2.1.2 step 2): phi = IFFT(G * FFT(rho)),
+ * inverse normalised by 1/n^3.  rho and phi (device, n^3 FP32) may alias. */
+int cube2_potential(cube2_ctx *ctx, int level, const float *rho, float *phi, void *work,
+                    size_t work_bytes, cube2_stream_t stream);
+
+/* Finite-difference force and CIC interpolation (section 2.1.2 steps 3-4):
+ * E = -D phi with the 4-point stencil of eq. (7), interpolated with the
+ * deposit's integer weights; both levels are gathered in one particle sweep
+ * (phi_coarse may be NULL with one level).  acc (device, 3*n FP32) receives
+ * G m_p sum_levels H^-2 (W * E), H the level spacing; accumulate != 0 adds. */
+int cube2_interp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                 const float *phi_fine, const float *phi_coarse, float *acc, int accumulate,
+                 cube2_stream_t stream);
+
+/* The whole PM force of all levels: deposit, potential, interpolation.
+ * acc (device, 3*n FP32), accumulate != 0 adds to it. */
+int cube2_pm_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                   float *acc, int accumulate, void *work, size_t work_bytes,
+                   cube2_stream_t stream);
+
+/* PP force (eq. 4d): a_i += G m_p sum_{j != i, 0 < r < b_fine}
+ * [R(r,b_pp) - R(r,b_fine)] (x_j - x_i)/r with R of eq. (2) and the exact
+ * minimum-image integer separation, in FP32 with compensated summation.
+ * acc (device, 3*n FP32), accumulate != 0 adds to it. */
+int cube2_pp_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                   float *acc, int accumulate, void *work, size_t work_bytes,
+                   cube2_stream_t stream);
+
+/* Leapfrog kick and drift (sections 2.2.3, 2.3): v' = v + kick*a and
+ * q' = q + rint(drift * v' * 2^15) (round half even, FP64 arithmetic),
+ * wrapped periodically, then a stable re-sort by IOS cell.  Inputs (device):
+ * pos_in, cell_start_in, vel_in (3*n), acc (3*n).  Outputs (device, must not
+ * alias the inputs): pos_out, cell_start_out, vel_out, perm_out (perm_out[i] =
+ * input slot of output particle i). */
+int cube2_kick_drift(cube2_ctx *ctx, const uint16_t *pos_in, const uint32_t *cell_start_in,
+                     const float *vel_in, const float *acc, int64_t n, double kick, double drift,
+                     uint16_t *pos_out, uint32_t *cell_start_out, float *vel_out,
+                     int32_t *perm_out, void *work, size_t work_bytes, cube2_stream_t stream);
+
+/* FP64 diagnostics (device reductions, deterministic order): out8 (host) =
+ * { m sum v_x, m sum v_y, m sum v_z, (m/2) sum |v|^2,
+ *   m sum a_x, m sum a_y, m sum a_z, max |a| }.  vel may be NULL (zeros).
+ * Synchronises the stream. */
+int cube2_reduce(cube2_ctx *ctx, const float *vel, const float *acc, int64_t n, double *out8,
+                 void *work, size_t work_bytes, cube2_stream_t stream);
+
+/* Synchronise the stream and return the device status (CUBE2_OK or
+ * CUBE2_EOVERFLOW), clearing it. */
+int cube2_status(cube2_ctx *ctx, cube2_stream_t stream);
+
+/* ---- adjoints ---------------------------------------------------------- */
+
+/* Adjoint of cube2_deposit for the FP32 density of `level`: given rho_bar
+ * (device, n^3), x_bar[d*n+i] (device, fine-cell units) = sum_nodes rho_bar
+ * * d(W)/dx_d with the CIC weights' derivative (left-continuous at faces).
+ * accumulate != 0 adds. */
+int cube2_deposit_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                           int64_t n, int level, const float *rho_bar, float *x_bar,
+                           int accumulate, void *work, size_t work_bytes, cube2_stream_t stream);
+
+/* Adjoint of cube2_pm_force: given acc_bar (device, 3*n), x_bar (device,
+ * 3*n) = (d acc / d x)^T acc_bar.  Per level: scatter of acc_bar, FD
+ * divergence (the transpose of eq. 7's stencil), the same FFT-G-IFFT (G is
+ * real and even, so the operator is symmetric), the deposit adjoint, plus
+ * the derivative of the interpolation weights.  accumulate != 0 adds. */
+int cube2_pm_force_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                            int64_t n, const float *acc_bar, float *x_bar, int accumulate,
+                            void *work, size_t work_bytes, cube2_stream_t stream);
+
+/* Adjoint of cube2_pp_force: x_bar_k = G m_p sum_j J(D_kj) (acc_bar_j -
+ * acc_bar_k), J(D) = g(r) I + g'(r) D D^T / r.  accumulate != 0 adds. */
+int cube2_pp_force_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                            int64_t n, const float *acc_bar, float *x_bar, int accumulate,
+                            void *work, size_t work_bytes, cube2_stream_t stream);
+
+/* Adjoint of cube2_kick_drift with the rounding taken as identity:
+ * given the output cotangents xbar_out, vbar_out (device, 3*n, output order)
+ * and perm (from the forward), writes in input order
+ * vbar_in = vbar_out + drift * xbar_out, xbar_in = xbar_out and
+ * acc_bar = kick * vbar_in (all device, 3*n). */
+int cube2_kick_drift_backward(cube2_ctx *ctx, int64_t n, const int32_t *perm,
+                              const float *xbar_out, const float *vbar_out, double kick,
+                              double drift, float *xbar_in, float *vbar_in, float *acc_bar,
+                              cube2_stream_t stream);
+
+/* Text of a status code. */
+const char *cube2_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUBE2_H */

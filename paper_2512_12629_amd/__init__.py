@@ -1,0 +1,395 @@
+"""MI355X (gfx950) implementation of the CUBE2 force computation.
+
+Two-level particle-mesh + particle-particle gravity of Yu et al.,
+arXiv 2512.12629 (section 2.1), with leapfrog kick-drift on integer in-cell
+positions (section 2.3) and hand-written adjoints, as a C-ABI HIP library
+(include/cube2.h, built into _build/libcube2.so).  This module is the thin
+Python binding: the ``cube2_*`` functions take torch tensors and pass their
+device pointers and the current HIP stream through; all arithmetic runs in
+the library's kernels.  There is no CPU fallback: importing raises if the
+library has not been built (``python -m paper_2512_12629_amd.build``).
+
+Tensor conventions (device tensors, SoA over particles):
+  x      float32 (3, N) box units in [0, 1)      (cube2_pack input)
+  pos    int16   (3, N) in-cell offsets (uint16 bits)
+  cs     int32   ((n_fine/2)^3 + 1,) cell_start (uint32 bits)
+  perm   int32   (N,)
+  vel, acc, x_bar, acc_bar  float32 (3, N), fine cells per time unit(s)
+  meshes float32 (n, n, n) [z][y][x]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libcube2.so")
+
+CUBE2_PP_OFF = 1
+_ERRORS = {0: "ok", -1: "invalid argument", -2: "unsupported configuration",
+           -3: "tables or work buffer too small", -4: "deposit overflow guard",
+           -5: "HIP runtime error", -6: "tables not initialised"}
+
+
+class Cube2Error(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {_ERRORS.get(code, code)} ({code})")
+        self.code = code
+
+
+class cube2_config(ctypes.Structure):
+    _fields_ = [("n_fine", ctypes.c_int32), ("coarse_ratio", ctypes.c_int32),
+                ("b_coarse", ctypes.c_double), ("b_fine", ctypes.c_double),
+                ("b_pp", ctypes.c_double), ("m_p", ctypes.c_double),
+                ("g_newton", ctypes.c_double), ("alias_nmax", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"libcube2.so not built ({LIB_PATH}); run `python -m paper_2512_12629_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, I64, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    sigs = {
+        "cube2_create": [ctypes.POINTER(cube2_config), ctypes.POINTER(P)],
+        "cube2_destroy": [P],
+        "cube2_sizes": [P, I64, ctypes.POINTER(S), ctypes.POINTER(S)],
+        "cube2_level_shape": [P, I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+        "cube2_init_tables": [P, P, S, P],
+        "cube2_green_table": [P, I, P, P],
+        "cube2_pack": [P, P, I64, P, P, P, P, S, P],
+        "cube2_deposit": [P, P, P, I64, I, P, P, P, S, P],
+        "cube2_fft_r2c": [P, I, P, P, P, S, P],
+        "cube2_potential": [P, I, P, P, P, S, P],
+        "cube2_interp": [P, P, P, I64, P, P, P, I, P],
+        "cube2_pm_force": [P, P, P, I64, P, I, P, S, P],
+        "cube2_pp_force": [P, P, P, I64, P, I, P, S, P],
+        "cube2_kick_drift": [P, P, P, P, P, I64, D, D, P, P, P, P, P, S, P],
+        "cube2_reduce": [P, P, P, I64, ctypes.POINTER(D), P, S, P],
+        "cube2_status": [P, P],
+        "cube2_deposit_backward": [P, P, P, I64, I, P, P, I, P, S, P],
+        "cube2_pm_force_backward": [P, P, P, I64, P, P, I, P, S, P],
+        "cube2_pp_force_backward": [P, P, P, I64, P, P, I, P, S, P],
+        "cube2_kick_drift_backward": [P, I64, P, P, P, D, D, P, P, P, P],
+        "cube2_strerror": [I],
+    }
+    for name, args in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = None if name == "cube2_destroy" else (
+            ctypes.c_char_p if name == "cube2_strerror" else ctypes.c_int)
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(code, what):
+    if code != 0:
+        raise Cube2Error(code, what)
+
+
+# ---------------------------------------------------------------------------
+# Same-name wrappers of the C ABI (argument marshalling only)
+# ---------------------------------------------------------------------------
+
+def cube2_create(cfg: cube2_config):
+    h = ctypes.c_void_p()
+    _check(_lib.cube2_create(ctypes.byref(cfg), ctypes.byref(h)), "cube2_create")
+    return h
+
+
+def cube2_destroy(ctx):
+    _lib.cube2_destroy(ctx)
+
+
+def cube2_sizes(ctx, n_max: int):
+    tb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_lib.cube2_sizes(ctx, int(n_max), ctypes.byref(tb), ctypes.byref(wb)), "cube2_sizes")
+    return tb.value, wb.value
+
+
+def cube2_level_shape(ctx, level: int):
+    n, p = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.cube2_level_shape(ctx, int(level), ctypes.byref(n), ctypes.byref(p)),
+           "cube2_level_shape")
+    return n.value, p.value
+
+
+def cube2_init_tables(ctx, tables, stream=None):
+    _check(_lib.cube2_init_tables(ctx, _ptr(tables), tables.numel() * tables.element_size(),
+                                  _stream(stream)), "cube2_init_tables")
+
+
+def cube2_green_table(ctx, level, out, stream=None):
+    _check(_lib.cube2_green_table(ctx, int(level), _ptr(out), _stream(stream)), "cube2_green_table")
+
+
+def cube2_pack(ctx, x, pos, cell_start, perm, work, stream=None):
+    _check(_lib.cube2_pack(ctx, _ptr(x), x.shape[1], _ptr(pos), _ptr(cell_start), _ptr(perm),
+                           _ptr(work), work.numel(), _stream(stream)), "cube2_pack")
+
+
+def cube2_deposit(ctx, pos, cell_start, level, rho, rho_fx, work, stream=None):
+    _check(_lib.cube2_deposit(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], int(level),
+                              _ptr(rho), _ptr(rho_fx), _ptr(work), work.numel(), _stream(stream)),
+           "cube2_deposit")
+
+
+def cube2_fft_r2c(ctx, level, mesh, spec, work, stream=None):
+    _check(_lib.cube2_fft_r2c(ctx, int(level), _ptr(mesh), _ptr(spec), _ptr(work), work.numel(),
+                              _stream(stream)), "cube2_fft_r2c")
+
+
+def cube2_potential(ctx, level, rho, phi, work, stream=None):
+    _check(_lib.cube2_potential(ctx, int(level), _ptr(rho), _ptr(phi), _ptr(work), work.numel(),
+                                _stream(stream)), "cube2_potential")
+
+
+def cube2_interp(ctx, pos, cell_start, phi_fine, phi_coarse, acc, accumulate=False, stream=None):
+    _check(_lib.cube2_interp(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], _ptr(phi_fine),
+                             _ptr(phi_coarse), _ptr(acc), int(bool(accumulate)), _stream(stream)),
+           "cube2_interp")
+
+
+def cube2_pm_force(ctx, pos, cell_start, acc, work, accumulate=False, stream=None):
+    _check(_lib.cube2_pm_force(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], _ptr(acc),
+                               int(bool(accumulate)), _ptr(work), work.numel(), _stream(stream)),
+           "cube2_pm_force")
+
+
+def cube2_pp_force(ctx, pos, cell_start, acc, work, accumulate=False, stream=None):
+    _check(_lib.cube2_pp_force(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], _ptr(acc),
+                               int(bool(accumulate)), _ptr(work), work.numel(), _stream(stream)),
+           "cube2_pp_force")
+
+
+def cube2_kick_drift(ctx, pos_in, cs_in, vel_in, acc, kick, drift, pos_out, cs_out, vel_out,
+                     perm_out, work, stream=None):
+    _check(_lib.cube2_kick_drift(ctx, _ptr(pos_in), _ptr(cs_in), _ptr(vel_in), _ptr(acc),
+                                 pos_in.shape[1], float(kick), float(drift), _ptr(pos_out),
+                                 _ptr(cs_out), _ptr(vel_out), _ptr(perm_out), _ptr(work),
+                                 work.numel(), _stream(stream)), "cube2_kick_drift")
+
+
+def cube2_reduce(ctx, vel, acc, work, stream=None):
+    out = (ctypes.c_double * 8)()
+    _check(_lib.cube2_reduce(ctx, _ptr(vel), _ptr(acc), acc.shape[1], out, _ptr(work),
+                             work.numel(), _stream(stream)), "cube2_reduce")
+    return list(out)
+
+
+def cube2_status(ctx, stream=None):
+    return _lib.cube2_status(ctx, _stream(stream))
+
+
+def cube2_deposit_backward(ctx, pos, cell_start, level, rho_bar, x_bar, work, accumulate=False,
+                           stream=None):
+    _check(_lib.cube2_deposit_backward(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], int(level),
+                                       _ptr(rho_bar), _ptr(x_bar), int(bool(accumulate)),
+                                       _ptr(work), work.numel(), _stream(stream)),
+           "cube2_deposit_backward")
+
+
+def cube2_pm_force_backward(ctx, pos, cell_start, acc_bar, x_bar, work, accumulate=False,
+                            stream=None):
+    _check(_lib.cube2_pm_force_backward(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1],
+                                        _ptr(acc_bar), _ptr(x_bar), int(bool(accumulate)),
+                                        _ptr(work), work.numel(), _stream(stream)),
+           "cube2_pm_force_backward")
+
+
+def cube2_pp_force_backward(ctx, pos, cell_start, acc_bar, x_bar, work, accumulate=False,
+                            stream=None):
+    _check(_lib.cube2_pp_force_backward(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1],
+                                        _ptr(acc_bar), _ptr(x_bar), int(bool(accumulate)),
+                                        _ptr(work), work.numel(), _stream(stream)),
+           "cube2_pp_force_backward")
+
+
+def cube2_kick_drift_backward(ctx, perm, xbar_out, vbar_out, kick, drift, xbar_in, vbar_in,
+                              acc_bar, stream=None):
+    _check(_lib.cube2_kick_drift_backward(ctx, perm.shape[0], _ptr(perm), _ptr(xbar_out),
+                                          _ptr(vbar_out), float(kick), float(drift),
+                                          _ptr(xbar_in), _ptr(vbar_in), _ptr(acc_bar),
+                                          _stream(stream)), "cube2_kick_drift_backward")
+
+
+def cube2_strerror(code: int) -> str:
+    return _lib.cube2_strerror(int(code)).decode()
+
+
+# ---------------------------------------------------------------------------
+# Convenience object: owns the context, the tables and a work buffer
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Config:
+    """Force parameters, lengths in fine cells (see include/cube2.h)."""
+    n_fine: int
+    coarse_ratio: int = 0
+    b_coarse: float = 14.0
+    b_fine: float = 2.0
+    b_pp: float = 0.2
+    m_p: float = 1.0
+    g_newton: float = 1.0
+    alias_nmax: int = 2
+    flags: int = 0
+
+    def c(self) -> cube2_config:
+        return cube2_config(self.n_fine, self.coarse_ratio, self.b_coarse, self.b_fine, self.b_pp,
+                            self.m_p, self.g_newton, self.alias_nmax, self.flags)
+
+
+class Cube2:
+    """Context + device tables + work buffer on one GPU."""
+
+    def __init__(self, cfg: Config, n_max: int, device="cuda"):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.ctx = cube2_create(cfg.c())
+        tb, wb = cube2_sizes(self.ctx, n_max)
+        self.n_max = n_max
+        self.tables = torch.empty(tb, dtype=torch.uint8, device=self.device)
+        self.work = torch.empty(wb, dtype=torch.uint8, device=self.device)
+        cube2_init_tables(self.ctx, self.tables)
+        self.n_cells = (cfg.n_fine // 2) ** 3
+        self.levels = 2 if cfg.coarse_ratio else 1
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None) is not None:
+                cube2_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    def level_shape(self, level):
+        return cube2_level_shape(self.ctx, level)
+
+    def _need(self, n):
+        if n > self.n_max:
+            raise ValueError(f"{n} particles > n_max {self.n_max}")
+
+    # -- forward -------------------------------------------------------------
+    def pack(self, x):
+        n = x.shape[1]
+        self._need(n)
+        pos = torch.empty((3, n), dtype=torch.int16, device=self.device)
+        cs = torch.empty(self.n_cells + 1, dtype=torch.int32, device=self.device)
+        perm = torch.empty(n, dtype=torch.int32, device=self.device)
+        cube2_pack(self.ctx, x.contiguous(), pos, cs, perm, self.work)
+        return pos, cs, perm
+
+    def deposit(self, pos, cs, level=0, fx=False):
+        n, _ = self.level_shape(level)
+        rho = torch.empty((n, n, n), dtype=torch.float32, device=self.device)
+        rfx = torch.empty((n, n, n), dtype=torch.int64, device=self.device) if fx else None
+        cube2_deposit(self.ctx, pos, cs, level, rho, rfx, self.work)
+        return (rho, rfx) if fx else rho
+
+    def fft_r2c(self, mesh, level=0):
+        n, pitch = self.level_shape(level)
+        spec = torch.empty((n, n, pitch, 2), dtype=torch.float32, device=self.device)
+        cube2_fft_r2c(self.ctx, level, mesh.contiguous(), spec, self.work)
+        return torch.view_as_complex(spec)[:, :, : n // 2 + 1]
+
+    def potential(self, rho, level=0):
+        phi = torch.empty_like(rho)
+        cube2_potential(self.ctx, level, rho.contiguous(), phi, self.work)
+        return phi
+
+    def green_table(self, level=0):
+        n, _ = self.level_shape(level)
+        h = n // 2 + 1
+        out = torch.empty((h, h, h), dtype=torch.float32, device=self.device)
+        cube2_green_table(self.ctx, level, out)
+        return out
+
+    def interp(self, pos, cs, phi_f, phi_c=None, acc=None):
+        acc_out = torch.empty((3, pos.shape[1]), dtype=torch.float32, device=self.device)
+        cube2_interp(self.ctx, pos, cs, phi_f, phi_c, acc_out)
+        return acc_out
+
+    def pm_force(self, pos, cs, acc=None):
+        accumulate = acc is not None
+        if acc is None:
+            acc = torch.empty((3, pos.shape[1]), dtype=torch.float32, device=self.device)
+        cube2_pm_force(self.ctx, pos, cs, acc, self.work, accumulate)
+        return acc
+
+    def pp_force(self, pos, cs, acc=None):
+        accumulate = acc is not None
+        if acc is None:
+            acc = torch.empty((3, pos.shape[1]), dtype=torch.float32, device=self.device)
+        cube2_pp_force(self.ctx, pos, cs, acc, self.work, accumulate)
+        return acc
+
+    def force(self, pos, cs):
+        acc = self.pm_force(pos, cs)
+        return self.pp_force(pos, cs, acc)
+
+    def kick_drift(self, pos, cs, vel, acc, kick, drift):
+        n = pos.shape[1]
+        pos2 = torch.empty_like(pos)
+        cs2 = torch.empty_like(cs)
+        vel2 = torch.empty_like(vel)
+        perm = torch.empty(n, dtype=torch.int32, device=self.device)
+        cube2_kick_drift(self.ctx, pos, cs, vel.contiguous(), acc.contiguous(), kick, drift, pos2,
+                         cs2, vel2, perm, self.work)
+        return pos2, cs2, vel2, perm
+
+    def reduce(self, vel, acc):
+        return cube2_reduce(self.ctx, vel, acc, self.work)
+
+    def status(self):
+        return cube2_status(self.ctx)
+
+    # -- adjoints -------------------------------------------------------------
+    def deposit_backward(self, pos, cs, rho_bar, level=0):
+        xb = torch.empty((3, pos.shape[1]), dtype=torch.float32, device=self.device)
+        cube2_deposit_backward(self.ctx, pos, cs, level, rho_bar.contiguous(), xb, self.work)
+        return xb
+
+    def pm_force_backward(self, pos, cs, acc_bar, x_bar=None):
+        accumulate = x_bar is not None
+        if x_bar is None:
+            x_bar = torch.empty((3, pos.shape[1]), dtype=torch.float32, device=self.device)
+        cube2_pm_force_backward(self.ctx, pos, cs, acc_bar.contiguous(), x_bar, self.work,
+                                accumulate)
+        return x_bar
+
+    def pp_force_backward(self, pos, cs, acc_bar, x_bar=None):
+        accumulate = x_bar is not None
+        if x_bar is None:
+            x_bar = torch.empty((3, pos.shape[1]), dtype=torch.float32, device=self.device)
+        cube2_pp_force_backward(self.ctx, pos, cs, acc_bar.contiguous(), x_bar, self.work,
+                                accumulate)
+        return x_bar
+
+    def kick_drift_backward(self, perm, xbar_out, vbar_out, kick, drift):
+        xb = torch.empty_like(xbar_out)
+        vb = torch.empty_like(vbar_out)
+        ab = torch.empty_like(vbar_out)
+        cube2_kick_drift_backward(self.ctx, perm, xbar_out.contiguous(), vbar_out.contiguous(),
+                                  kick, drift, xb, vb, ab)
+        return xb, vb, ab

@@ -1,0 +1,357 @@
+// api.hip -- the C ABI of include/cube2.h: argument checks, buffer layout
+// and the order of the launches.  All arithmetic is in the kernel files.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+
+using namespace cube2;
+
+namespace {
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int v) { int r = 0; while ((1 << r) < v) ++r; return r; }
+int pitch_of(int n) { return (int)align_up((size_t)(n / 2 + 1), 16); }
+
+size_t table_layout(cube2_ctx *c) {
+    size_t off = 256;  // status word block
+    for (int l = 0; l < c->n_levels; ++l) {
+        Level &L = c->lv[l];
+        L.tw_off = off;
+        off = align_up(off + (size_t)L.n * sizeof(float2), 256);
+    }
+    for (int l = 0; l < c->n_levels; ++l) {
+        Level &L = c->lv[l];
+        size_t h = (size_t)(L.n / 2 + 1);
+        L.g_off = off;
+        off = align_up(off + h * h * h * sizeof(float), 256);
+    }
+    return off;
+}
+
+}  // namespace
+
+namespace cube2 {
+
+WorkLayout work_layout(const cube2_ctx *c, int64_t n) {
+    WorkLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+    const size_t nf3 = (size_t)c->n_f * c->n_f * c->n_f;
+    const size_t nc = c->n_levels > 1 ? (size_t)c->lv[1].n : 0;
+    const size_t nc3 = nc * nc * nc;
+    L.real_f = take(nf3 * sizeof(float));
+    L.real_c = take(nc3 * sizeof(float));
+    L.bar_f = take(nf3 * sizeof(float));
+    L.bar_c = take(nc3 * sizeof(float));
+    L.spec = take((size_t)c->n_f * c->n_f * c->lv[0].pitch * sizeof(float2));
+    L.coarse_acc = take(nc3 * sizeof(uint64_t));
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    L.keys = take(nn * 4);
+    L.vals = take(nn * 4);
+    L.keys2 = take(nn * 4);
+    L.vals2 = take(nn * 4);
+    size_t nblk = (nn + 4095) / 4096;
+    L.hist = take(nblk * 256 * 4 + 1024);
+    L.counts = take((size_t)(c->n_cells + 1) * 4);
+    L.scan_tmp = take(((size_t)(c->n_cells + 1) / 1024 + 64) * 4 * 2 + 4096);
+    L.offs_tmp = take(nn * 3 * sizeof(uint16_t));
+    L.red = take(8192 * 8 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+}  // namespace cube2
+
+#define CHECK_WORK(n)                                                      \
+    WorkLayout L_ = work_layout(ctx, (n));                                 \
+    if (!work || work_bytes < L_.total) return CUBE2_EWORKSPACE;           \
+    unsigned char *work_ = static_cast<unsigned char *>(work)
+
+#define CHECK_READY()                                          \
+    if (!ctx) return CUBE2_EINVAL;                             \
+    if (!ctx->tables) return CUBE2_ESTATE
+
+extern "C" {
+
+int cube2_create(const cube2_config *cfg, cube2_ctx **out) {
+    if (!cfg || !out) return CUBE2_EINVAL;
+    *out = nullptr;
+    const cube2_config &c = *cfg;
+    if (!is_pow2(c.n_fine) || c.n_fine < 16 || c.n_fine > 1024) return CUBE2_EUNSUPPORTED;
+    if (c.coarse_ratio != 0) {
+        if (c.coarse_ratio != 2 && c.coarse_ratio != 4 && c.coarse_ratio != 8)
+            return CUBE2_EUNSUPPORTED;
+        if (c.n_fine / c.coarse_ratio < 8) return CUBE2_EUNSUPPORTED;
+        if (!(c.b_coarse > c.b_fine)) return CUBE2_EINVAL;
+    }
+    if (!(c.b_fine > 0.0) || c.b_fine > 2.0) return CUBE2_EUNSUPPORTED;
+    if (!(c.b_pp > 0.0) || !(c.b_pp < c.b_fine)) return CUBE2_EINVAL;
+    if (!(c.m_p > 0.0) || !std::isfinite(c.g_newton)) return CUBE2_EINVAL;
+    if (c.alias_nmax < 0 || c.alias_nmax > 4) return CUBE2_EUNSUPPORTED;
+
+    cube2_ctx *ctx = new (std::nothrow) cube2_ctx();
+    if (!ctx) return CUBE2_EINVAL;
+    ctx->cfg = c;
+    ctx->n_f = c.n_fine;
+    ctx->n_ios = c.n_fine / 2;
+    ctx->nt = ctx->n_ios / kTileIos;
+    ctx->n_cells = (int64_t)ctx->n_ios * ctx->n_ios * ctx->n_ios;
+    ctx->n_levels = c.coarse_ratio ? 2 : 1;
+    Level &F = ctx->lv[0];
+    F.n = c.n_fine;
+    F.H = 1;
+    F.hshift = 0;
+    F.pitch = pitch_of(F.n);
+    F.b_a = c.b_fine;
+    F.b_prev = c.coarse_ratio ? c.b_coarse : -1.0;
+    if (c.coarse_ratio) {
+        Level &C = ctx->lv[1];
+        C.n = c.n_fine / c.coarse_ratio;
+        C.H = c.coarse_ratio;
+        C.hshift = ilog2(c.coarse_ratio);
+        C.pitch = pitch_of(C.n);
+        C.b_a = c.b_coarse;
+        C.b_prev = -1.0;
+    }
+    ctx->table_bytes = table_layout(ctx);
+    *out = ctx;
+    return CUBE2_OK;
+}
+
+void cube2_destroy(cube2_ctx *ctx) { delete ctx; }
+
+int cube2_sizes(const cube2_ctx *ctx, int64_t n_max, size_t *table_bytes, size_t *work_bytes) {
+    if (!ctx || n_max < 0 || n_max > INT32_MAX) return CUBE2_EINVAL;
+    if (table_bytes) *table_bytes = ctx->table_bytes;
+    if (work_bytes) *work_bytes = work_layout(ctx, n_max).total;
+    return CUBE2_OK;
+}
+
+int cube2_level_shape(const cube2_ctx *ctx, int level, int32_t *n, int32_t *pitch) {
+    if (!ctx || level < 0 || level >= ctx->n_levels) return CUBE2_EINVAL;
+    if (n) *n = ctx->lv[level].n;
+    if (pitch) *pitch = ctx->lv[level].pitch;
+    return CUBE2_OK;
+}
+
+int cube2_init_tables(cube2_ctx *ctx, void *tables, size_t table_bytes, cube2_stream_t stream) {
+    if (!ctx || !tables) return CUBE2_EINVAL;
+    if (table_bytes < ctx->table_bytes) return CUBE2_EWORKSPACE;
+    ctx->tables = static_cast<unsigned char *>(tables);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    CUBE2_CHECK_HIP(hipMemsetAsync(ctx->tables, 0, 256, s));
+    return launch_green(ctx, s);
+}
+
+int cube2_green_table(const cube2_ctx *ctx, int level, float *out, cube2_stream_t stream) {
+    CHECK_READY();
+    if (level < 0 || level >= ctx->n_levels || !out) return CUBE2_EINVAL;
+    size_t h = (size_t)(ctx->lv[level].n / 2 + 1);
+    CUBE2_CHECK_HIP(hipMemcpyAsync(out, ctx->tables + ctx->lv[level].g_off, h * h * h * 4,
+                                   hipMemcpyDeviceToDevice,
+                                   reinterpret_cast<hipStream_t>(stream)));
+    return CUBE2_OK;
+}
+
+int cube2_pack(cube2_ctx *ctx, const float *x, int64_t n, uint16_t *pos, uint32_t *cell_start,
+               int32_t *perm, void *work, size_t work_bytes, cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start || (n > 0 && (!x || !pos || !perm)))
+        return CUBE2_EINVAL;
+    CHECK_WORK(n);
+    return launch_pack(ctx, x, n, pos, cell_start, perm, work_, L_,
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
+int cube2_deposit(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                  int level, float *rho, uint64_t *rho_fx, void *work, size_t work_bytes,
+                  cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start || !rho || (n > 0 && !pos)) return CUBE2_EINVAL;
+    if (level < 0 || level >= ctx->n_levels) return CUBE2_EINVAL;
+    CHECK_WORK(n);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (level == 0)
+        return launch_deposit(ctx, pos, cell_start, n, rho, rho_fx, nullptr, nullptr, work_, L_, s);
+    return launch_deposit(ctx, pos, cell_start, n, nullptr, nullptr, rho, rho_fx, work_, L_, s);
+}
+
+int cube2_fft_r2c(cube2_ctx *ctx, int level, const float *mesh, float *spec, void *work,
+                  size_t work_bytes, cube2_stream_t stream) {
+    CHECK_READY();
+    if (level < 0 || level >= ctx->n_levels || !mesh || !spec) return CUBE2_EINVAL;
+    (void)work;
+    (void)work_bytes;
+    return launch_fft_r2c(ctx, level, mesh, reinterpret_cast<float2 *>(spec),
+                          reinterpret_cast<hipStream_t>(stream));
+}
+
+int cube2_potential(cube2_ctx *ctx, int level, const float *rho, float *phi, void *work,
+                    size_t work_bytes, cube2_stream_t stream) {
+    CHECK_READY();
+    if (level < 0 || level >= ctx->n_levels || !rho || !phi) return CUBE2_EINVAL;
+    CHECK_WORK(0);
+    return launch_potential(ctx, level, rho, phi, reinterpret_cast<float2 *>(work_ + L_.spec),
+                            reinterpret_cast<hipStream_t>(stream));
+}
+
+int cube2_interp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                 const float *phi_fine, const float *phi_coarse, float *acc, int accumulate,
+                 cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start || !phi_fine) return CUBE2_EINVAL;
+    if (n > 0 && (!pos || !acc)) return CUBE2_EINVAL;
+    if (ctx->n_levels > 1 && !phi_coarse) return CUBE2_EINVAL;
+    return launch_interp(ctx, pos, cell_start, n, phi_fine, phi_coarse, acc, accumulate,
+                         reinterpret_cast<hipStream_t>(stream));
+}
+
+int cube2_pm_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                   float *acc, int accumulate, void *work, size_t work_bytes,
+                   cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start || (n > 0 && (!pos || !acc))) return CUBE2_EINVAL;
+    CHECK_WORK(n);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    float *rf = reinterpret_cast<float *>(work_ + L_.real_f);
+    float *rc = ctx->n_levels > 1 ? reinterpret_cast<float *>(work_ + L_.real_c) : nullptr;
+    float2 *spec = reinterpret_cast<float2 *>(work_ + L_.spec);
+    int rcode = launch_deposit(ctx, pos, cell_start, n, rf, nullptr, rc, nullptr, work_, L_, s);
+    if (rcode) return rcode;
+    for (int l = 0; l < ctx->n_levels; ++l) {
+        float *m = l == 0 ? rf : rc;
+        rcode = launch_potential(ctx, l, m, m, spec, s);
+        if (rcode) return rcode;
+    }
+    if (n == 0) return CUBE2_OK;
+    return launch_interp(ctx, pos, cell_start, n, rf, rc, acc, accumulate, s);
+}
+
+int cube2_pp_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                   float *acc, int accumulate, void *work, size_t work_bytes,
+                   cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start || (n > 0 && (!pos || !acc))) return CUBE2_EINVAL;
+    CHECK_WORK(n);
+    (void)work_;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (n == 0) return CUBE2_OK;
+    if (ctx->cfg.flags & CUBE2_PP_OFF) {
+        if (!accumulate) CUBE2_CHECK_HIP(hipMemsetAsync(acc, 0, (size_t)n * 3 * 4, s));
+        return CUBE2_OK;
+    }
+    return launch_pp(ctx, pos, cell_start, n, acc, accumulate, s);
+}
+
+int cube2_kick_drift(cube2_ctx *ctx, const uint16_t *pos_in, const uint32_t *cell_start_in,
+                     const float *vel_in, const float *acc, int64_t n, double kick, double drift,
+                     uint16_t *pos_out, uint32_t *cell_start_out, float *vel_out,
+                     int32_t *perm_out, void *work, size_t work_bytes, cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start_in || !cell_start_out) return CUBE2_EINVAL;
+    if (n > 0 && (!pos_in || !vel_in || !acc || !pos_out || !vel_out || !perm_out))
+        return CUBE2_EINVAL;
+    if (!std::isfinite(kick) || !std::isfinite(drift)) return CUBE2_EINVAL;
+    if (n > 0 && ((const void *)pos_in == (const void *)pos_out ||
+                  (const void *)vel_in == (const void *)vel_out))
+        return CUBE2_EINVAL;
+    if ((const void *)cell_start_in == (const void *)cell_start_out) return CUBE2_EINVAL;
+    CHECK_WORK(n);
+    return launch_kick_drift(ctx, pos_in, cell_start_in, vel_in, acc, n, kick, drift, pos_out,
+                             cell_start_out, vel_out, perm_out, work_, L_,
+                             reinterpret_cast<hipStream_t>(stream));
+}
+
+int cube2_reduce(cube2_ctx *ctx, const float *vel, const float *acc, int64_t n, double *out8,
+                 void *work, size_t work_bytes, cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !out8 || (n > 0 && !acc)) return CUBE2_EINVAL;
+    CHECK_WORK(n);
+    return launch_reduce(ctx, vel, acc, n, out8, work_, L_,
+                         reinterpret_cast<hipStream_t>(stream));
+}
+
+int cube2_status(cube2_ctx *ctx, cube2_stream_t stream) {
+    CHECK_READY();
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint32_t word = 0;
+    CUBE2_CHECK_HIP(hipMemcpyAsync(&word, status_word(ctx), 4, hipMemcpyDeviceToHost, s));
+    CUBE2_CHECK_HIP(hipStreamSynchronize(s));
+    CUBE2_CHECK_HIP(hipMemsetAsync(status_word(ctx), 0, 4, s));
+    CUBE2_CHECK_HIP(hipStreamSynchronize(s));
+    return word ? CUBE2_EOVERFLOW : CUBE2_OK;
+}
+
+int cube2_deposit_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                           int64_t n, int level, const float *rho_bar, float *x_bar,
+                           int accumulate, void *work, size_t work_bytes, cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start || !rho_bar || (n > 0 && (!pos || !x_bar)))
+        return CUBE2_EINVAL;
+    if (level < 0 || level >= ctx->n_levels) return CUBE2_EINVAL;
+    (void)work;
+    (void)work_bytes;
+    if (n == 0) return CUBE2_OK;
+    return launch_deposit_backward(ctx, pos, cell_start, n, level, rho_bar, x_bar, accumulate,
+                                   reinterpret_cast<hipStream_t>(stream));
+}
+
+int cube2_pm_force_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                            int64_t n, const float *acc_bar, float *x_bar, int accumulate,
+                            void *work, size_t work_bytes, cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start || (n > 0 && (!pos || !acc_bar || !x_bar)))
+        return CUBE2_EINVAL;
+    CHECK_WORK(n);
+    if (n == 0) return CUBE2_OK;
+    return launch_pm_backward(ctx, pos, cell_start, n, acc_bar, x_bar, accumulate, work_, L_,
+                              reinterpret_cast<hipStream_t>(stream));
+}
+
+int cube2_pp_force_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                            int64_t n, const float *acc_bar, float *x_bar, int accumulate,
+                            void *work, size_t work_bytes, cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start || (n > 0 && (!pos || !acc_bar || !x_bar)))
+        return CUBE2_EINVAL;
+    (void)work;
+    (void)work_bytes;
+    if (n == 0) return CUBE2_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (ctx->cfg.flags & CUBE2_PP_OFF) {
+        if (!accumulate) CUBE2_CHECK_HIP(hipMemsetAsync(x_bar, 0, (size_t)n * 3 * 4, s));
+        return CUBE2_OK;
+    }
+    return launch_pp_backward(ctx, pos, cell_start, n, acc_bar, x_bar, accumulate, s);
+}
+
+int cube2_kick_drift_backward(cube2_ctx *ctx, int64_t n, const int32_t *perm,
+                              const float *xbar_out, const float *vbar_out, double kick,
+                              double drift, float *xbar_in, float *vbar_in, float *acc_bar,
+                              cube2_stream_t stream) {
+    if (!ctx) return CUBE2_EINVAL;
+    if (n < 0 || n > INT32_MAX) return CUBE2_EINVAL;
+    if (n > 0 && (!perm || !xbar_out || !vbar_out || !xbar_in || !vbar_in || !acc_bar))
+        return CUBE2_EINVAL;
+    if (!std::isfinite(kick) || !std::isfinite(drift)) return CUBE2_EINVAL;
+    if (n == 0) return CUBE2_OK;
+    return launch_kick_drift_backward(ctx, n, perm, xbar_out, vbar_out, kick, drift, xbar_in,
+                                      vbar_in, acc_bar, reinterpret_cast<hipStream_t>(stream));
+}
+
+const char *cube2_strerror(int code) {
+    switch (code) {
+        case CUBE2_OK: return "ok";
+        case CUBE2_EINVAL: return "invalid argument";
+        case CUBE2_EUNSUPPORTED: return "unsupported configuration";
+        case CUBE2_EWORKSPACE: return "tables or work buffer too small";
+        case CUBE2_EOVERFLOW: return "deposit accumulator overflow guard tripped";
+        case CUBE2_EHIP: return "HIP runtime error";
+        case CUBE2_ESTATE: return "tables not initialised";
+        default: return "unknown status code";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,600 @@
+// backward.hip -- adjoints (vector-Jacobian products) of the deposit, the PM
+// force and the PP force.  The paper has no adjoint; these follow from the
+// forward definitions:
+//
+// PM, one level of spacing H, c = G m / H^2, unit-mass density rho:
+//   a_i = c sum_n W(y_i - n) E(n),  E = -D phi,  phi = K rho,  rho = sum_j W
+//   Abar_d(n)  = c sum_i W(y_i - n) abar_{i,d}
+//   phibar     = +D . Abar   (the 4-point stencil is antisymmetric: D^T = -D)
+//   rhobar     = K phibar    (G real and even: K symmetric; same FFT pipeline)
+//   xbar_i    += sum_n grad W(y_i - n) [c abar_i . E(n) + rhobar(n)]
+// grad W of the CIC weights is piecewise constant: (1/H) (+-1) times the two
+// other weights (left-continuous at cell faces).
+//
+// PP: a_k = G m sum_j g(r) D_kj with D_kj = x_j - x_k gives
+//   xbar_k = G m sum_j J(D_kj) (abar_j - abar_k),  J = g I + g' D D^T / r.
+#include "common.hpp"
+
+namespace cube2 {
+namespace {
+
+// ---------------------------------------------------------------------------
+// fine level: phibar on a 16^3 node tile from the particles of an 11^3 box of
+// IOS cells (a particle in fine cell j reaches nodes j-2 .. j+3 along the
+// stencil axis and j, j+1 across it)
+// ---------------------------------------------------------------------------
+
+constexpr int kAB = kTileIos + 3;            // 11 IOS cells per axis: [c0-2, c0+9)
+constexpr int kASegs = kAB * kAB * kAB;      // 1331
+constexpr int kASegPerThread = (kASegs + kBlock - 1) / kBlock;  // 6
+
+// coefficients of the 1D "CIC then stencil transpose" kernel at offsets
+// -2..3 from the lower CIC node j, for node values A0 (at j) and A1 (at j+1)
+__device__ __forceinline__ void stencil_t(float A0, float A1, float (&o)[6]) {
+    o[0] = -A0 * (1.0f / 12.0f);
+    o[1] = (2.0f / 3.0f) * A0 - A1 * (1.0f / 12.0f);
+    o[2] = (2.0f / 3.0f) * A1;
+    o[3] = -(2.0f / 3.0f) * A0;
+    o[4] = A0 * (1.0f / 12.0f) - (2.0f / 3.0f) * A1;
+    o[5] = A1 * (1.0f / 12.0f);
+}
+
+__global__ __launch_bounds__(kBlock) void fine_phibar_kernel(
+    const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs,
+    const float *__restrict__ abar, int n, int n_f, int nt, float c, float *__restrict__ phibar) {
+    __shared__ uint32_t seg_pre[kASegs + 1];
+    __shared__ uint32_t seg_src[kASegs];
+    __shared__ float acc[kTileFine * kTileFine * kTileFine];
+    __shared__ uint32_t scan_sh[kBlock / 64 + 1];
+    int tx, ty, tz;
+    tile_of_block(blockIdx.x, nt, tx, ty, tz);
+    const int tid = threadIdx.x;
+    const int n_ios = nt * kTileIos;
+    const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
+    for (int i = tid; i < kTileFine * kTileFine * kTileFine; i += kBlock) acc[i] = 0.0f;
+    uint32_t cnt[kASegPerThread], src[kASegPerThread], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kASegPerThread; ++k) {
+        const int s = tid * kASegPerThread + k;
+        cnt[k] = 0;
+        src[k] = 0;
+        if (s < kASegs) {
+            const int bx = s % kAB, by = (s / kAB) % kAB, bz = s / (kAB * kAB);
+            const uint32_t key = cell_key(wrapn(c0x + bx - 2, n_ios), wrapn(c0y + by - 2, n_ios),
+                                          wrapn(c0z + bz - 2, n_ios), nt);
+            src[k] = cs[key];
+            cnt[k] = cs[key + 1] - src[k];
+        }
+        sum += cnt[k];
+    }
+    uint32_t total;
+    uint32_t pre = block_exclusive_scan(sum, scan_sh, total);
+#pragma unroll
+    for (int k = 0; k < kASegPerThread; ++k) {
+        const int s = tid * kASegPerThread + k;
+        if (s < kASegs) {
+            seg_pre[s] = pre;
+            seg_src[s] = src[k];
+        }
+        pre += cnt[k];
+    }
+    if (tid == 0) seg_pre[kASegs] = total;
+    __syncthreads();
+    const float inv = 1.0f / 32768.0f;
+    constexpr int T = kTileFine;
+    for (uint32_t v = tid; v < total; v += kBlock) {
+        const int s = seg_search(seg_pre, kASegs, v);
+        const uint32_t p = seg_src[s] + (v - seg_pre[s]);
+        const int b[3] = {s % kAB, (s / kAB) % kAB, s / (kAB * kAB)};
+        int j[3];
+        float w[3][2], ab[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const uint32_t o = pos[(int64_t)d * n + p];
+            j[d] = 2 * (b[d] - 2) + (int)(o >> 15);
+            const int f = (int)(o & 0x7FFFu);
+            w[d][1] = (float)f * inv;
+            w[d][0] = (float)(32768 - f) * inv;
+            ab[d] = c * abar[(int64_t)d * n + p];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int e = d == 0 ? 1 : 0, f = d == 2 ? 1 : 2;  // the two other axes
+            float o[6];
+            stencil_t(w[d][0] * ab[d], w[d][1] * ab[d], o);
+#pragma unroll
+            for (int se = 0; se < 2; ++se)
+#pragma unroll
+                for (int sf = 0; sf < 2; ++sf) {
+                    const int ne = j[e] + se, nf = j[f] + sf;
+                    if ((unsigned)ne >= (unsigned)T || (unsigned)nf >= (unsigned)T) continue;
+                    const float wef = w[e][se] * w[f][sf];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) {
+                        const int nd = j[d] - 2 + k;
+                        if ((unsigned)nd >= (unsigned)T) continue;
+                        int nn[3];
+                        nn[d] = nd;
+                        nn[e] = ne;
+                        nn[f] = nf;
+                        atomicAdd(&acc[(nn[2] * T + nn[1]) * T + nn[0]], wef * o[k]);
+                    }
+                }
+        }
+    }
+    __syncthreads();
+    const int a0x = tx * T, a0y = ty * T, a0z = tz * T;
+    for (int i = tid; i < T * T * T; i += kBlock) {
+        const int lx = i % T, ly = (i / T) % T, lz = i / (T * T);
+        phibar[((int64_t)(a0z + lz) * n_f + (a0y + ly)) * n_f + (a0x + lx)] = acc[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coarse level: CIC scatter of c*abar (3 components) per tile in LDS, added
+// to a 3-component coarse mesh, then the stencil transpose on that mesh
+// ---------------------------------------------------------------------------
+
+constexpr int kCN = kTileFine / 2 + 1;  // 9 coarse nodes per axis (ratio 2)
+
+__global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
+    const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs,
+    const float *__restrict__ abar, int n, int nt, int n_c, int hshift, float c,
+    float *__restrict__ Amesh) {
+    __shared__ float A[3][kCN * kCN * kCN];
+    __shared__ uint32_t cst[kTileCells + 1];
+    int tx, ty, tz;
+    tile_of_block(blockIdx.x, nt, tx, ty, tz);
+    const int tid = threadIdx.x;
+    const int NC = (kTileFine >> hshift) + 1;
+    for (int i = tid; i < 3 * kCN * kCN * kCN; i += kBlock) (&A[0][0])[i] = 0.0f;
+    const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
+    for (int i = tid; i <= kTileCells; i += kBlock) cst[i] = cs[key0 + i];
+    __syncthreads();
+    const float inv = 1.0f / 32768.0f;
+    for (uint32_t p = cst[0] + tid; p < cst[kTileCells]; p += kBlock) {
+        const int u = seg_search(cst, kTileCells, p);
+        const int uc[3] = {u & 7, (u >> 3) & 7, u >> 6};
+        int j[3];
+        float w[3][2], ab[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const uint32_t q = ((uint32_t)uc[d] << 16) + pos[(int64_t)d * n + p];
+            j[d] = (int)(q >> (kFracBits + hshift));
+            const int f = (int)((q >> hshift) & 0x7FFFu);
+            w[d][1] = (float)f * inv;
+            w[d][0] = (float)(32768 - f) * inv;
+            ab[d] = c * abar[(int64_t)d * n + p];
+        }
+#pragma unroll
+        for (int sz = 0; sz < 2; ++sz)
+#pragma unroll
+            for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+                for (int sx = 0; sx < 2; ++sx) {
+                    const float W = w[0][sx] * w[1][sy] * w[2][sz];
+                    const int idx = ((j[2] + sz) * NC + j[1] + sy) * NC + j[0] + sx;
+                    atomicAdd(&A[0][idx], W * ab[0]);
+                    atomicAdd(&A[1][idx], W * ab[1]);
+                    atomicAdd(&A[2][idx], W * ab[2]);
+                }
+    }
+    __syncthreads();
+    const int A0x = (tx * kTileFine) >> hshift, A0y = (ty * kTileFine) >> hshift,
+              A0z = (tz * kTileFine) >> hshift;
+    const int64_t m = (int64_t)n_c * n_c * n_c;
+    for (int i = tid; i < NC * NC * NC; i += kBlock) {
+        const int lx = i % NC, ly = (i / NC) % NC, lz = i / (NC * NC);
+        const int64_t g = ((int64_t)wrapn(A0z + lz, n_c) * n_c + wrapn(A0y + ly, n_c)) * n_c +
+                          wrapn(A0x + lx, n_c);
+        for (int d = 0; d < 3; ++d) {
+            const float v = A[d][i];
+            if (v != 0.0f) atomicAdd(&Amesh[d * m + g], v);
+        }
+    }
+}
+
+__global__ void fill_f32(float *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+// phibar(m) = sum_d (2/3)(A_d(m+e_d) - A_d(m-e_d)) - (1/12)(A_d(m+2e_d) - A_d(m-2e_d))
+__global__ void divergence_kernel(const float *__restrict__ A, int n, float *__restrict__ out) {
+    const int64_t m3 = (int64_t)n * n * n;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m3) return;
+    const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((int64_t)n * n));
+    auto at = [&](int d, int xx, int yy, int zz) {
+        return A[d * m3 + ((int64_t)wrapn(zz, n) * n + wrapn(yy, n)) * n + wrapn(xx, n)];
+    };
+    float s = (2.0f / 3.0f) * (at(0, x + 1, y, z) - at(0, x - 1, y, z)) -
+              (1.0f / 12.0f) * (at(0, x + 2, y, z) - at(0, x - 2, y, z));
+    s += (2.0f / 3.0f) * (at(1, x, y + 1, z) - at(1, x, y - 1, z)) -
+         (1.0f / 12.0f) * (at(1, x, y + 2, z) - at(1, x, y - 2, z));
+    s += (2.0f / 3.0f) * (at(2, x, y, z + 1) - at(2, x, y, z - 1)) -
+         (1.0f / 12.0f) * (at(2, x, y, z + 2) - at(2, x, y, z - 2));
+    out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// xbar gather: sum over the 8 CIC nodes of grad W times
+//   T = c (abar . E) + rhobar   (PM adjoint)   or   T = rhobar (deposit adjoint)
+// ---------------------------------------------------------------------------
+
+constexpr int kFS = kTileFine + 5;   // potential tile with stencil halo
+constexpr int kRS = kTileFine + 1;   // rhobar tile: nodes a .. a+16
+constexpr int kCSMax = kTileFine / 2 + 5;
+constexpr int kCRMax = kTileFine / 2 + 1;
+
+__device__ __forceinline__ float fd_at(const float *P, int idx, int st) {
+    return -((2.0f / 3.0f) * (P[idx + st] - P[idx - st]) -
+             (1.0f / 12.0f) * (P[idx + 2 * st] - P[idx - 2 * st]));
+}
+
+// adds (1/H) sum_s grad W_s T_s to xb
+template <bool WITH_E>
+__device__ __forceinline__ void level_gather(const float *P, int S, const float *Rb, int SR,
+                                             const int (&j)[3], const float (&w)[3][2],
+                                             const float (&ab)[3], float c, float invH,
+                                             float (&xb)[3]) {
+    float g[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int sz = 0; sz < 2; ++sz)
+#pragma unroll
+        for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+            for (int sx = 0; sx < 2; ++sx) {
+                float T = Rb[((j[2] + sz) * SR + j[1] + sy) * SR + j[0] + sx];
+                if (WITH_E) {
+                    const int idx = ((j[2] + sz + 2) * S + j[1] + sy + 2) * S + j[0] + sx + 2;
+                    const float ex = fd_at(P, idx, 1), ey = fd_at(P, idx, S), ez = fd_at(P, idx, S * S);
+                    T += c * (ab[0] * ex + ab[1] * ey + ab[2] * ez);
+                }
+                g[0] += (sx ? 1.0f : -1.0f) * w[1][sy] * w[2][sz] * T;
+                g[1] += (sy ? 1.0f : -1.0f) * w[0][sx] * w[2][sz] * T;
+                g[2] += (sz ? 1.0f : -1.0f) * w[0][sx] * w[1][sy] * T;
+            }
+    xb[0] += g[0] * invH;
+    xb[1] += g[1] * invH;
+    xb[2] += g[2] * invH;
+}
+
+template <bool WITH_E, bool TWO>
+__global__ __launch_bounds__(kBlock) void xbar_gather_kernel(
+    const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs,
+    const float *__restrict__ abar, int n, int n_f, int nt, const float *__restrict__ phi_f,
+    const float *__restrict__ rb_f, float c_f, const float *__restrict__ phi_c,
+    const float *__restrict__ rb_c, float c_c, int n_c, int hshift, float *__restrict__ xbar,
+    int accumulate) {
+    __shared__ float pf[WITH_E ? kFS * kFS * kFS : 1];
+    __shared__ float rf[kRS * kRS * kRS];
+    __shared__ float pc[(WITH_E && TWO) ? kCSMax * kCSMax * kCSMax : 1];
+    __shared__ float rc[TWO ? kCRMax * kCRMax * kCRMax : 1];
+    __shared__ uint32_t cst[kTileCells + 1];
+    int tx, ty, tz;
+    tile_of_block(blockIdx.x, nt, tx, ty, tz);
+    const int tid = threadIdx.x;
+    const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
+    for (int i = tid; i <= kTileCells; i += kBlock) cst[i] = cs[key0 + i];
+    const int a0x = tx * kTileFine, a0y = ty * kTileFine, a0z = tz * kTileFine;
+    if (WITH_E)
+        for (int i = tid; i < kFS * kFS * kFS; i += kBlock) {
+            const int lx = i % kFS, ly = (i / kFS) % kFS, lz = i / (kFS * kFS);
+            pf[i] = phi_f[((int64_t)wrapn(a0z + lz - 2, n_f) * n_f + wrapn(a0y + ly - 2, n_f)) * n_f +
+                          wrapn(a0x + lx - 2, n_f)];
+        }
+    for (int i = tid; i < kRS * kRS * kRS; i += kBlock) {
+        const int lx = i % kRS, ly = (i / kRS) % kRS, lz = i / (kRS * kRS);
+        rf[i] = rb_f ? rb_f[((int64_t)wrapn(a0z + lz, n_f) * n_f + wrapn(a0y + ly, n_f)) * n_f +
+                            wrapn(a0x + lx, n_f)]
+                     : 0.0f;
+    }
+    const int CS = (kTileFine >> hshift) + 5, CR = (kTileFine >> hshift) + 1;
+    if (TWO) {
+        const int cx0 = a0x >> hshift, cy0 = a0y >> hshift, cz0 = a0z >> hshift;
+        if (WITH_E)
+            for (int i = tid; i < CS * CS * CS; i += kBlock) {
+                const int lx = i % CS, ly = (i / CS) % CS, lz = i / (CS * CS);
+                pc[i] = phi_c[((int64_t)wrapn(cz0 + lz - 2, n_c) * n_c + wrapn(cy0 + ly - 2, n_c)) * n_c +
+                              wrapn(cx0 + lx - 2, n_c)];
+            }
+        for (int i = tid; i < CR * CR * CR; i += kBlock) {
+            const int lx = i % CR, ly = (i / CR) % CR, lz = i / (CR * CR);
+            rc[i] = rb_c[((int64_t)wrapn(cz0 + lz, n_c) * n_c + wrapn(cy0 + ly, n_c)) * n_c +
+                         wrapn(cx0 + lx, n_c)];
+        }
+    }
+    __syncthreads();
+    const float inv = 1.0f / 32768.0f;
+    for (uint32_t p = cst[0] + tid; p < cst[kTileCells]; p += kBlock) {
+        const int u = seg_search(cst, kTileCells, p);
+        const int uc[3] = {u & 7, (u >> 3) & 7, u >> 6};
+        int jf[3], jc[3];
+        float wf[3][2], wc[3][2], ab[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const uint32_t o = pos[(int64_t)d * n + p];
+            const int f = (int)(o & 0x7FFFu);
+            jf[d] = 2 * uc[d] + (int)(o >> 15);
+            wf[d][1] = (float)f * inv;
+            wf[d][0] = (float)(32768 - f) * inv;
+            ab[d] = WITH_E ? abar[(int64_t)d * n + p] : 0.0f;
+            if (TWO) {
+                const uint32_t q = ((uint32_t)uc[d] << 16) + o;
+                const int fc = (int)((q >> hshift) & 0x7FFFu);
+                jc[d] = (int)(q >> (kFracBits + hshift));
+                wc[d][1] = (float)fc * inv;
+                wc[d][0] = (float)(32768 - fc) * inv;
+            }
+        }
+        float xb[3] = {0.f, 0.f, 0.f};
+        level_gather<WITH_E>(pf, kFS, rf, kRS, jf, wf, ab, c_f, 1.0f, xb);
+        if (TWO)
+            level_gather<WITH_E>(pc, CS, rc, CR, jc, wc, ab, c_c, 1.0f / (float)(1 << hshift), xb);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            float *dst = xbar + (int64_t)d * n + p;
+            *dst = accumulate ? *dst + xb[d] : xb[d];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// PP adjoint
+// ---------------------------------------------------------------------------
+
+constexpr int kPB = kTileIos + 2;
+constexpr int kPSegs = kPB * kPB * kPB;
+constexpr int kPSegPerThread = (kPSegs + kBlock - 1) / kBlock;
+constexpr int kCap = 2048;
+
+struct PairLaw {
+    float bpp, ibpp, ibpp3, ibpp4;
+    float bf, ibf, ibf3, ibf4, bf2;
+};
+
+// F(t) and F'(t) with R(r,b)/r = b^-3 F(r/b) (see pp.hip)
+__device__ __forceinline__ void f_and_df(float t, float tinv, int branch, float &F, float &dF) {
+    if (branch == 0) {
+        const float t2 = t * t;
+        F = 64.0f / 5.0f + t2 * (-256.0f / 5.0f + t * (32.0f + t * (1536.0f / 35.0f + t * (-192.0f / 5.0f))));
+        dF = t * (-512.0f / 5.0f + t * (96.0f + t * (6144.0f / 35.0f + t * (-192.0f))));
+    } else if (branch == 1) {
+        const float ti2 = tinv * tinv;
+        F = 256.0f / 5.0f + t * (-96.0f + t * (256.0f / 5.0f + t * (32.0f + t * (-1536.0f / 35.0f + t * (64.0f / 5.0f))))) +
+            tinv * (-32.0f / 5.0f + ti2 * (3.0f / 35.0f));
+        dF = -96.0f + t * (512.0f / 5.0f + t * (96.0f + t * (-6144.0f / 35.0f + t * 64.0f))) +
+             ti2 * (32.0f / 5.0f + ti2 * (-9.0f / 35.0f));
+    } else {
+        const float ti2 = tinv * tinv;
+        F = ti2 * tinv;
+        dF = -3.0f * ti2 * ti2;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void pp_adjoint_kernel(
+    const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs,
+    const float *__restrict__ abar, int n, int nt, PairLaw law, float gm,
+    float *__restrict__ xbar, int accumulate) {
+    __shared__ uint32_t seg_pre[kPSegs + 1];
+    __shared__ uint32_t seg_src[kPSegs];
+    __shared__ float4 xs[kCap];
+    __shared__ float4 as[kCap];
+    __shared__ uint32_t scan_sh[kBlock / 64 + 1];
+    int tx, ty, tz;
+    tile_of_block(blockIdx.x, nt, tx, ty, tz);
+    const int tid = threadIdx.x;
+    const int n_ios = nt * kTileIos;
+    const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
+    uint32_t cnt[kPSegPerThread], src[kPSegPerThread], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPSegPerThread; ++k) {
+        const int s = tid * kPSegPerThread + k;
+        cnt[k] = 0;
+        src[k] = 0;
+        if (s < kPSegs) {
+            const int bx = s % kPB, by = (s / kPB) % kPB, bz = s / (kPB * kPB);
+            const uint32_t key = cell_key(wrapn(c0x + bx - 1, n_ios), wrapn(c0y + by - 1, n_ios),
+                                          wrapn(c0z + bz - 1, n_ios), nt);
+            src[k] = cs[key];
+            cnt[k] = cs[key + 1] - src[k];
+        }
+        sum += cnt[k];
+    }
+    uint32_t total;
+    uint32_t pre = block_exclusive_scan(sum, scan_sh, total);
+#pragma unroll
+    for (int k = 0; k < kPSegPerThread; ++k) {
+        const int s = tid * kPSegPerThread + k;
+        if (s < kPSegs) {
+            seg_pre[s] = pre;
+            seg_src[s] = src[k];
+        }
+        pre += cnt[k];
+    }
+    if (tid == 0) seg_pre[kPSegs] = total;
+    __syncthreads();
+    const bool staged = total <= (uint32_t)kCap;
+    const float inv = 1.0f / 32768.0f;
+    if (staged)
+        for (uint32_t v = tid; v < total; v += kBlock) {
+            const int s = seg_search(seg_pre, kPSegs, v);
+            const uint32_t p = seg_src[s] + (v - seg_pre[s]);
+            const int bx = s % kPB, by = (s / kPB) % kPB, bz = s / (kPB * kPB);
+            xs[v] = make_float4((float)(2 * (bx - 1)) + (float)pos[p] * inv,
+                                (float)(2 * (by - 1)) + (float)pos[(int64_t)n + p] * inv,
+                                (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv, 0.f);
+            as[v] = make_float4(abar[p], abar[(int64_t)n + p], abar[2 * (int64_t)n + p], 0.f);
+        }
+    __syncthreads();
+    const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
+    const uint32_t p0 = cs[key0], p1 = cs[key0 + kTileCells];
+    for (uint32_t p = p0 + tid; p < p1; p += kBlock) {
+        int lo = 0, hi = kTileCells;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cs[key0 + mid] <= p) lo = mid; else hi = mid;
+        }
+        const int bx = (lo & 7) + 1, by = ((lo >> 3) & 7) + 1, bz = (lo >> 6) + 1;
+        const float xi = (float)(2 * (bx - 1)) + (float)pos[p] * inv;
+        const float yi = (float)(2 * (by - 1)) + (float)pos[(int64_t)n + p] * inv;
+        const float zi = (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv;
+        const float akx = abar[p], aky = abar[(int64_t)n + p], akz = abar[2 * (int64_t)n + p];
+        float sx = 0.f, sy = 0.f, sz = 0.f;
+        for (int nb = 0; nb < 27; ++nb) {
+            const int ox = nb % 3 - 1, oy = (nb / 3) % 3 - 1, oz = nb / 9 - 1;
+            const int s = ((bz + oz) * kPB + (by + oy)) * kPB + (bx + ox);
+            const uint32_t v0 = seg_pre[s], v1 = seg_pre[s + 1];
+            for (uint32_t v = v0; v < v1; ++v) {
+                float xj, yj, zj, ajx, ajy, ajz;
+                if (staged) {
+                    const float4 q = xs[v], a = as[v];
+                    xj = q.x; yj = q.y; zj = q.z;
+                    ajx = a.x; ajy = a.y; ajz = a.z;
+                } else {
+                    const uint32_t pj = seg_src[s] + (v - v0);
+                    xj = (float)(2 * (bx + ox - 1)) + (float)pos[pj] * inv;
+                    yj = (float)(2 * (by + oy - 1)) + (float)pos[(int64_t)n + pj] * inv;
+                    zj = (float)(2 * (bz + oz - 1)) + (float)pos[2 * (int64_t)n + pj] * inv;
+                    ajx = abar[pj];
+                    ajy = abar[(int64_t)n + pj];
+                    ajz = abar[2 * (int64_t)n + pj];
+                }
+                const float dx = xj - xi, dy = yj - yi, dz = zj - zi;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 > 0.0f && r2 < law.bf2) {
+                    const float rinv = __frsqrt_rn(r2), r = r2 * rinv;
+                    const float tf = r * law.ibf;
+                    const float tp = r * law.ibpp;
+                    float g, dg;
+                    if (tp >= 1.0f && tf >= 0.5f) {
+                        // factored tail (see pp.hip): G(t) = (1-t)^5 Q(t) / t^3,
+                        // G'(t) = (1-t)^4 [-5 t Q + (1-t)(t Q' - 3 Q)] / t^4
+                        const float s = 1.0f - tf, s2 = s * s, tinv = law.bf * rinv;
+                        const float Q = 32.0f / 35.0f + tf * (32.0f / 7.0f + tf * (704.0f / 35.0f + tf * (64.0f / 5.0f)));
+                        const float dQ = 32.0f / 7.0f + tf * (1408.0f / 35.0f + tf * (192.0f / 5.0f));
+                        const float ti3 = tinv * tinv * tinv;
+                        g = law.ibf3 * s2 * s2 * s * Q * ti3;
+                        dg = law.ibf4 * s2 * s2 * (-5.0f * tf * Q + s * (tf * dQ - 3.0f * Q)) * ti3 * tinv;
+                    } else {
+                        float Ff, dFf, Fp, dFp;
+                        f_and_df(tf, law.bf * rinv, tf < 0.5f ? 0 : 1, Ff, dFf);
+                        f_and_df(tp, law.bpp * rinv, tp < 0.5f ? 0 : (tp < 1.0f ? 1 : 2), Fp, dFp);
+                        g = Fp * law.ibpp3 - Ff * law.ibf3;
+                        dg = dFp * law.ibpp4 - dFf * law.ibf4;
+                    }
+                    const float ux = ajx - akx, uy = ajy - aky, uz = ajz - akz;
+                    const float du = (dx * ux + dy * uy + dz * uz) * dg * rinv;
+                    sx += g * ux + du * dx;
+                    sy += g * uy + du * dy;
+                    sz += g * uz + du * dz;
+                }
+            }
+        }
+        const float xb[3] = {gm * sx, gm * sy, gm * sz};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            float *dst = xbar + (int64_t)d * n + p;
+            *dst = accumulate ? *dst + xb[d] : xb[d];
+        }
+    }
+}
+
+}  // namespace
+
+int launch_deposit_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                            int level, const float *rho_bar, float *x_bar, int accumulate,
+                            hipStream_t s) {
+    const int nt = ctx->nt;
+    const unsigned blocks = (unsigned)(nt * nt * nt);
+    if (level == 0) {
+        xbar_gather_kernel<false, false><<<blocks, kBlock, 0, s>>>(
+            pos, cs, nullptr, (int)n, ctx->n_f, nt, nullptr, rho_bar, 0.f, nullptr, nullptr, 0.f, 1,
+            0, x_bar, accumulate);
+    } else {
+        // coarse only: a zero fine rhobar contributes nothing
+        const Level &C = ctx->lv[1];
+        xbar_gather_kernel<false, true><<<blocks, kBlock, 0, s>>>(
+            pos, cs, nullptr, (int)n, ctx->n_f, nt, nullptr, nullptr, 0.f, nullptr, rho_bar, 0.f,
+            C.n, C.hshift, x_bar, accumulate);
+    }
+    CUBE2_LAUNCH_CHECK();
+    return CUBE2_OK;
+}
+
+int launch_pm_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                       const float *acc_bar, float *x_bar, int accumulate, unsigned char *work,
+                       const WorkLayout &L, hipStream_t s) {
+    const int nt = ctx->nt;
+    const unsigned blocks = (unsigned)(nt * nt * nt);
+    const double gm = ctx->cfg.g_newton * ctx->cfg.m_p;
+    float *rf = reinterpret_cast<float *>(work + L.real_f);
+    float *rc = ctx->n_levels > 1 ? reinterpret_cast<float *>(work + L.real_c) : nullptr;
+    float *bf = reinterpret_cast<float *>(work + L.bar_f);
+    float *bc = ctx->n_levels > 1 ? reinterpret_cast<float *>(work + L.bar_c) : nullptr;
+    float2 *spec = reinterpret_cast<float2 *>(work + L.spec);
+    // forward potentials (recomputed)
+    int r = launch_deposit(ctx, pos, cs, n, rf, nullptr, rc, nullptr, work, L, s);
+    if (r) return r;
+    for (int l = 0; l < ctx->n_levels; ++l) {
+        float *m = l == 0 ? rf : rc;
+        r = launch_potential(ctx, l, m, m, spec, s);
+        if (r) return r;
+    }
+    // phibar of the fine level, then rhobar = K phibar in place
+    fine_phibar_kernel<<<blocks, kBlock, 0, s>>>(pos, cs, acc_bar, (int)n, ctx->n_f, nt,
+                                                 (float)gm, bf);
+    CUBE2_LAUNCH_CHECK();
+    r = launch_potential(ctx, 0, bf, bf, spec, s);
+    if (r) return r;
+    float cc = 0.0f;
+    if (ctx->n_levels > 1) {
+        const Level &C = ctx->lv[1];
+        const int64_t m = (int64_t)C.n * C.n * C.n;
+        cc = (float)(gm / ((double)C.H * C.H));
+        // the coarse 3-component Abar mesh lives in the (free) spectrum buffer
+        float *Am = reinterpret_cast<float *>(spec);
+        fill_f32<<<(unsigned)((3 * m + 255) / 256), 256, 0, s>>>(Am, 3 * m);
+        CUBE2_LAUNCH_CHECK();
+        coarse_abar_kernel<<<blocks, kBlock, 0, s>>>(pos, cs, acc_bar, (int)n, nt, C.n, C.hshift,
+                                                     cc, Am);
+        CUBE2_LAUNCH_CHECK();
+        divergence_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(Am, C.n, bc);
+        CUBE2_LAUNCH_CHECK();
+        r = launch_potential(ctx, 1, bc, bc, spec, s);
+        if (r) return r;
+        xbar_gather_kernel<true, true><<<blocks, kBlock, 0, s>>>(
+            pos, cs, acc_bar, (int)n, ctx->n_f, nt, rf, bf, (float)gm, rc, bc, cc, C.n, C.hshift,
+            x_bar, accumulate);
+    } else {
+        xbar_gather_kernel<true, false><<<blocks, kBlock, 0, s>>>(
+            pos, cs, acc_bar, (int)n, ctx->n_f, nt, rf, bf, (float)gm, nullptr, nullptr, 0.f, 1, 0,
+            x_bar, accumulate);
+    }
+    CUBE2_LAUNCH_CHECK();
+    return CUBE2_OK;
+}
+
+int launch_pp_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                       const float *acc_bar, float *x_bar, int accumulate, hipStream_t s) {
+    const double bpp = ctx->cfg.b_pp, bf = ctx->cfg.b_fine;
+    PairLaw law;
+    law.bpp = (float)bpp;
+    law.ibpp = (float)(1.0 / bpp);
+    law.ibpp3 = (float)(1.0 / (bpp * bpp * bpp));
+    law.ibpp4 = (float)(1.0 / (bpp * bpp * bpp * bpp));
+    law.bf = (float)bf;
+    law.ibf = (float)(1.0 / bf);
+    law.ibf3 = (float)(1.0 / (bf * bf * bf));
+    law.ibf4 = (float)(1.0 / (bf * bf * bf * bf));
+    law.bf2 = (float)(bf * bf);
+    const int nt = ctx->nt;
+    pp_adjoint_kernel<<<(unsigned)(nt * nt * nt), kBlock, 0, s>>>(
+        pos, cs, acc_bar, (int)n, nt, law, (float)(ctx->cfg.g_newton * ctx->cfg.m_p), x_bar,
+        accumulate);
+    CUBE2_LAUNCH_CHECK();
+    return CUBE2_OK;
+}
+
+}  // namespace cube2

@@ -1,0 +1,173 @@
+// common.hpp -- shared definitions of the gfx950 CUBE2 force library.
+//
+// Geometry used by every kernel:
+//   * fine mesh: n_f cells per side, positions q in units of 2^-15 fine cells;
+//   * IOS cells of 2x2x2 fine cells (n_ios = n_f/2 per side), the unit of the
+//     particle order; tiles of 8^3 IOS cells (16^3 fine cells) group them;
+//   * key of IOS cell c = tile index * 512 + cell-in-tile index, both x fastest.
+// Every particle-side kernel runs one workgroup per tile: the tile's particles
+// are the contiguous range cell_start[key0] .. cell_start[key0 + 512].
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/cube2.h"
+
+namespace cube2 {
+
+constexpr int kFracBits = 15;     // in-cell fraction of a fine cell
+constexpr int kTileIos = 8;       // IOS cells per tile side
+constexpr int kTileFine = 16;     // fine cells per tile side
+constexpr int kTileCells = 512;   // IOS cells per tile
+constexpr int kBlock = 256;       // threads of the particle-side kernels
+
+struct Level {
+    int n = 0;          // cells per side
+    int H = 1;          // spacing in fine cells
+    int hshift = 0;     // log2(H)
+    int pitch = 0;      // complex row pitch of the half spectrum
+    double b_a = 0;     // softening of the level (fine cells)
+    double b_prev = 0;  // truncation (fine cells); <= 0 means infinity
+    size_t tw_off = 0;  // byte offset of the twiddle table in `tables`
+    size_t g_off = 0;   // byte offset of the octant Green's table
+};
+
+}  // namespace cube2
+
+struct cube2_ctx {
+    cube2_config cfg;
+    int n_f = 0, n_ios = 0, nt = 0;   // fine cells, IOS cells, tiles per side
+    int64_t n_cells = 0;               // IOS cells
+    int n_levels = 1;                  // 1 or 2; level 0 = fine, 1 = coarse
+    cube2::Level lv[2];
+    size_t table_bytes = 0;
+    unsigned char *tables = nullptr;   // device; set by cube2_init_tables
+};
+
+namespace cube2 {
+
+// Byte layout of the work buffer for n particles.
+struct WorkLayout {
+    size_t real_f, real_c, bar_f, bar_c, spec, coarse_acc;
+    size_t keys, vals, keys2, vals2, hist, counts, scan_tmp, offs_tmp, red;
+    size_t total;
+};
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+WorkLayout work_layout(const cube2_ctx *ctx, int64_t n);
+
+inline uint32_t *status_word(const cube2_ctx *ctx) {
+    return reinterpret_cast<uint32_t *>(ctx->tables);
+}
+
+// ---- device helpers ------------------------------------------------------
+
+__device__ __forceinline__ uint32_t cell_key(int cx, int cy, int cz, int nt) {
+    int tx = cx >> 3, ty = cy >> 3, tz = cz >> 3;
+    int ux = cx & 7, uy = cy & 7, uz = cz & 7;
+    return (uint32_t)(((tz * nt + ty) * nt + tx) * kTileCells + (uz * 8 + uy) * 8 + ux);
+}
+
+// Tile coordinates of workgroup b.  Blocks are dealt to the 8 XCDs round
+// robin; this mapping gives each XCD a contiguous slab of tiles so that the
+// halos shared between neighbouring tiles stay in one L2.
+__device__ __forceinline__ void tile_of_block(int b, int nt, int &tx, int &ty, int &tz) {
+    int ntiles = nt * nt * nt;
+    int t = b;
+    if ((ntiles & 7) == 0) t = (b & 7) * (ntiles >> 3) + (b >> 3);
+    tx = t % nt;
+    ty = (t / nt) % nt;
+    tz = t / (nt * nt);
+}
+
+__device__ __forceinline__ int wrapn(int i, int n) {  // n is a power of two
+    return i & (n - 1);
+}
+
+// Largest s in [0, cnt) with pre[s] <= v (pre nondecreasing, pre[0] <= v).
+__device__ __forceinline__ int seg_search(const uint32_t *pre, int cnt, uint32_t v) {
+    int lo = 0, hi = cnt;  // invariant: pre[lo] <= v, answer in [lo, hi)
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (pre[mid] <= v) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Block-wide exclusive scan of one uint32 per thread (blockDim == kBlock).
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh /*kBlock/64+1*/,
+                                                         uint32_t &total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        uint32_t s = sh[w];
+        if (w < wid) off += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return off + x - v;
+}
+
+// ---- launch helpers (host) -------------------------------------------------
+
+#define CUBE2_CHECK_HIP(expr)                                  \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return CUBE2_EHIP;               \
+    } while (0)
+
+#define CUBE2_LAUNCH_CHECK() CUBE2_CHECK_HIP(hipGetLastError())
+
+// Host entry points of the kernel files (return CUBE2_* codes).
+int launch_pack(cube2_ctx *ctx, const float *x, int64_t n, uint16_t *pos, uint32_t *cell_start,
+                int32_t *perm, unsigned char *work, const WorkLayout &L, hipStream_t s);
+int launch_sort_by_cell(cube2_ctx *ctx, int64_t n, const uint16_t *offs_in_unsorted,
+                        uint16_t *pos, uint32_t *cell_start, int32_t *perm,
+                        unsigned char *work, const WorkLayout &L, hipStream_t s);
+int launch_deposit(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                   float *rho_f, uint64_t *rho_f_fx, float *rho_c, uint64_t *rho_c_fx,
+                   unsigned char *work, const WorkLayout &L, hipStream_t s);
+int launch_green(cube2_ctx *ctx, hipStream_t s);
+int launch_fft_r2c(cube2_ctx *ctx, int level, const float *mesh, float2 *spec, hipStream_t s);
+int launch_potential(cube2_ctx *ctx, int level, const float *rho, float *phi, float2 *spec,
+                     hipStream_t s);
+int launch_interp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                  const float *phi_f, const float *phi_c, float *acc, int accumulate,
+                  hipStream_t s);
+int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, float *acc,
+              int accumulate, hipStream_t s);
+int launch_kick_drift(cube2_ctx *ctx, const uint16_t *pos_in, const uint32_t *cs_in,
+                      const float *vel_in, const float *acc, int64_t n, double kick,
+                      double drift, uint16_t *pos_out, uint32_t *cs_out, float *vel_out,
+                      int32_t *perm_out, unsigned char *work, const WorkLayout &L,
+                      hipStream_t s);
+int launch_reduce(cube2_ctx *ctx, const float *vel, const float *acc, int64_t n, double *out8,
+                  unsigned char *work, const WorkLayout &L, hipStream_t s);
+int launch_deposit_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                            int level, const float *rho_bar, float *x_bar, int accumulate,
+                            hipStream_t s);
+int launch_pm_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                       const float *acc_bar, float *x_bar, int accumulate, unsigned char *work,
+                       const WorkLayout &L, hipStream_t s);
+int launch_pp_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                       const float *acc_bar, float *x_bar, int accumulate, hipStream_t s);
+int launch_kick_drift_backward(cube2_ctx *ctx, int64_t n, const int32_t *perm,
+                               const float *xbar_out, const float *vbar_out, double kick,
+                               double drift, float *xbar_in, float *vbar_in, float *acc_bar,
+                               hipStream_t s);
+
+}  // namespace cube2

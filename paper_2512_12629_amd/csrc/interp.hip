@@ -1,0 +1,147 @@
+// interp.hip -- finite-difference force (eq. 7) and CIC interpolation back to
+// the particles (section 2.1.2, steps 3 and 4) for both PM levels in one
+// sweep over the cell-sorted particles.
+//
+// One workgroup per tile (8^3 IOS cells = 16^3 fine cells).  It stages in LDS
+// the fine potential on the tile plus a halo (2 nodes for the stencil below,
+// 3 above: the CIC upper node plus the stencil), and the coarse potential on
+// the tile's coarse footprint with the same halo.  Each particle then reads
+// the 6 potential values along each axis around its 2x2 CIC footprint and
+// forms E = -[(2/3)(phi(+1) - phi(-1)) - (1/12)(phi(+2) - phi(-2))] at its two
+// nodes per axis, weighted with the deposit's 15-bit integer weights.
+#include "common.hpp"
+
+namespace cube2 {
+namespace {
+
+constexpr int kFS = kTileFine + 5;        // 21: fine tile with halo
+constexpr int kCSMax = kTileFine / 2 + 5; // 13: coarse tile with halo (ratio 2)
+
+// FD force at the particle's two nodes along one axis, CIC-weighted.
+// p points at phi(node j) on that axis; st is the axis stride in LDS.
+__device__ __forceinline__ float axis_force(const float *p, int st, float w0, float w1) {
+    const float pm2 = p[-2 * st], pm1 = p[-st], p0 = p[0], p1 = p[st], p2 = p[2 * st],
+                p3 = p[3 * st];
+    const float e0 = -((2.0f / 3.0f) * (p1 - pm1) - (1.0f / 12.0f) * (p2 - pm2));
+    const float e1 = -((2.0f / 3.0f) * (p2 - p0) - (1.0f / 12.0f) * (p3 - pm1));
+    return w0 * e0 + w1 * e1;
+}
+
+// CIC-weighted force of a staged potential tile P (side S) at the particle
+// whose lower CIC node is (jx, jy, jz) in tile coordinates.
+__device__ __forceinline__ void gather(const float *P, int S, int jx, int jy, int jz,
+                                       const float (&wx)[2], const float (&wy)[2],
+                                       const float (&wz)[2], float &ax, float &ay, float &az) {
+    const int SS = S * S;
+    ax = ay = az = 0.0f;
+#pragma unroll
+    for (int s1 = 0; s1 < 2; ++s1)
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+            // x: nodes (jx.., jy+s1, jz+s2)
+            ax += wy[s1] * wz[s2] * axis_force(P + (jz + s2) * SS + (jy + s1) * S + jx, 1, wx[0], wx[1]);
+            // y: nodes (jx+s1, jy.., jz+s2)
+            ay += wx[s1] * wz[s2] * axis_force(P + (jz + s2) * SS + jy * S + jx + s1, S, wy[0], wy[1]);
+            // z: nodes (jx+s1, jy+s2, jz..)
+            az += wx[s1] * wy[s2] * axis_force(P + jz * SS + (jy + s2) * S + jx + s1, SS, wz[0], wz[1]);
+        }
+}
+
+template <bool TWO>
+__global__ __launch_bounds__(kBlock) void interp_kernel(
+    const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs, int n, int n_f, int nt,
+    const float *__restrict__ phi_f, const float *__restrict__ phi_c, int n_c, int hshift,
+    float scale_f, float scale_c, float *__restrict__ acc, int accumulate) {
+    __shared__ float pf[kFS * kFS * kFS];
+    __shared__ float pc[TWO ? kCSMax * kCSMax * kCSMax : 1];
+    __shared__ uint32_t cst[kTileCells + 1];
+
+    int tx, ty, tz;
+    tile_of_block(blockIdx.x, nt, tx, ty, tz);
+    const int tid = threadIdx.x;
+    const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
+    for (int i = tid; i <= kTileCells; i += kBlock) cst[i] = cs[key0 + i];
+    const int ax0 = tx * kTileFine, ay0 = ty * kTileFine, az0 = tz * kTileFine;
+    for (int i = tid; i < kFS * kFS * kFS; i += kBlock) {
+        const int lx = i % kFS, ly = (i / kFS) % kFS, lz = i / (kFS * kFS);
+        const int gx = wrapn(ax0 + lx - 2, n_f), gy = wrapn(ay0 + ly - 2, n_f),
+                  gz = wrapn(az0 + lz - 2, n_f);
+        pf[i] = phi_f[((int64_t)gz * n_f + gy) * n_f + gx];
+    }
+    const int CS = (kTileFine >> hshift) + 5;
+    if (TWO) {
+        const int cx0 = ax0 >> hshift, cy0 = ay0 >> hshift, cz0 = az0 >> hshift;
+        for (int i = tid; i < CS * CS * CS; i += kBlock) {
+            const int lx = i % CS, ly = (i / CS) % CS, lz = i / (CS * CS);
+            const int gx = wrapn(cx0 + lx - 2, n_c), gy = wrapn(cy0 + ly - 2, n_c),
+                      gz = wrapn(cz0 + lz - 2, n_c);
+            pc[i] = phi_c[((int64_t)gz * n_c + gy) * n_c + gx];
+        }
+    }
+    __syncthreads();
+    const uint32_t p0 = cst[0], p1 = cst[kTileCells];
+    const float inv = 1.0f / 32768.0f;
+    for (uint32_t p = p0 + tid; p < p1; p += kBlock) {
+        const int u = seg_search(cst, kTileCells, p);
+        const int uc[3] = {u & 7, (u >> 3) & 7, u >> 6};
+        int jf[3], jc[3];
+        float wf[3][2], wc[3][2];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const uint32_t o = pos[(int64_t)d * n + p];
+            const int f = (int)(o & 0x7FFFu);
+            jf[d] = 2 * uc[d] + (int)(o >> 15) + 2;       // +2: LDS halo
+            wf[d][1] = (float)f * inv;
+            wf[d][0] = (float)(32768 - f) * inv;
+            if (TWO) {
+                const uint32_t q = ((uint32_t)uc[d] << 16) + o;  // tile-relative, 2^-15 units
+                const int fc = (int)((q >> hshift) & 0x7FFFu);
+                jc[d] = (int)(q >> (kFracBits + hshift)) + 2;
+                wc[d][1] = (float)fc * inv;
+                wc[d][0] = (float)(32768 - fc) * inv;
+            }
+        }
+        float a[3];
+        gather(pf, kFS, jf[0], jf[1], jf[2], wf[0], wf[1], wf[2], a[0], a[1], a[2]);
+        a[0] *= scale_f;
+        a[1] *= scale_f;
+        a[2] *= scale_f;
+        if (TWO) {
+            float c[3];
+            gather(pc, CS, jc[0], jc[1], jc[2], wc[0], wc[1], wc[2], c[0], c[1], c[2]);
+            a[0] += scale_c * c[0];
+            a[1] += scale_c * c[1];
+            a[2] += scale_c * c[2];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            float *dst = acc + (int64_t)d * n + p;
+            *dst = accumulate ? *dst + a[d] : a[d];
+        }
+    }
+}
+
+}  // namespace
+
+int launch_interp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                  const float *phi_f, const float *phi_c, float *acc, int accumulate,
+                  hipStream_t s) {
+    const int nt = ctx->nt;
+    const unsigned blocks = (unsigned)(nt * nt * nt);
+    const double gm = ctx->cfg.g_newton * ctx->cfg.m_p;
+    if (ctx->n_levels > 1) {
+        const Level &C = ctx->lv[1];
+        interp_kernel<true><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, phi_f, phi_c,
+                                                     C.n, C.hshift, (float)gm,
+                                                     (float)(gm / ((double)C.H * C.H)), acc,
+                                                     accumulate);
+    } else {
+        interp_kernel<false><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, phi_f,
+                                                      nullptr, 1, 0, (float)gm, 0.0f, acc,
+                                                      accumulate);
+    }
+    CUBE2_LAUNCH_CHECK();
+    return CUBE2_OK;
+}
+
+}  // namespace cube2

@@ -1,0 +1,231 @@
+// pack.hip -- IOS particle order (section 2.3): quantise positions to integer
+// in-cell offsets and sort particles stably by IOS cell, so that the particle
+// order encodes cell membership and a prefix count per cell (cell_start)
+// replaces per-particle cell indices.
+//
+// The sort is a stable least-significant-digit radix sort on the cell key
+// (8-bit digits), written for 64-wide wavefronts: per 4096-key block a digit
+// histogram, one device-wide scan of the digit-major histogram, then a
+// scatter in which each key's rank among equal digits of its block comes
+// from wave ballots (a 64-lane match on the digit) plus per-wave counts in
+// LDS.  Ties keep their input order, so the result equals a stable argsort.
+#include "common.hpp"
+
+namespace cube2 {
+namespace {
+
+constexpr int kSortItems = 16;                   // keys per thread per block
+constexpr int kSortTile = kBlock * kSortItems;   // 4096 keys per block
+constexpr int kScanItems = 4;                    // items per thread in the scan
+constexpr int kScanTile = kBlock * kScanItems;   // 1024
+
+__global__ void fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// q = floor(x * n_f * 2^15) mod (n_f * 2^15); key of the IOS cell; offsets.
+__global__ void quantize_kernel(const float *__restrict__ x, int n, int n_f, int nt,
+                                uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                uint16_t *__restrict__ offs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double span = (double)n_f * 32768.0;
+    const int64_t mask = (int64_t)n_f * 32768 - 1;
+    int c[3];
+    for (int d = 0; d < 3; ++d) {
+        const int64_t q = (int64_t)floor((double)x[(int64_t)d * n + i] * span) & mask;
+        c[d] = (int)(q >> 16);
+        offs[(int64_t)d * n + i] = (uint16_t)(q & 0xFFFF);
+    }
+    keys[i] = cell_key(c[0], c[1], c[2], nt);
+    vals[i] = (uint32_t)i;
+}
+
+__global__ void histogram_kernel(const uint32_t *__restrict__ keys, int n,
+                                 uint32_t *__restrict__ counts) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&counts[keys[i]], 1u);
+}
+
+// Exclusive scan, phase 1: scan each 1024-element tile, record tile sums.
+__global__ void scan_tiles(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                           int64_t m, uint32_t *__restrict__ sums) {
+    __shared__ uint32_t sh[kBlock / 64 + 1];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems], s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < m) ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t total;
+    uint32_t pre = block_exclusive_scan(s, sh, total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < m) out[base + k] = pre;
+        pre += v[k];
+    }
+    if (threadIdx.x == 0 && sums) sums[blockIdx.x] = total;
+}
+
+__global__ void scan_add(uint32_t *__restrict__ out, int64_t m, const uint32_t *__restrict__ offs) {
+    const int64_t i = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
+    const uint32_t o = offs[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t j = i + (int64_t)k * kBlock;
+        if (j < m) out[j] += o;
+    }
+}
+
+// Device-wide exclusive scan of m entries (in may equal out); tmp holds
+// the per-level tile sums.
+int exclusive_scan(const uint32_t *in, uint32_t *out, int64_t m, uint32_t *tmp, hipStream_t s) {
+    const int64_t tiles = (m + kScanTile - 1) / kScanTile;
+    if (tiles <= 1) {
+        scan_tiles<<<1, kBlock, 0, s>>>(in, out, m, nullptr);
+        CUBE2_LAUNCH_CHECK();
+        return CUBE2_OK;
+    }
+    uint32_t *sums = tmp;
+    scan_tiles<<<(unsigned)tiles, kBlock, 0, s>>>(in, out, m, sums);
+    CUBE2_LAUNCH_CHECK();
+    int r = exclusive_scan(sums, sums, tiles, tmp + align_up((size_t)tiles, 64), s);
+    if (r) return r;
+    scan_add<<<(unsigned)tiles, kBlock, 0, s>>>(out, m, sums);
+    CUBE2_LAUNCH_CHECK();
+    return CUBE2_OK;
+}
+
+__global__ void radix_count(const uint32_t *__restrict__ keys, int n, int shift, int nblk,
+                            uint32_t *__restrict__ ghist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t i = base + r * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    ghist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                              uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int n,
+                              int shift, int nblk, const uint32_t *__restrict__ goff) {
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[kBlock / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    base[tid] = goff[(int64_t)tid * nblk + blockIdx.x];
+    for (int k = 0; k < kBlock / 64; ++k) wcnt[k][tid] = 0;
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t blk0 = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t i = blk0 + r * kBlock + tid;
+        const bool valid = i < n;
+        uint32_t key = 0, val = 0, dig = 0;
+        if (valid) {
+            key = kin[i];
+            val = vin[i];
+            dig = (key >> shift) & 255u;
+        }
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (dig >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == 0) wcnt[w][dig] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t o = base[dig] + rank;
+            for (int k = 0; k < w; ++k) o += wcnt[k][dig];
+            kout[o] = key;
+            vout[o] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int k = 0; k < kBlock / 64; ++k) {
+            add += wcnt[k][tid];
+            wcnt[k][tid] = 0;
+        }
+        base[tid] += add;
+        __syncthreads();
+    }
+}
+
+__global__ void gather_offsets(const uint32_t *__restrict__ perm, const uint16_t *__restrict__ offs,
+                               int n, uint16_t *__restrict__ pos, int32_t *__restrict__ perm_out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t p = perm[i];
+    pos[i] = offs[p];
+    pos[(int64_t)n + i] = offs[(int64_t)n + p];
+    pos[2 * (int64_t)n + i] = offs[2 * (int64_t)n + p];
+    if (perm_out) perm_out[i] = (int32_t)p;
+}
+
+}  // namespace
+
+// keys/vals (work) and offs_tmp (work) hold the unsorted particles.
+int launch_sort_by_cell(cube2_ctx *ctx, int64_t n64, const uint16_t *offs, uint16_t *pos,
+                        uint32_t *cell_start, int32_t *perm, unsigned char *work,
+                        const WorkLayout &L, hipStream_t s) {
+    const int n = (int)n64;
+    uint32_t *counts = reinterpret_cast<uint32_t *>(work + L.counts);
+    uint32_t *tmp = reinterpret_cast<uint32_t *>(work + L.scan_tmp);
+    uint32_t *k0 = reinterpret_cast<uint32_t *>(work + L.keys);
+    uint32_t *v0 = reinterpret_cast<uint32_t *>(work + L.vals);
+    uint32_t *k1 = reinterpret_cast<uint32_t *>(work + L.keys2);
+    uint32_t *v1 = reinterpret_cast<uint32_t *>(work + L.vals2);
+    uint32_t *ghist = reinterpret_cast<uint32_t *>(work + L.hist);
+    const int64_t m = ctx->n_cells + 1;
+
+    // cell_start = exclusive scan of the per-cell counts (last entry = n)
+    fill_u32<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(counts, 0u, m);
+    CUBE2_LAUNCH_CHECK();
+    if (n > 0) {
+        histogram_kernel<<<(n + 255) / 256, 256, 0, s>>>(k0, n, counts);
+        CUBE2_LAUNCH_CHECK();
+    }
+    int r = exclusive_scan(counts, cell_start, m, tmp, s);
+    if (r) return r;
+    if (n == 0) return CUBE2_OK;
+
+    int bits = 0;
+    while (((int64_t)1 << bits) < ctx->n_cells) ++bits;
+    const int nblk = (n + kSortTile - 1) / kSortTile;
+    for (int shift = 0; shift < bits; shift += 8) {
+        radix_count<<<nblk, kBlock, 0, s>>>(k0, n, shift, nblk, ghist);
+        CUBE2_LAUNCH_CHECK();
+        r = exclusive_scan(ghist, ghist, (int64_t)nblk * 256, tmp, s);
+        if (r) return r;
+        radix_scatter<<<nblk, kBlock, 0, s>>>(k0, v0, k1, v1, n, shift, nblk, ghist);
+        CUBE2_LAUNCH_CHECK();
+        uint32_t *t = k0; k0 = k1; k1 = t;
+        t = v0; v0 = v1; v1 = t;
+    }
+    gather_offsets<<<(n + 255) / 256, 256, 0, s>>>(v0, offs, n, pos, perm);
+    CUBE2_LAUNCH_CHECK();
+    return CUBE2_OK;
+}
+
+int launch_pack(cube2_ctx *ctx, const float *x, int64_t n64, uint16_t *pos, uint32_t *cell_start,
+                int32_t *perm, unsigned char *work, const WorkLayout &L, hipStream_t s) {
+    const int n = (int)n64;
+    uint16_t *offs = reinterpret_cast<uint16_t *>(work + L.offs_tmp);
+    if (n > 0) {
+        quantize_kernel<<<(n + 255) / 256, 256, 0, s>>>(
+            x, n, ctx->n_f, ctx->nt, reinterpret_cast<uint32_t *>(work + L.keys),
+            reinterpret_cast<uint32_t *>(work + L.vals), offs);
+        CUBE2_LAUNCH_CHECK();
+    }
+    return launch_sort_by_cell(ctx, n, offs, pos, cell_start, perm, work, L, s);
+}
+
+}  // namespace cube2
