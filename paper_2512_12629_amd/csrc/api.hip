@@ -1,5 +1,6 @@
 // api.hip -- the C ABI of include/cube2.h: argument checks, buffer layout
 // and the order of the launches.  All arithmetic is in the kernel files.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -27,6 +28,8 @@ size_t table_layout(cube2_ctx *c) {
         L.g_off = off;
         off = align_up(off + h * h * h * sizeof(float), 256);
     }
+    c->pp_off = off;
+    off = align_up(off + (size_t)(kPairKMax + 1) * kPairRow * sizeof(float), 256);
     return off;
 }
 
@@ -55,7 +58,8 @@ WorkLayout work_layout(const cube2_ctx *c, int64_t n) {
     size_t nblk = (nn + 4095) / 4096;
     L.hist = take(nblk * 256 * 4 + 1024);
     L.counts = take((size_t)(c->n_cells + 1) * 4);
-    L.scan_tmp = take(((size_t)(c->n_cells + 1) / 1024 + 64) * 4 * 2 + 4096);
+    const size_t scan_len = std::max((size_t)(c->n_cells + 1), nblk * 256);
+    L.scan_tmp = take((scan_len / 1024 + 64) * 4 * 2 + 4096);
     L.offs_tmp = take(nn * 3 * sizeof(uint16_t));
     L.red = take(8192 * 8 * sizeof(double));
     L.total = off;
@@ -116,6 +120,7 @@ int cube2_create(const cube2_config *cfg, cube2_ctx **out) {
         C.b_prev = -1.0;
     }
     ctx->table_bytes = table_layout(ctx);
+    build_pair_table(ctx);
     *out = ctx;
     return CUBE2_OK;
 }
@@ -142,6 +147,8 @@ int cube2_init_tables(cube2_ctx *ctx, void *tables, size_t table_bytes, cube2_st
     ctx->tables = static_cast<unsigned char *>(tables);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     CUBE2_CHECK_HIP(hipMemsetAsync(ctx->tables, 0, 256, s));
+    CUBE2_CHECK_HIP(hipMemcpyAsync(ctx->tables + ctx->pp_off, ctx->pp_rows.data(),
+                                   ctx->pp_rows.size() * sizeof(float), hipMemcpyHostToDevice, s));
     return launch_green(ctx, s);
 }
 

@@ -13,6 +13,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/cube2.h"
 
@@ -37,8 +38,18 @@ struct Level {
 
 }  // namespace cube2
 
+namespace cube2 {
+// Pair-law table of the PP kernels (built on the host, see pp.hip).
+constexpr int kPairKMax = 64;      // grid intervals of [0, b_f)
+constexpr int kPairRow = 12;       // floats per interval: 9 coefficients, y map, pad
+}  // namespace cube2
+
 struct cube2_ctx {
     cube2_config cfg;
+    int pp_K = 0;                      // intervals of the pair-law grid
+    float pp_kinv = 0.f;               // K / b_f
+    std::vector<float> pp_rows;        // (K+1) * kPairRow floats (host copy)
+    size_t pp_off = 0;                 // byte offset of the pair-law table in `tables`
     int n_f = 0, n_ios = 0, nt = 0;   // fine cells, IOS cells, tiles per side
     int64_t n_cells = 0;               // IOS cells
     int n_levels = 1;                  // 1 or 2; level 0 = fine, 1 = coarse
@@ -98,8 +109,9 @@ __device__ __forceinline__ int seg_search(const uint32_t *pre, int cnt, uint32_t
     return lo;
 }
 
-// Block-wide exclusive scan of one uint32 per thread (blockDim == kBlock).
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh /*kBlock/64+1*/,
+// Block-wide exclusive scan of one uint32 per thread (blockDim == BLOCK).
+template <int BLOCK = kBlock>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh /*BLOCK/64+1*/,
                                                          uint32_t &total) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint32_t x = v;
@@ -112,7 +124,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
     __syncthreads();
     uint32_t off = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
+    for (int w = 0; w < BLOCK / 64; ++w) {
         uint32_t s = sh[w];
         if (w < wid) off += s;
         tot += s;
@@ -150,6 +162,7 @@ int launch_interp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64
                   hipStream_t s);
 int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, float *acc,
               int accumulate, hipStream_t s);
+void build_pair_table(cube2_ctx *ctx);
 int launch_kick_drift(cube2_ctx *ctx, const uint16_t *pos_in, const uint32_t *cs_in,
                       const float *vel_in, const float *acc, int64_t n, double kick,
                       double drift, uint16_t *pos_out, uint32_t *cs_out, float *vel_out,

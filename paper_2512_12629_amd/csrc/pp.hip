@@ -10,10 +10,14 @@
 // the tile origin in fine cells.  Offsets are multiples of 2^-15 below 2^5,
 // so these floats and their differences are exact: the pair separation is
 // the exact integer one.  Each thread takes one particle of the tile and
-// loops over its 27 neighbour cells; neighbours in a dense cell are read by
-// all lanes of a wave at the same LDS address (a broadcast).  Per neighbour
-// cell the pair sum is accumulated in FP32 and then added to the total with
+// loops over its 27 neighbour cells, which in the staged box are 9
+// contiguous ranges (x-rows of three cells); neighbours in a dense cell are
+// read by all lanes of a wave at the same LDS address (a broadcast).  Per
+// range the pair sum is accumulated in FP32 and then added to the total with
 // Kahan compensation.  Boxes too large for LDS read the same data from HBM.
+#include <algorithm>
+#include <cmath>
+
 #include "common.hpp"
 
 namespace cube2 {
@@ -21,53 +25,31 @@ namespace {
 
 constexpr int kPB = kTileIos + 2;          // 10 IOS cells per axis
 constexpr int kPSegs = kPB * kPB * kPB;    // 1000
-constexpr int kPSegPerThread = (kPSegs + kBlock - 1) / kBlock;  // 4
-constexpr int kCap = 3072;                 // staged particles (48 KB)
+constexpr int kPPBlock = 512;              // 8 waves: 4 per SIMD at 2 blocks per CU
+constexpr int kPSegPerThread = (kPSegs + kPPBlock - 1) / kPPBlock;  // 2
+constexpr int kCap = 3840;                 // staged particles (60 KB)
 
-struct PairLaw {
-    // R(r,b)/r in terms of t = r/b:  b^-3 F(t) with
-    //   F_in(t)  = 64/5 - 256/5 t^2 + 32 t^3 + 1536/35 t^4 - 192/5 t^5        (t < 1/2)
-    //   F_out(t) = 3/(35 t^3) - 32/(5 t) + 256/5 - 96 t + 256/5 t^2 + 32 t^3
-    //              - 1536/35 t^4 + 64/5 t^5                                   (1/2 <= t < 1)
-    //   F(t)     = t^-3                                                       (t >= 1)
-    float bpp, ibpp, ibpp3;  // b_pp, 1/b_pp, 1/b_pp^3
-    float bf, ibf, ibf3, bf2;
-};
+}  // namespace
 
-__device__ __forceinline__ float f_in(float t) {
-    const float t2 = t * t;
-    return 64.0f / 5.0f + t2 * (-256.0f / 5.0f + t * (32.0f + t * (1536.0f / 35.0f + t * (-192.0f / 5.0f))));
-}
-__device__ __forceinline__ float f_out(float t, float tinv) {
-    const float poly = 256.0f / 5.0f + t * (-96.0f + t * (256.0f / 5.0f + t * (32.0f + t * (-1536.0f / 35.0f + t * (64.0f / 5.0f)))));
-    return poly + tinv * (-32.0f / 5.0f + tinv * tinv * (3.0f / 35.0f));
-}
+// The pair law g(r) = [R(r,b_pp) - R(r,b_f)] / r (eqs. 2 and 4d) as
+// g = U(r) / r^3 with U = r^3 g.  On each of the intervals delimited by the
+// breakpoints of eq. (2) -- b_pp/2, b_pp (PP softening), b_f/2 (fine
+// softening) -- and the cutoff b_f, U is an exact polynomial of degree 8 in r:
+//   r^3 b^-3 F_in(r/b)  = sum_k a_k b^(-3-k) r^(k+3),
+//   r^3 b^-3 F_out(r/b) = 3/35 - 32/5 (r/b)^2 + sum_k c_k b^(-3-k) r^(k+3),
+//   r^3 r^-3 = 1 (Newtonian beyond b_pp),
+// with F_in, F_out the two polynomial branches of R(r,b)/r in t = r/b.
+// [0, b_f) is cut into K equal intervals with every breakpoint on an
+// interval edge, and each interval stores its polynomial re-expanded (FP64,
+// on the host) in a local variable y in [0, 1]:  y = fract(r K / b_f) (left
+// edge, keeps U ~ r^3 accurate at r -> 0) or y = 1 - fract(.) (right edge)
+// on the intervals where 1/r^2 - R(r, b_f) vanishes like (1 - r/b_f)^5 at the
+// cutoff, which use the exact factorisation r^3 g = s^5 Q(1 - s),
+// s = 1 - r/b_f, Q(t) = 32/35 + 32/7 t + 704/35 t^2 + 64/5 t^3.  The row of
+// r >= b_f is zero.  The interval is r K / b_f truncated: one multiply and
+// no compare chain; each lane reads its row (12 floats) from LDS.
 
-// On b_f/2 <= r < b_f with r >= b_pp, g = [1/r^2 - R(r, b_f)] / r vanishes
-// like (1 - t)^5 at the cutoff and the difference cancels in FP32.  Dividing
-// out the root gives the exact factored form
-//   g = b_f^-3 (1 - t)^5 (32/35 + 32/7 t + 704/35 t^2 + 64/5 t^3) / t^3.
-__device__ __forceinline__ float tail_poly(float t) {
-    return 32.0f / 35.0f + t * (32.0f / 7.0f + t * (704.0f / 35.0f + t * (64.0f / 5.0f)));
-}
-
-// g(r) = [R(r,b_pp) - R(r,b_f)] / r for 0 < r < b_f (caller checks the range).
-__device__ __forceinline__ float pair_g(float r2, const PairLaw &L) {
-    const float rinv = __frsqrt_rn(r2);
-    const float r = r2 * rinv;
-    const float tf = r * L.ibf;  // < 1
-    if (r >= L.bpp) {
-        if (tf >= 0.5f) {
-            const float s = 1.0f - tf, s2 = s * s, tinv = L.bf * rinv;
-            return L.ibf3 * (s2 * s2 * s) * tail_poly(tf) * (tinv * tinv * tinv);
-        }
-        return rinv * rinv * rinv - f_in(tf) * L.ibf3;
-    }
-    const float gf = (tf < 0.5f ? f_in(tf) : f_out(tf, L.bf * rinv)) * L.ibf3;
-    const float tp = r * L.ibpp;
-    const float gp = (tp < 0.5f ? f_in(tp) : f_out(tp, L.bpp * rinv)) * L.ibpp3;
-    return gp - gf;
-}
+namespace {
 
 __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
     const float y = v - c;
@@ -76,21 +58,53 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
     s = t;
 }
 
-__global__ __launch_bounds__(kBlock) void pp_kernel(const uint16_t *__restrict__ pos,
-                                                    const uint32_t *__restrict__ cs, int n, int nt,
-                                                    PairLaw law, float gm,
-                                                    float *__restrict__ acc, int accumulate) {
+// g(r) * D accumulated into (fx, fy, fz); rows (LDS) hold the pair-law table.
+__device__ __forceinline__ void pair_accumulate(float dx, float dy, float dz, const float4 *rows,
+                                                float kinv, int K, float &fx, float &fy,
+                                                float &fz) {
+    // coincident particles (D = 0, r2 = 0) are clamped to r2 = 1e-12, below the
+    // smallest nonzero separation (2^-15 fine cells), so g stays finite and g D = 0
+    const float r2 = fmaxf(dx * dx + dy * dy + dz * dz, 1e-12f);
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * rinv;
+    const float f = r * kinv;
+    const int idx = min((int)f, K);
+    const float4 c0 = rows[3 * idx], c1 = rows[3 * idx + 1], c2 = rows[3 * idx + 2];
+    const float y = c2.y + c2.z * __builtin_amdgcn_fractf(f);
+    const float U =
+        c0.x + y * (c0.y + y * (c0.z + y * (c0.w + y * (c1.x + y * (c1.y + y * (c1.z + y * (c1.w + y * c2.x)))))));
+    const float g = U * (rinv * rinv * rinv);
+    fx += g * dx;
+    fy += g * dy;
+    fz += g * dz;
+}
+
+// Heavy tiles are done in z-chunks: own cells are ordered z-major, so the own
+// cells of z-layers [z0, z1) are a contiguous particle range and the box cells
+// they need are the contiguous box layers [z0, z1 + 2), a contiguous slice of
+// the staged list.
+
+__global__ __launch_bounds__(kPPBlock) void pp_kernel(const uint16_t *__restrict__ pos,
+                                                     const uint32_t *__restrict__ cs, int n,
+                                                     int nt, const float4 *__restrict__ table,
+                                                     int K, float kinv, float gm,
+                                                     float *__restrict__ acc, int accumulate) {
     __shared__ uint32_t seg_pre[kPSegs + 1];
     __shared__ uint32_t seg_src[kPSegs];
     __shared__ float4 xs[kCap];
-    __shared__ uint32_t scan_sh[kBlock / 64 + 1];
+    __shared__ float4 rows[3 * (kPairKMax + 1)];
+    __shared__ uint32_t cst[kTileCells + 1];     // own cells: particle starts (tile-relative)
+    __shared__ uint32_t scan_sh[kPPBlock / 64 + 1];
+    __shared__ int chunk_sh;
 
     int tx, ty, tz;
     tile_of_block(blockIdx.x, nt, tx, ty, tz);
     const int tid = threadIdx.x;
     const int n_ios = nt * kTileIos;
     const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
+    for (int i = tid; i < 3 * (K + 1); i += kPPBlock) rows[i] = table[i];
 
+    // particle ranges of the 10^3 box of IOS cells [c0-1, c0+9)
     uint32_t cnt[kPSegPerThread], src[kPSegPerThread], sum = 0;
 #pragma unroll
     for (int k = 0; k < kPSegPerThread; ++k) {
@@ -107,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void pp_kernel(const uint16_t *__restrict__
         sum += cnt[k];
     }
     uint32_t total;
-    uint32_t pre = block_exclusive_scan(sum, scan_sh, total);
+    uint32_t pre = block_exclusive_scan<kPPBlock>(sum, scan_sh, total);
 #pragma unroll
     for (int k = 0; k < kPSegPerThread; ++k) {
         const int s = tid * kPSegPerThread + k;
@@ -117,97 +131,197 @@ __global__ __launch_bounds__(kBlock) void pp_kernel(const uint16_t *__restrict__
         }
         pre += cnt[k];
     }
-    if (tid == 0) seg_pre[kPSegs] = total;
-    __syncthreads();
-    const bool staged = total <= (uint32_t)kCap;
-    const float inv = 1.0f / 32768.0f;
-    if (staged) {
-        for (uint32_t v = tid; v < total; v += kBlock) {
-            const int s = seg_search(seg_pre, kPSegs, v);
-            const uint32_t p = seg_src[s] + (v - seg_pre[s]);
-            const int bx = s % kPB, by = (s / kPB) % kPB, bz = s / (kPB * kPB);
-            float4 q;
-            q.x = (float)(2 * (bx - 1)) + (float)pos[p] * inv;
-            q.y = (float)(2 * (by - 1)) + (float)pos[(int64_t)n + p] * inv;
-            q.z = (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv;
-            q.w = 0.0f;
-            xs[v] = q;
+    // own cells: particle starts relative to the tile's first particle
+    const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
+    const uint32_t p0 = cs[key0];
+    cst[tid] = cs[key0 + tid] - p0;
+    if (tid == 0) {
+        seg_pre[kPSegs] = total;
+        cst[kTileCells] = cs[key0 + kTileCells] - p0;
+        // z-chunks: the smallest power-of-two count whose staged slices fit
+        int C = 1;
+        for (; C < 8; C <<= 1) {
+            bool fits = true;
+            for (int c = 0; c < C; ++c) {
+                const int z0 = c * 8 / C, z1 = (c + 1) * 8 / C;
+                if (seg_pre[(z1 + 2) * kPB * kPB] - seg_pre[z0 * kPB * kPB] > (uint32_t)kCap)
+                    fits = false;
+            }
+            if (fits) break;
         }
+        chunk_sh = C;
     }
     __syncthreads();
+    const int C = chunk_sh;
+    const float inv = 1.0f / 32768.0f;
 
-    // own particles: box cells with b in [1, 9)
-    const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
-    const uint32_t p0 = cs[key0], p1 = cs[key0 + kTileCells];
-    for (uint32_t p = p0 + tid; p < p1; p += kBlock) {
-        // the own cell of p: search the own cells' segments (row by row is
-        // not contiguous in the box), using the tile's cell_start directly
-        int lo = 0, hi = kTileCells;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (cs[key0 + mid] <= p) lo = mid; else hi = mid;
+    for (int c = 0; c < C; ++c) {
+        const int z0 = c * 8 / C, z1 = (c + 1) * 8 / C;
+        const uint32_t vb = seg_pre[z0 * kPB * kPB], ve = seg_pre[(z1 + 2) * kPB * kPB];
+        const bool staged = ve - vb <= (uint32_t)kCap;
+        if (c > 0) __syncthreads();  // previous chunk done with xs
+        if (staged) {
+            for (uint32_t v = vb + tid; v < ve; v += kPPBlock) {
+                const int s = seg_search(seg_pre, kPSegs, v);
+                const uint32_t p = seg_src[s] + (v - seg_pre[s]);
+                const int bx = s % kPB, by = (s / kPB) % kPB, bz = s / (kPB * kPB);
+                float4 q;
+                q.x = (float)(2 * (bx - 1)) + (float)pos[p] * inv;
+                q.y = (float)(2 * (by - 1)) + (float)pos[(int64_t)n + p] * inv;
+                q.z = (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv;
+                q.w = 0.0f;
+                xs[v - vb] = q;
+            }
         }
-        const int bx = (lo & 7) + 1, by = ((lo >> 3) & 7) + 1, bz = (lo >> 6) + 1;
-        const float xi = (float)(2 * (bx - 1)) + (float)pos[p] * inv;
-        const float yi = (float)(2 * (by - 1)) + (float)pos[(int64_t)n + p] * inv;
-        const float zi = (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv;
-        float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
-        for (int nb = 0; nb < 27; ++nb) {
-            const int ox = nb % 3 - 1, oy = (nb / 3) % 3 - 1, oz = nb / 9 - 1;
-            const int s = ((bz + oz) * kPB + (by + oy)) * kPB + (bx + ox);
-            const uint32_t v0 = seg_pre[s], v1 = seg_pre[s + 1];
-            float fx = 0.f, fy = 0.f, fz = 0.f;
-            for (uint32_t v = v0; v < v1; ++v) {
-                float xj, yj, zj;
-                if (staged) {
-                    const float4 q = xs[v];
-                    xj = q.x;
-                    yj = q.y;
-                    zj = q.z;
-                } else {
-                    const uint32_t pj = seg_src[s] + (v - v0);
-                    xj = (float)(2 * (bx + ox - 1)) + (float)pos[pj] * inv;
-                    yj = (float)(2 * (by + oy - 1)) + (float)pos[(int64_t)n + pj] * inv;
-                    zj = (float)(2 * (bz + oz - 1)) + (float)pos[2 * (int64_t)n + pj] * inv;
+        __syncthreads();
+        // own particles of the cells [z0*64, z1*64): a contiguous range
+        const uint32_t q0 = cst[z0 * 64], q1 = cst[z1 * 64];
+        for (uint32_t lp = q0 + tid; lp < q1; lp += kPPBlock) {
+            const int u = seg_search(cst, kTileCells, lp);
+            const uint32_t p = p0 + lp;
+            const int bx = (u & 7) + 1, by = ((u >> 3) & 7) + 1, bz = (u >> 6) + 1;
+            const float xi = (float)(2 * (bx - 1)) + (float)pos[p] * inv;
+            const float yi = (float)(2 * (by - 1)) + (float)pos[(int64_t)n + p] * inv;
+            const float zi = (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv;
+            float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+            if (staged) {
+                // the three x-neighbours of a cell are consecutive box segments,
+                // so the 27 neighbour cells are 9 contiguous ranges of xs
+                for (int row = 0; row < 9; ++row) {
+                    const int oy = row % 3 - 1, oz = row / 3 - 1;
+                    const int sm = ((bz + oz) * kPB + (by + oy)) * kPB + bx;
+                    const uint32_t v0 = seg_pre[sm - 1] - vb, v1 = seg_pre[sm + 2] - vb;
+                    float fx = 0.f, fy = 0.f, fz = 0.f;
+                    uint32_t v = v0;
+                    for (; v + 1 < v1; v += 2) {
+                        const float4 qa = xs[v], qb = xs[v + 1];
+                        pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, rows, kinv, K, fx, fy, fz);
+                        pair_accumulate(qb.x - xi, qb.y - yi, qb.z - zi, rows, kinv, K, fx, fy, fz);
+                    }
+                    if (v < v1) {
+                        const float4 qa = xs[v];
+                        pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, rows, kinv, K, fx, fy, fz);
+                    }
+                    kahan_add(sx, cx, fx);
+                    kahan_add(sy, cy, fy);
+                    kahan_add(sz, cz, fz);
                 }
-                const float dx = xj - xi, dy = yj - yi, dz = zj - zi;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 > 0.0f && r2 < law.bf2) {
-                    const float g = pair_g(r2, law);
-                    fx += g * dx;
-                    fy += g * dy;
-                    fz += g * dz;
+            } else {
+                for (int nb = 0; nb < 27; ++nb) {
+                    const int ox = nb % 3 - 1, oy = (nb / 3) % 3 - 1, oz = nb / 9 - 1;
+                    const int s = ((bz + oz) * kPB + (by + oy)) * kPB + (bx + ox);
+                    const uint32_t v0 = seg_pre[s], v1 = seg_pre[s + 1];
+                    const float bxo = (float)(2 * (bx + ox - 1)), byo = (float)(2 * (by + oy - 1)),
+                                bzo = (float)(2 * (bz + oz - 1));
+                    float fx = 0.f, fy = 0.f, fz = 0.f;
+                    for (uint32_t v = v0; v < v1; ++v) {
+                        const uint32_t pj = seg_src[s] + (v - v0);
+                        const float xj = bxo + (float)pos[pj] * inv;
+                        const float yj = byo + (float)pos[(int64_t)n + pj] * inv;
+                        const float zj = bzo + (float)pos[2 * (int64_t)n + pj] * inv;
+                        pair_accumulate(xj - xi, yj - yi, zj - zi, rows, kinv, K, fx, fy, fz);
+                    }
+                    kahan_add(sx, cx, fx);
+                    kahan_add(sy, cy, fy);
+                    kahan_add(sz, cz, fz);
                 }
             }
-            kahan_add(sx, cx, fx);
-            kahan_add(sy, cy, fy);
-            kahan_add(sz, cz, fz);
-        }
-        const float a[3] = {gm * sx, gm * sy, gm * sz};
+            const float a[3] = {gm * sx, gm * sy, gm * sz};
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            float *dst = acc + (int64_t)d * n + p;
-            *dst = accumulate ? *dst + a[d] : a[d];
+            for (int d = 0; d < 3; ++d) {
+                float *dst = acc + (int64_t)d * n + p;
+                *dst = accumulate ? *dst + a[d] : a[d];
+            }
         }
     }
 }
 
 }  // namespace
 
+namespace {
+
+// Q(y) = P(alpha + beta y) for a degree-8 polynomial (coefficients low to high).
+void compose(const double P[9], double alpha, double beta, double Q[9]) {
+    double q[9] = {P[8], 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int m = 7; m >= 0; --m) {
+        double t[9];
+        for (int j = 0; j < 9; ++j) t[j] = alpha * q[j] + (j > 0 ? beta * q[j - 1] : 0.0);
+        t[0] += P[m];
+        for (int j = 0; j < 9; ++j) q[j] = t[j];
+    }
+    for (int j = 0; j < 9; ++j) Q[j] = q[j];
+}
+
+}  // namespace
+
+// The pair-law table (see the comment above pair_accumulate), in FP64.
+void build_pair_table(cube2_ctx *ctx) {
+    static const double a[6] = {64.0 / 5, 0.0, -256.0 / 5, 32.0, 1536.0 / 35, -192.0 / 5};
+    static const double c[6] = {256.0 / 5, -96.0, 256.0 / 5, 32.0, -1536.0 / 35, 64.0 / 5};
+    const double bpp = ctx->cfg.b_pp, bf = ctx->cfg.b_fine;
+    // smallest K with b_pp/2, b_pp and b_f/2 on interval edges
+    int K = kPairKMax;
+    for (int k = 1; k <= kPairKMax; ++k) {
+        const double w = bf / k;
+        bool ok = true;
+        for (double b : {bpp / 2, bpp, bf / 2}) {
+            const double q = b / w;
+            if (std::fabs(q - std::nearbyint(q)) > 1e-9 * std::max(1.0, q)) ok = false;
+        }
+        if (ok) { K = k; break; }
+    }
+    const double w = bf / K;
+    ctx->pp_K = K;
+    ctx->pp_kinv = (float)(K / bf);
+    ctx->pp_rows.assign((size_t)(K + 1) * kPairRow, 0.0f);
+    for (int k = 0; k < K; ++k) {
+        const double mid = (k + 0.5) * w, rl = k * w, rr = (k + 1) * w;
+        const int pb = mid < bpp / 2 ? 0 : (mid < bpp ? 1 : 2);  // in, out, Newtonian
+        const int fb = mid < bf / 2 ? 0 : 1;                      // in, out
+        double P[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Q[9];
+        double ya, yb;
+        if (pb == 2 && fb == 1) {
+            // r^3 g = s^5 Q(1-s) = s^5 (1344/35 - 2912/35 s + 2048/35 s^2 - 64/5 s^3),
+            // s = (b_f - r)/b_f = (b_f - rr)/b_f + (w/b_f) y, y = 1 - fract
+            P[5] = 1344.0 / 35;
+            P[6] = -2912.0 / 35;
+            P[7] = 2048.0 / 35;
+            P[8] = -64.0 / 5;
+            compose(P, (bf - rr) / bf, w / bf, Q);
+            ya = 1.0;
+            yb = -1.0;
+        } else {
+            auto add = [&](int br, double b, double sg) {
+                if (br == 0) {
+                    for (int i = 0; i < 6; ++i) P[i + 3] += sg * a[i] * std::pow(b, -3 - i);
+                } else if (br == 1) {
+                    P[0] += sg * 3.0 / 35;
+                    P[2] += sg * (-32.0 / 5) / (b * b);
+                    for (int i = 0; i < 6; ++i) P[i + 3] += sg * c[i] * std::pow(b, -3 - i);
+                } else {
+                    P[0] += sg;
+                }
+            };
+            add(pb, bpp, 1.0);
+            add(fb, bf, -1.0);
+            compose(P, rl, w, Q);  // r = rl + w y, y = fract
+            ya = 0.0;
+            yb = 1.0;
+        }
+        float *row = &ctx->pp_rows[(size_t)k * kPairRow];
+        for (int j = 0; j < 9; ++j) row[j] = (float)Q[j];
+        row[9] = (float)ya;
+        row[10] = (float)yb;
+    }
+}
+
 int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, float *acc,
               int accumulate, hipStream_t s) {
-    const double bpp = ctx->cfg.b_pp, bf = ctx->cfg.b_fine;
-    PairLaw law;
-    law.bpp = (float)bpp;
-    law.ibpp = (float)(1.0 / bpp);
-    law.ibpp3 = (float)(1.0 / (bpp * bpp * bpp));
-    law.bf = (float)bf;
-    law.ibf = (float)(1.0 / bf);
-    law.ibf3 = (float)(1.0 / (bf * bf * bf));
-    law.bf2 = (float)(bf * bf);
+    const float4 *table = reinterpret_cast<const float4 *>(ctx->tables + ctx->pp_off);
     const int nt = ctx->nt;
-    pp_kernel<<<(unsigned)(nt * nt * nt), kBlock, 0, s>>>(
-        pos, cs, (int)n, nt, law, (float)(ctx->cfg.g_newton * ctx->cfg.m_p), acc, accumulate);
+    pp_kernel<<<(unsigned)(nt * nt * nt), kPPBlock, 0, s>>>(
+        pos, cs, (int)n, nt, table, ctx->pp_K, ctx->pp_kinv,
+        (float)(ctx->cfg.g_newton * ctx->cfg.m_p), acc, accumulate);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }
