@@ -11,8 +11,7 @@
 // grad W of the CIC weights is piecewise constant: (1/H) (+-1) times the two
 // other weights (left-continuous at cell faces).
 //
-// PP: a_k = G m sum_j g(r) D_kj with D_kj = x_j - x_k gives
-//   xbar_k = G m sum_j J(D_kj) (abar_j - abar_k),  J = g I + g' D D^T / r.
+// The PP adjoint lives with the PP kernel (pp.hip).
 #include "common.hpp"
 
 namespace cube2 {
@@ -340,167 +339,6 @@ __global__ __launch_bounds__(kBlock) void xbar_gather_kernel(
     }
 }
 
-// ---------------------------------------------------------------------------
-// PP adjoint
-// ---------------------------------------------------------------------------
-
-constexpr int kPB = kTileIos + 2;
-constexpr int kPSegs = kPB * kPB * kPB;
-constexpr int kPSegPerThread = (kPSegs + kBlock - 1) / kBlock;
-constexpr int kCap = 2048;
-
-struct PairLaw {
-    float bpp, ibpp, ibpp3, ibpp4;
-    float bf, ibf, ibf3, ibf4, bf2;
-};
-
-// F(t) and F'(t) with R(r,b)/r = b^-3 F(r/b) (see pp.hip)
-__device__ __forceinline__ void f_and_df(float t, float tinv, int branch, float &F, float &dF) {
-    if (branch == 0) {
-        const float t2 = t * t;
-        F = 64.0f / 5.0f + t2 * (-256.0f / 5.0f + t * (32.0f + t * (1536.0f / 35.0f + t * (-192.0f / 5.0f))));
-        dF = t * (-512.0f / 5.0f + t * (96.0f + t * (6144.0f / 35.0f + t * (-192.0f))));
-    } else if (branch == 1) {
-        const float ti2 = tinv * tinv;
-        F = 256.0f / 5.0f + t * (-96.0f + t * (256.0f / 5.0f + t * (32.0f + t * (-1536.0f / 35.0f + t * (64.0f / 5.0f))))) +
-            tinv * (-32.0f / 5.0f + ti2 * (3.0f / 35.0f));
-        dF = -96.0f + t * (512.0f / 5.0f + t * (96.0f + t * (-6144.0f / 35.0f + t * 64.0f))) +
-             ti2 * (32.0f / 5.0f + ti2 * (-9.0f / 35.0f));
-    } else {
-        const float ti2 = tinv * tinv;
-        F = ti2 * tinv;
-        dF = -3.0f * ti2 * ti2;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void pp_adjoint_kernel(
-    const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs,
-    const float *__restrict__ abar, int n, int nt, PairLaw law, float gm,
-    float *__restrict__ xbar, int accumulate) {
-    __shared__ uint32_t seg_pre[kPSegs + 1];
-    __shared__ uint32_t seg_src[kPSegs];
-    __shared__ float4 xs[kCap];
-    __shared__ float4 as[kCap];
-    __shared__ uint32_t scan_sh[kBlock / 64 + 1];
-    int tx, ty, tz;
-    tile_of_block(blockIdx.x, nt, tx, ty, tz);
-    const int tid = threadIdx.x;
-    const int n_ios = nt * kTileIos;
-    const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
-    uint32_t cnt[kPSegPerThread], src[kPSegPerThread], sum = 0;
-#pragma unroll
-    for (int k = 0; k < kPSegPerThread; ++k) {
-        const int s = tid * kPSegPerThread + k;
-        cnt[k] = 0;
-        src[k] = 0;
-        if (s < kPSegs) {
-            const int bx = s % kPB, by = (s / kPB) % kPB, bz = s / (kPB * kPB);
-            const uint32_t key = cell_key(wrapn(c0x + bx - 1, n_ios), wrapn(c0y + by - 1, n_ios),
-                                          wrapn(c0z + bz - 1, n_ios), nt);
-            src[k] = cs[key];
-            cnt[k] = cs[key + 1] - src[k];
-        }
-        sum += cnt[k];
-    }
-    uint32_t total;
-    uint32_t pre = block_exclusive_scan(sum, scan_sh, total);
-#pragma unroll
-    for (int k = 0; k < kPSegPerThread; ++k) {
-        const int s = tid * kPSegPerThread + k;
-        if (s < kPSegs) {
-            seg_pre[s] = pre;
-            seg_src[s] = src[k];
-        }
-        pre += cnt[k];
-    }
-    if (tid == 0) seg_pre[kPSegs] = total;
-    __syncthreads();
-    const bool staged = total <= (uint32_t)kCap;
-    const float inv = 1.0f / 32768.0f;
-    if (staged)
-        for (uint32_t v = tid; v < total; v += kBlock) {
-            const int s = seg_search(seg_pre, kPSegs, v);
-            const uint32_t p = seg_src[s] + (v - seg_pre[s]);
-            const int bx = s % kPB, by = (s / kPB) % kPB, bz = s / (kPB * kPB);
-            xs[v] = make_float4((float)(2 * (bx - 1)) + (float)pos[p] * inv,
-                                (float)(2 * (by - 1)) + (float)pos[(int64_t)n + p] * inv,
-                                (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv, 0.f);
-            as[v] = make_float4(abar[p], abar[(int64_t)n + p], abar[2 * (int64_t)n + p], 0.f);
-        }
-    __syncthreads();
-    const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
-    const uint32_t p0 = cs[key0], p1 = cs[key0 + kTileCells];
-    for (uint32_t p = p0 + tid; p < p1; p += kBlock) {
-        int lo = 0, hi = kTileCells;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (cs[key0 + mid] <= p) lo = mid; else hi = mid;
-        }
-        const int bx = (lo & 7) + 1, by = ((lo >> 3) & 7) + 1, bz = (lo >> 6) + 1;
-        const float xi = (float)(2 * (bx - 1)) + (float)pos[p] * inv;
-        const float yi = (float)(2 * (by - 1)) + (float)pos[(int64_t)n + p] * inv;
-        const float zi = (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv;
-        const float akx = abar[p], aky = abar[(int64_t)n + p], akz = abar[2 * (int64_t)n + p];
-        float sx = 0.f, sy = 0.f, sz = 0.f;
-        for (int nb = 0; nb < 27; ++nb) {
-            const int ox = nb % 3 - 1, oy = (nb / 3) % 3 - 1, oz = nb / 9 - 1;
-            const int s = ((bz + oz) * kPB + (by + oy)) * kPB + (bx + ox);
-            const uint32_t v0 = seg_pre[s], v1 = seg_pre[s + 1];
-            for (uint32_t v = v0; v < v1; ++v) {
-                float xj, yj, zj, ajx, ajy, ajz;
-                if (staged) {
-                    const float4 q = xs[v], a = as[v];
-                    xj = q.x; yj = q.y; zj = q.z;
-                    ajx = a.x; ajy = a.y; ajz = a.z;
-                } else {
-                    const uint32_t pj = seg_src[s] + (v - v0);
-                    xj = (float)(2 * (bx + ox - 1)) + (float)pos[pj] * inv;
-                    yj = (float)(2 * (by + oy - 1)) + (float)pos[(int64_t)n + pj] * inv;
-                    zj = (float)(2 * (bz + oz - 1)) + (float)pos[2 * (int64_t)n + pj] * inv;
-                    ajx = abar[pj];
-                    ajy = abar[(int64_t)n + pj];
-                    ajz = abar[2 * (int64_t)n + pj];
-                }
-                const float dx = xj - xi, dy = yj - yi, dz = zj - zi;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 > 0.0f && r2 < law.bf2) {
-                    const float rinv = __frsqrt_rn(r2), r = r2 * rinv;
-                    const float tf = r * law.ibf;
-                    const float tp = r * law.ibpp;
-                    float g, dg;
-                    if (tp >= 1.0f && tf >= 0.5f) {
-                        // factored tail (see pp.hip): G(t) = (1-t)^5 Q(t) / t^3,
-                        // G'(t) = (1-t)^4 [-5 t Q + (1-t)(t Q' - 3 Q)] / t^4
-                        const float s = 1.0f - tf, s2 = s * s, tinv = law.bf * rinv;
-                        const float Q = 32.0f / 35.0f + tf * (32.0f / 7.0f + tf * (704.0f / 35.0f + tf * (64.0f / 5.0f)));
-                        const float dQ = 32.0f / 7.0f + tf * (1408.0f / 35.0f + tf * (192.0f / 5.0f));
-                        const float ti3 = tinv * tinv * tinv;
-                        g = law.ibf3 * s2 * s2 * s * Q * ti3;
-                        dg = law.ibf4 * s2 * s2 * (-5.0f * tf * Q + s * (tf * dQ - 3.0f * Q)) * ti3 * tinv;
-                    } else {
-                        float Ff, dFf, Fp, dFp;
-                        f_and_df(tf, law.bf * rinv, tf < 0.5f ? 0 : 1, Ff, dFf);
-                        f_and_df(tp, law.bpp * rinv, tp < 0.5f ? 0 : (tp < 1.0f ? 1 : 2), Fp, dFp);
-                        g = Fp * law.ibpp3 - Ff * law.ibf3;
-                        dg = dFp * law.ibpp4 - dFf * law.ibf4;
-                    }
-                    const float ux = ajx - akx, uy = ajy - aky, uz = ajz - akz;
-                    const float du = (dx * ux + dy * uy + dz * uz) * dg * rinv;
-                    sx += g * ux + du * dx;
-                    sy += g * uy + du * dy;
-                    sz += g * uz + du * dz;
-                }
-            }
-        }
-        const float xb[3] = {gm * sx, gm * sy, gm * sz};
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            float *dst = xbar + (int64_t)d * n + p;
-            *dst = accumulate ? *dst + xb[d] : xb[d];
-        }
-    }
-}
-
 }  // namespace
 
 int launch_deposit_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
@@ -572,27 +410,6 @@ int launch_pm_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, 
             pos, cs, acc_bar, (int)n, ctx->n_f, nt, rf, bf, (float)gm, nullptr, nullptr, 0.f, 1, 0,
             x_bar, accumulate);
     }
-    CUBE2_LAUNCH_CHECK();
-    return CUBE2_OK;
-}
-
-int launch_pp_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
-                       const float *acc_bar, float *x_bar, int accumulate, hipStream_t s) {
-    const double bpp = ctx->cfg.b_pp, bf = ctx->cfg.b_fine;
-    PairLaw law;
-    law.bpp = (float)bpp;
-    law.ibpp = (float)(1.0 / bpp);
-    law.ibpp3 = (float)(1.0 / (bpp * bpp * bpp));
-    law.ibpp4 = (float)(1.0 / (bpp * bpp * bpp * bpp));
-    law.bf = (float)bf;
-    law.ibf = (float)(1.0 / bf);
-    law.ibf3 = (float)(1.0 / (bf * bf * bf));
-    law.ibf4 = (float)(1.0 / (bf * bf * bf * bf));
-    law.bf2 = (float)(bf * bf);
-    const int nt = ctx->nt;
-    pp_adjoint_kernel<<<(unsigned)(nt * nt * nt), kBlock, 0, s>>>(
-        pos, cs, acc_bar, (int)n, nt, law, (float)(ctx->cfg.g_newton * ctx->cfg.m_p), x_bar,
-        accumulate);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }

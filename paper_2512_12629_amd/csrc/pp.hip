@@ -79,19 +79,55 @@ __device__ __forceinline__ void pair_accumulate(float dx, float dy, float dz, co
     fz += g * dz;
 }
 
+// Adjoint of one pair for the cotangents: out += J(D) u with u = abar_j -
+// abar_i and J = g I + g' D D^T / r.  g' = r^-3 (y_b K/b_f dU/dy - 3 U / r)
+// with U and dU/dy from the same table row (Horner with derivative).
+__device__ __forceinline__ void pair_adjoint(float dx, float dy, float dz, float ux, float uy,
+                                             float uz, const float4 *rows, float kinv, int K,
+                                             float &ox, float &oy, float &oz) {
+    const float r2 = fmaxf(dx * dx + dy * dy + dz * dz, 1e-12f);
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * rinv;
+    const float f = r * kinv;
+    const int idx = min((int)f, K);
+    const float4 c0 = rows[3 * idx], c1 = rows[3 * idx + 1], c2 = rows[3 * idx + 2];
+    const float y = c2.y + c2.z * __builtin_amdgcn_fractf(f);
+    const float cf[9] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w, c2.x};
+    float U = cf[8], dU = 0.0f;
+#pragma unroll
+    for (int j = 7; j >= 0; --j) {
+        dU = dU * y + U;
+        U = U * y + cf[j];
+    }
+    const float ri3 = rinv * rinv * rinv;
+    const float g = U * ri3;
+    const float gp = ri3 * (c2.z * kinv * dU - 3.0f * U * rinv);
+    const float du = (dx * ux + dy * uy + dz * uz) * gp * rinv;
+    ox += g * ux + du * dx;
+    oy += g * uy + du * dy;
+    oz += g * uz + du * dz;
+}
+
 // Heavy tiles are done in z-chunks: own cells are ordered z-major, so the own
 // cells of z-layers [z0, z1) are a contiguous particle range and the box cells
 // they need are the contiguous box layers [z0, z1 + 2), a contiguous slice of
 // the staged list.
 
+// ADJ = false: acc = G m sum_j g D (forward).  ADJ = true: out = G m sum_j
+// J(D) (abar_j - abar_i) for the cotangent abar (the adjoint), which stages
+// abar_j beside x_j and so holds half as many particles per chunk.
+template <bool ADJ>
 __global__ __launch_bounds__(kPPBlock) void pp_kernel(const uint16_t *__restrict__ pos,
                                                      const uint32_t *__restrict__ cs, int n,
                                                      int nt, const float4 *__restrict__ table,
                                                      int K, float kinv, float gm,
+                                                     const float *__restrict__ abar,
                                                      float *__restrict__ acc, int accumulate) {
+    constexpr int CAP = ADJ ? kCap / 2 : kCap;
     __shared__ uint32_t seg_pre[kPSegs + 1];
     __shared__ uint32_t seg_src[kPSegs];
-    __shared__ float4 xs[kCap];
+    __shared__ float4 xs[CAP];
+    __shared__ float4 as_[ADJ ? CAP : 1];
     __shared__ float4 rows[3 * (kPairKMax + 1)];
     __shared__ uint32_t cst[kTileCells + 1];     // own cells: particle starts (tile-relative)
     __shared__ uint32_t scan_sh[kPPBlock / 64 + 1];
@@ -144,7 +180,7 @@ __global__ __launch_bounds__(kPPBlock) void pp_kernel(const uint16_t *__restrict
             bool fits = true;
             for (int c = 0; c < C; ++c) {
                 const int z0 = c * 8 / C, z1 = (c + 1) * 8 / C;
-                if (seg_pre[(z1 + 2) * kPB * kPB] - seg_pre[z0 * kPB * kPB] > (uint32_t)kCap)
+                if (seg_pre[(z1 + 2) * kPB * kPB] - seg_pre[z0 * kPB * kPB] > (uint32_t)CAP)
                     fits = false;
             }
             if (fits) break;
@@ -158,7 +194,7 @@ __global__ __launch_bounds__(kPPBlock) void pp_kernel(const uint16_t *__restrict
     for (int c = 0; c < C; ++c) {
         const int z0 = c * 8 / C, z1 = (c + 1) * 8 / C;
         const uint32_t vb = seg_pre[z0 * kPB * kPB], ve = seg_pre[(z1 + 2) * kPB * kPB];
-        const bool staged = ve - vb <= (uint32_t)kCap;
+        const bool staged = ve - vb <= (uint32_t)CAP;
         if (c > 0) __syncthreads();  // previous chunk done with xs
         if (staged) {
             for (uint32_t v = vb + tid; v < ve; v += kPPBlock) {
@@ -171,6 +207,8 @@ __global__ __launch_bounds__(kPPBlock) void pp_kernel(const uint16_t *__restrict
                 q.z = (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv;
                 q.w = 0.0f;
                 xs[v - vb] = q;
+                if (ADJ)
+                    as_[v - vb] = make_float4(abar[p], abar[(int64_t)n + p], abar[2 * (int64_t)n + p], 0.f);
             }
         }
         __syncthreads();
@@ -183,6 +221,12 @@ __global__ __launch_bounds__(kPPBlock) void pp_kernel(const uint16_t *__restrict
             const float xi = (float)(2 * (bx - 1)) + (float)pos[p] * inv;
             const float yi = (float)(2 * (by - 1)) + (float)pos[(int64_t)n + p] * inv;
             const float zi = (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv;
+            float aix = 0.f, aiy = 0.f, aiz = 0.f;
+            if (ADJ) {
+                aix = abar[p];
+                aiy = abar[(int64_t)n + p];
+                aiz = abar[2 * (int64_t)n + p];
+            }
             float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
             if (staged) {
                 // the three x-neighbours of a cell are consecutive box segments,
@@ -193,14 +237,22 @@ __global__ __launch_bounds__(kPPBlock) void pp_kernel(const uint16_t *__restrict
                     const uint32_t v0 = seg_pre[sm - 1] - vb, v1 = seg_pre[sm + 2] - vb;
                     float fx = 0.f, fy = 0.f, fz = 0.f;
                     uint32_t v = v0;
-                    for (; v + 1 < v1; v += 2) {
-                        const float4 qa = xs[v], qb = xs[v + 1];
-                        pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, rows, kinv, K, fx, fy, fz);
-                        pair_accumulate(qb.x - xi, qb.y - yi, qb.z - zi, rows, kinv, K, fx, fy, fz);
-                    }
-                    if (v < v1) {
-                        const float4 qa = xs[v];
-                        pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, rows, kinv, K, fx, fy, fz);
+                    if (ADJ) {
+                        for (; v < v1; ++v) {
+                            const float4 qa = xs[v], aa = as_[v];
+                            pair_adjoint(qa.x - xi, qa.y - yi, qa.z - zi, aa.x - aix, aa.y - aiy,
+                                         aa.z - aiz, rows, kinv, K, fx, fy, fz);
+                        }
+                    } else {
+                        for (; v + 1 < v1; v += 2) {
+                            const float4 qa = xs[v], qb = xs[v + 1];
+                            pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, rows, kinv, K, fx, fy, fz);
+                            pair_accumulate(qb.x - xi, qb.y - yi, qb.z - zi, rows, kinv, K, fx, fy, fz);
+                        }
+                        if (v < v1) {
+                            const float4 qa = xs[v];
+                            pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, rows, kinv, K, fx, fy, fz);
+                        }
                     }
                     kahan_add(sx, cx, fx);
                     kahan_add(sy, cy, fy);
@@ -219,7 +271,12 @@ __global__ __launch_bounds__(kPPBlock) void pp_kernel(const uint16_t *__restrict
                         const float xj = bxo + (float)pos[pj] * inv;
                         const float yj = byo + (float)pos[(int64_t)n + pj] * inv;
                         const float zj = bzo + (float)pos[2 * (int64_t)n + pj] * inv;
-                        pair_accumulate(xj - xi, yj - yi, zj - zi, rows, kinv, K, fx, fy, fz);
+                        if (ADJ)
+                            pair_adjoint(xj - xi, yj - yi, zj - zi, abar[pj] - aix,
+                                         abar[(int64_t)n + pj] - aiy, abar[2 * (int64_t)n + pj] - aiz,
+                                         rows, kinv, K, fx, fy, fz);
+                        else
+                            pair_accumulate(xj - xi, yj - yi, zj - zi, rows, kinv, K, fx, fy, fz);
                     }
                     kahan_add(sx, cx, fx);
                     kahan_add(sy, cy, fy);
@@ -319,9 +376,20 @@ int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n
               int accumulate, hipStream_t s) {
     const float4 *table = reinterpret_cast<const float4 *>(ctx->tables + ctx->pp_off);
     const int nt = ctx->nt;
-    pp_kernel<<<(unsigned)(nt * nt * nt), kPPBlock, 0, s>>>(
+    pp_kernel<false><<<(unsigned)(nt * nt * nt), kPPBlock, 0, s>>>(
         pos, cs, (int)n, nt, table, ctx->pp_K, ctx->pp_kinv,
-        (float)(ctx->cfg.g_newton * ctx->cfg.m_p), acc, accumulate);
+        (float)(ctx->cfg.g_newton * ctx->cfg.m_p), nullptr, acc, accumulate);
+    CUBE2_LAUNCH_CHECK();
+    return CUBE2_OK;
+}
+
+int launch_pp_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                       const float *acc_bar, float *x_bar, int accumulate, hipStream_t s) {
+    const float4 *table = reinterpret_cast<const float4 *>(ctx->tables + ctx->pp_off);
+    const int nt = ctx->nt;
+    pp_kernel<true><<<(unsigned)(nt * nt * nt), kPPBlock, 0, s>>>(
+        pos, cs, (int)n, nt, table, ctx->pp_K, ctx->pp_kinv,
+        (float)(ctx->cfg.g_newton * ctx->cfg.m_p), acc_bar, x_bar, accumulate);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }
