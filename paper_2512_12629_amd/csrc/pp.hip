@@ -25,9 +25,14 @@ namespace {
 
 constexpr int kPB = kTileIos + 2;          // 10 IOS cells per axis
 constexpr int kPSegs = kPB * kPB * kPB;    // 1000
-constexpr int kPPBlock = 512;              // 8 waves: 4 per SIMD at 2 blocks per CU
-constexpr int kPSegPerThread = (kPSegs + kPPBlock - 1) / kPPBlock;  // 2
-constexpr int kCap = 3840;                 // staged particles (60 KB)
+// Forward: 512 threads, 3840 staged particles (60 KB): 2 blocks (4 waves per
+// SIMD) per CU.  Adjoint: the cotangent is staged too, so it runs 1024-thread
+// blocks with 4096 staged particles (128 KB): 1 block (4 waves per SIMD).
+template <bool ADJ> struct PPGeo {
+    static constexpr int BLOCK = ADJ ? 1024 : 512;
+    static constexpr int CAP = ADJ ? 4096 : 3840;
+    static constexpr int SEG_PER_THREAD = (kPSegs + BLOCK - 1) / BLOCK;
+};
 
 }  // namespace
 
@@ -117,13 +122,15 @@ __device__ __forceinline__ void pair_adjoint(float dx, float dy, float dz, float
 // J(D) (abar_j - abar_i) for the cotangent abar (the adjoint), which stages
 // abar_j beside x_j and so holds half as many particles per chunk.
 template <bool ADJ>
-__global__ __launch_bounds__(kPPBlock) void pp_kernel(const uint16_t *__restrict__ pos,
+__global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *__restrict__ pos,
                                                      const uint32_t *__restrict__ cs, int n,
                                                      int nt, const float4 *__restrict__ table,
                                                      int K, float kinv, float gm,
                                                      const float *__restrict__ abar,
                                                      float *__restrict__ acc, int accumulate) {
-    constexpr int CAP = ADJ ? kCap / 2 : kCap;
+    constexpr int CAP = PPGeo<ADJ>::CAP;
+    constexpr int kPPBlock = PPGeo<ADJ>::BLOCK;
+    constexpr int kPSegPerThread = PPGeo<ADJ>::SEG_PER_THREAD;
     __shared__ uint32_t seg_pre[kPSegs + 1];
     __shared__ uint32_t seg_src[kPSegs];
     __shared__ float4 xs[CAP];
@@ -170,7 +177,7 @@ __global__ __launch_bounds__(kPPBlock) void pp_kernel(const uint16_t *__restrict
     // own cells: particle starts relative to the tile's first particle
     const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
     const uint32_t p0 = cs[key0];
-    cst[tid] = cs[key0 + tid] - p0;
+    if (tid < kTileCells) cst[tid] = cs[key0 + tid] - p0;
     if (tid == 0) {
         seg_pre[kPSegs] = total;
         cst[kTileCells] = cs[key0 + kTileCells] - p0;
@@ -376,7 +383,7 @@ int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n
               int accumulate, hipStream_t s) {
     const float4 *table = reinterpret_cast<const float4 *>(ctx->tables + ctx->pp_off);
     const int nt = ctx->nt;
-    pp_kernel<false><<<(unsigned)(nt * nt * nt), kPPBlock, 0, s>>>(
+    pp_kernel<false><<<(unsigned)(nt * nt * nt), PPGeo<false>::BLOCK, 0, s>>>(
         pos, cs, (int)n, nt, table, ctx->pp_K, ctx->pp_kinv,
         (float)(ctx->cfg.g_newton * ctx->cfg.m_p), nullptr, acc, accumulate);
     CUBE2_LAUNCH_CHECK();
@@ -387,7 +394,7 @@ int launch_pp_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, 
                        const float *acc_bar, float *x_bar, int accumulate, hipStream_t s) {
     const float4 *table = reinterpret_cast<const float4 *>(ctx->tables + ctx->pp_off);
     const int nt = ctx->nt;
-    pp_kernel<true><<<(unsigned)(nt * nt * nt), kPPBlock, 0, s>>>(
+    pp_kernel<true><<<(unsigned)(nt * nt * nt), PPGeo<true>::BLOCK, 0, s>>>(
         pos, cs, (int)n, nt, table, ctx->pp_K, ctx->pp_kinv,
         (float)(ctx->cfg.g_newton * ctx->cfg.m_p), acc_bar, x_bar, accumulate);
     CUBE2_LAUNCH_CHECK();
