@@ -42,10 +42,11 @@ WORKLOADS = {
                    desc="128^3 particles, Zel'dovich k^-2; single-level 256^3 mesh"),
 }
 
-# Algorithmic FP32 flops (FMA = 2) of one in-cutoff PP pair as the pair law
-# is written: 3 differences, r^2 (5), rsqrt (1), r and t (2), the fine
-# polynomial branch (12), scale (1), r^-3 (2), difference (1), 3 FMA (6).
-PP_FLOPS_PER_PAIR = 33
+# Algorithmic FP32 flops (FMA = 2) of one in-cutoff PP pair, counted from
+# the arithmetic of the compiled inner loop: 3 differences, r^2 (5), clamp,
+# rsqrt, r, r K/b_f, fract (5), the local variable (2), 8 Horner FMA (16),
+# r^-3 (2), g (1), 3 accumulating FMA (6).
+PP_FLOPS_PER_PAIR = 40
 
 
 def pair_counts():
