@@ -497,3 +497,60 @@ def reference_accel(xf: np.ndarray, params: Params) -> np.ndarray:
                 rr = r[i, j]
                 acc[:, i] += (refforce(rr, params.b_pp) - 1.0 / rr ** 2) * D[:, i, j] / rr
     return acc * (params.G_N * params.m_p)
+
+
+# ---------------------------------------------------------------------------
+# Multi-step leapfrog and its gradient (continuous FP64 positions)
+# ---------------------------------------------------------------------------
+
+def leapfrog_states(o: "Oracle", x0f: np.ndarray, v0: np.ndarray, kick: float, drift: float,
+                    steps: int):
+    """States of `steps` kick-drift steps: x_{k+1} = x_k + drift v_{k+1},
+    v_{k+1} = v_k + kick a(x_k); positions wrap into [0, n_fine)."""
+    L = float(o.p.n_fine)
+    xs, vs = [np.array(x0f, dtype=np.float64)], [np.array(v0, dtype=np.float64)]
+    for _ in range(steps):
+        a = o.accel(xs[-1])
+        v = vs[-1] + kick * a
+        xs.append(np.mod(xs[-1] + drift * v, L))
+        vs.append(v)
+    return xs, vs
+
+
+def leapfrog_loss(o: "Oracle", x0f, v0, kick, drift, steps, rho_target):
+    """Loss sum (rho_final - rho_target)^2 on the finest level, unit masses."""
+    xs, _ = leapfrog_states(o, x0f, v0, kick, drift, steps)
+    H, n, _, _ = o.p.levels()[-1]
+    rho = deposit(xs[-1], n, H, o.quant)
+    return float(np.sum((rho - rho_target) ** 2))
+
+
+def leapfrog_loss_grad(o: "Oracle", x0f, v0, kick, drift, steps, rho_target):
+    """(loss, d loss/d x0, d loss/d v0) by reverse mode through the steps:
+    given (xbar, vbar) after step k+1:  vbar += drift * xbar,
+    xbar_k = xbar + (da/dx)^T (kick * vbar), vbar_k = vbar."""
+    xs, vs = leapfrog_states(o, x0f, v0, kick, drift, steps)
+    H, n, _, _ = o.p.levels()[-1]
+    rho = deposit(xs[-1], n, H, o.quant)
+    loss = float(np.sum((rho - rho_target) ** 2))
+    rhobar = 2.0 * (rho - rho_target)
+    xbar = o.deposit_adjoint(xs[-1], rhobar)
+    vbar = np.zeros_like(xbar)
+    for k in range(steps - 1, -1, -1):
+        vbar = vbar + drift * xbar
+        xbar = xbar + o.accel_adjoint(xs[k], kick * vbar)
+    return loss, xbar, vbar
+
+
+def leapfrog_grad_on_states(o: "Oracle", xs, kick: float, drift: float, rho_target):
+    """Reverse mode of the same loss along a given trajectory xs[0..K]
+    (positions in one consistent particle order, fine cells); the map is
+    linear in the velocities, so only positions are needed."""
+    H, n, _, _ = o.p.levels()[-1]
+    rho = deposit(xs[-1], n, H, o.quant)
+    xbar = o.deposit_adjoint(xs[-1], 2.0 * (rho - rho_target))
+    vbar = np.zeros_like(xbar)
+    for k in range(len(xs) - 2, -1, -1):
+        vbar = vbar + drift * xbar
+        xbar = xbar + o.accel_adjoint(xs[k], kick * vbar)
+    return xbar, vbar

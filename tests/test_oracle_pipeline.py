@@ -315,3 +315,23 @@ def test_ios_order_is_a_stable_permutation():
     assert np.array_equal(np.diff(cs.astype(np.int64)), np.bincount(key, minlength=len(cs) - 1))
     # offsets plus the cell of each particle give back its position
     assert np.array_equal(off.astype(np.int64), q[:, perm] & 0xFFFF)
+
+
+def test_multistep_gradient_matches_finite_differences():
+    # reverse mode through 4 kick-drift steps vs FP64 central differences
+    p = oracle.Params(n_fine=16)
+    o = oracle.Oracle(p, quant=False)
+    rng = np.random.default_rng(41)
+    x0 = rng.random((3, 60)) * 16
+    v0 = 0.1 * rng.standard_normal((3, 60))
+    rho_t = oracle.deposit(np.mod(x0 + rng.standard_normal(x0.shape) * 0.3, 16), 16, 1, quant=False)
+    kick = drift = 0.05
+    loss, gx, gv = oracle.leapfrog_loss_grad(o, x0, v0, kick, drift, 4, rho_t)
+    for _ in range(3):
+        dx = rng.standard_normal(x0.shape)
+        dv = rng.standard_normal(v0.shape)
+        h = 1e-6
+        lp = oracle.leapfrog_loss(o, x0 + h * dx, v0 + h * dv, kick, drift, 4, rho_t)
+        lm = oracle.leapfrog_loss(o, x0 - h * dx, v0 - h * dv, kick, drift, 4, rho_t)
+        fd = (lp - lm) / (2 * h)
+        assert np.sum(gx * dx) + np.sum(gv * dv) == pytest.approx(fd, rel=1e-5)
