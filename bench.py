@@ -49,12 +49,72 @@ WORKLOADS = {
 PP_FLOPS_PER_PAIR = 40
 
 
+# VALU instructions per candidate pair of the compiled forward PP inner loop
+# (gfx950 ISA: 63 per iteration of the two-pair unrolled loop), and the
+# unpacked FP32 VALU issue rate (lane-ops per second).
+PP_VALU_PER_PAIR = 31.5
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def step_reference_bytes(n_particles: int, meshes) -> float:
+    """HBM bytes of one force evaluation in the reference traffic model:
+    per level of n^3 cells, the density write (4 B/cell), five read+write
+    sweeps over the n^2 (n/2+1) half spectrum (8 B per complex value), one
+    read of the octant Green's table, one read of the potential (4 B/cell);
+    per particle, two sweeps over the IOS data (10 B each) and the 12 B
+    acceleration write."""
+    b = 32.0 * n_particles
+    for n in meshes:
+        h = n // 2 + 1
+        b += 4.0 * n ** 3 + 5 * 2 * 8.0 * h * n * n + 4.0 * h ** 3 + 4.0 * n ** 3
+    return b
+
+
 def pair_counts():
     path = os.path.join(ROOT, "tests", "golden", "pair_counts.json")
     if os.path.exists(path):
         with open(path) as f:
             return json.load(f)
     return {}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pp_kernel_clu512_traffic.txt")
+PP_SOURCES = [os.path.join(ROOT, "paper_2512_12629_amd", "csrc", "pp.hip")]
+
+
+def source_digest(paths) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per pp_kernel launch from the FETCH_SIZE / WRITE_SIZE counter
+    passes recorded in the traffic summary, each divided by what the same
+    counter reads per byte for a plain copy kernel of known size.  None when
+    the summary is absent, covers another workload, or was taken on another
+    version of the kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith(("#", " ", "|")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if kv.get("workload") != workload or kv.get("source_digest") != source_digest(PP_SOURCES):
+            return None
+        copy_bytes = float(kv["copy_bytes"])
+        f_scale = float(kv["copy_fetch_kib"]) * 1024.0 / copy_bytes
+        w_scale = float(kv["copy_write_kib"]) * 1024.0 / copy_bytes
+        return (float(kv["pp_fetch_kib"]) * 1024.0 / f_scale
+                + float(kv["pp_write_kib"]) * 1024.0 / w_scale)
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
 
 
 def fft_bytes_reference(n: int, pitch: int) -> float:
@@ -69,12 +129,9 @@ def fft_bytes_reference(n: int, pitch: int) -> float:
     return (real + spec) + 2 * spec + (2 * spec + h ** 3 * 4.0) + 2 * spec + (spec + real)
 
 
-def cpu_baseline(workload: str):
-    """Oracle (FP64, as is) on a bounded sample: the same recipe at 1/64 of
-    the volume (n_p = 128, same sphere density), full PM + PP force."""
+def _oracle_force_time(workload: str, scale: int):
     import oracle
     w = WORKLOADS[workload]
-    scale = 4 if workload == "clu512" else 2
     n_p = synthetic.WORKLOADS[workload]["n_p"] // scale
     n_f = w["n_fine"] // scale
     x = synthetic.make(workload, n_p=n_p)
@@ -82,26 +139,39 @@ def cpu_baseline(workload: str):
     o = oracle.Oracle(p)
     for lvl in range(len(p.levels())):
         o.green(lvl)                      # tables are built before the timing
-    q = oracle.quantize(x, n_f)
-    xf = oracle.q_to_fine(q)
+    xf = oracle.q_to_fine(oracle.quantize(x, n_f))
     t0 = time.perf_counter()
     o.accel(xf)
-    dt = time.perf_counter() - t0
+    return x.shape[1], n_f, time.perf_counter() - t0
+
+
+def cpu_baseline(workload: str):
+    """Oracle (FP64, as is) on a bounded sample: the same recipe (same sphere
+    density) at 1/64 of the volume, or at 1/8 when the host does the 1/64
+    sample in under 5 s, so that the timed CPU work is about 10-30 s."""
+    scale = 4 if workload == "clu512" else 2
+    n, n_f, dt = _oracle_force_time(workload, scale)
+    if dt < 5.0 and scale > 1:
+        scale //= 2
+        n, n_f, dt = _oracle_force_time(workload, scale)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": x.shape[1] / dt, "unit": "particles/s", "cores": threads, "kind": "oracle",
-            "sample": f"{workload} recipe at 1/{scale ** 3} volume: {x.shape[1]} particles, "
+    return {"value": n / dt, "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "sample": f"{workload} recipe at 1/{scale ** 3} volume: {n} particles, "
                       f"fine mesh {n_f}^3, full FP64 PM+PP force, {dt:.2f} s"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="clu512", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="time only the force step (for profiler runs)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the timing, run a plain copy kernel (y = -x) of this many MiB "
+                         "read + the same written, as the reference for HBM counter passes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -155,7 +225,7 @@ def main():
     print(f"[bench] force: {np.median(ts):.3f} ms median over {args.steps}", file=sys.stderr,
           flush=True)
     status = c.status()
-    ms = float(np.mean(ts))
+    ms = float(np.median(ts))
     out = {
         "metric": "particles/sec per full PM+PP force step",
         "value": N / (ms * 1e-3),
@@ -166,9 +236,10 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "description": w["desc"], "particles": N,
                    "n_fine": w["n_fine"], "coarse_ratio": w["coarse_ratio"]},
-        "force_ms_median": float(np.median(ts)),
+        "force_ms_mean": float(np.mean(ts)),
         "wall_s_timed": wall, "table_init_s": t_init, "status": status,
     }
+    pairs = None
     if not args.no_extras:
         # stages (each is one C-ABI entry point on the same stream)
         n_f, pitch_f = c.level_shape(0)
@@ -209,8 +280,7 @@ def main():
         out["stages_ms"] = stages
 
         # roofline of the dominant kernel
-        counts = pair_counts()
-        pairs = counts.get(args.workload)
+        pairs = pair_counts().get(args.workload)
         t_pp_s = stages["pp_force"] * 1e-3
         fft_bytes = fft_bytes_reference(n_f, pitch_f)
         t_fft_s = stages["potential_fine"] * 1e-3
@@ -218,13 +288,31 @@ def main():
             ach = pairs * PP_FLOPS_PER_PAIR / t_pp_s / 1e12
             out["roofline"] = {"kernel": "pp_kernel", "bound": "alu", "achieved": ach,
                                "peak": VALU_FP32_TFLOPS, "unit": "TFLOP/s",
-                               "frac": ach / VALU_FP32_TFLOPS, "traffic": None,
+                               "frac": ach / VALU_FP32_TFLOPS,
+                               "traffic": measured_traffic(args.workload),
                                "pairs": pairs, "flops_per_pair": PP_FLOPS_PER_PAIR}
         else:
             ach = fft_bytes / t_fft_s / 1e9
             out["roofline"] = {"kernel": "fine potential (5 FFT sweeps)", "bound": "hbm",
                                "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": ach / HBM_PEAK_GBS, "traffic": None}
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = src.numel() * 4
+        del src, dst
+    if not args.no_extras and pairs:
+        meshes = [w["n_fine"]] + ([w["n_fine"] // w["coarse_ratio"]] if w["coarse_ratio"] else [])
+        hbm = step_reference_bytes(N, meshes)
+        t_hbm = hbm / (HBM_PEAK_GBS * 1e9)
+        t_alu = pairs * PP_VALU_PER_PAIR / VALU_LANE_OPS
+        out["step_roofline"] = {
+            "t_roof_ms": (t_hbm + t_alu) * 1e3, "t_hbm_ms": t_hbm * 1e3, "t_pp_valu_ms": t_alu * 1e3,
+            "reference_bytes": hbm, "pp_valu_per_pair": PP_VALU_PER_PAIR,
+            "frac": (t_hbm + t_alu) * 1e3 / ms}
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(args.workload)

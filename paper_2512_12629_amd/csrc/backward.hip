@@ -277,17 +277,11 @@ __global__ __launch_bounds__(kBlock) void xbar_gather_kernel(
     const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
     for (int i = tid; i <= kTileCells; i += kBlock) cst[i] = cs[key0 + i];
     const int a0x = tx * kTileFine, a0y = ty * kTileFine, a0z = tz * kTileFine;
-    if (WITH_E)
-        for (int i = tid; i < kFS * kFS * kFS; i += kBlock) {
-            const int lx = i % kFS, ly = (i / kFS) % kFS, lz = i / (kFS * kFS);
-            pf[i] = phi_f[((int64_t)wrapn(a0z + lz - 2, n_f) * n_f + wrapn(a0y + ly - 2, n_f)) * n_f +
-                          wrapn(a0x + lx - 2, n_f)];
-        }
-    for (int i = tid; i < kRS * kRS * kRS; i += kBlock) {
-        const int lx = i % kRS, ly = (i / kRS) % kRS, lz = i / (kRS * kRS);
-        rf[i] = rb_f ? rb_f[((int64_t)wrapn(a0z + lz, n_f) * n_f + wrapn(a0y + ly, n_f)) * n_f +
-                            wrapn(a0x + lx, n_f)]
-                     : 0.0f;
+    if (WITH_E) stage_block<kFS, kBlock>(pf, phi_f, n_f, a0x - 2, a0y - 2, a0z - 2);
+    if (rb_f) {
+        stage_block<kRS, kBlock>(rf, rb_f, n_f, a0x, a0y, a0z);
+    } else {
+        for (int i = tid; i < kRS * kRS * kRS; i += kBlock) rf[i] = 0.0f;
     }
     const int CS = (kTileFine >> hshift) + 5, CR = (kTileFine >> hshift) + 1;
     if (TWO) {

@@ -34,6 +34,7 @@ struct Level {
     double b_prev = 0;  // truncation (fine cells); <= 0 means infinity
     size_t tw_off = 0;  // byte offset of the twiddle table in `tables`
     size_t g_off = 0;   // byte offset of the octant Green's table
+    size_t tw64_off = 0, g64_off = 0;  // FP64 copies (CUBE2_FP64_FORM only)
 };
 
 }  // namespace cube2
@@ -50,6 +51,9 @@ struct cube2_ctx {
     float pp_kinv = 0.f;               // K / b_f
     std::vector<float> pp_rows;        // (K+1) * kPairRow floats (host copy)
     size_t pp_off = 0;                 // byte offset of the pair-law table in `tables`
+    std::vector<double> pp_rows64;     // the same rows in FP64
+    size_t pp64_off = 0;               // FP64 rows (CUBE2_FP64_FORM only)
+    bool fp64 = false;                 // CUBE2_FP64_FORM
     int n_f = 0, n_ios = 0, nt = 0;   // fine cells, IOS cells, tiles per side
     int64_t n_cells = 0;               // IOS cells
     int n_levels = 1;                  // 1 or 2; level 0 = fine, 1 = coarse
@@ -63,6 +67,7 @@ namespace cube2 {
 // Byte layout of the work buffer for n particles.
 struct WorkLayout {
     size_t real_f, real_c, bar_f, bar_c, spec, coarse_acc;
+    size_t real64_f, real64_c, spec64;  // FP64 form (zero-sized without it)
     size_t keys, vals, keys2, vals2, hist, counts, scan_tmp, offs_tmp, red;
     size_t total;
 };
@@ -132,6 +137,38 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
     __syncthreads();
     total = tot;
     return off + x - v;
+}
+
+// Copy the periodic S^3 block of an n^3 mesh starting at node (x0, y0, z0)
+// (wrapped) into LDS, x fastest.  The loads of one thread are issued as a
+// batch (all in flight before the LDS stores), so a block pays one memory
+// latency per batch instead of one per element.
+template <int S, int BLOCK>
+__device__ __forceinline__ void stage_block(float *__restrict__ dst, const float *__restrict__ mesh,
+                                            int n, int x0, int y0, int z0) {
+    constexpr int TOT = S * S * S;
+    constexpr int PER = (TOT + BLOCK - 1) / BLOCK;
+    constexpr int BATCH = PER < 12 ? PER : 12;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int k0 = 0; k0 < PER; k0 += BATCH) {
+        float v[BATCH];
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k) {
+            const int i = tid + (k0 + k) * BLOCK;
+            v[k] = 0.0f;
+            if (k0 + k < PER && i < TOT) {
+                const int lx = i % S, ly = (i / S) % S, lz = i / (S * S);
+                v[k] = mesh[((int64_t)((z0 + lz) & (n - 1)) * n + ((y0 + ly) & (n - 1))) * n +
+                            ((x0 + lx) & (n - 1))];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k) {
+            const int i = tid + (k0 + k) * BLOCK;
+            if (k0 + k < PER && i < TOT) dst[i] = v[k];
+        }
+    }
 }
 
 // ---- launch helpers (host) -------------------------------------------------

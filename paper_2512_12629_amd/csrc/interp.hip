@@ -62,20 +62,14 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(
     const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
     for (int i = tid; i <= kTileCells; i += kBlock) cst[i] = cs[key0 + i];
     const int ax0 = tx * kTileFine, ay0 = ty * kTileFine, az0 = tz * kTileFine;
-    for (int i = tid; i < kFS * kFS * kFS; i += kBlock) {
-        const int lx = i % kFS, ly = (i / kFS) % kFS, lz = i / (kFS * kFS);
-        const int gx = wrapn(ax0 + lx - 2, n_f), gy = wrapn(ay0 + ly - 2, n_f),
-                  gz = wrapn(az0 + lz - 2, n_f);
-        pf[i] = phi_f[((int64_t)gz * n_f + gy) * n_f + gx];
-    }
+    stage_block<kFS, kBlock>(pf, phi_f, n_f, ax0 - 2, ay0 - 2, az0 - 2);
     const int CS = (kTileFine >> hshift) + 5;
     if (TWO) {
         const int cx0 = ax0 >> hshift, cy0 = ay0 >> hshift, cz0 = az0 >> hshift;
-        for (int i = tid; i < CS * CS * CS; i += kBlock) {
-            const int lx = i % CS, ly = (i / CS) % CS, lz = i / (CS * CS);
-            const int gx = wrapn(cx0 + lx - 2, n_c), gy = wrapn(cy0 + ly - 2, n_c),
-                      gz = wrapn(cz0 + lz - 2, n_c);
-            pc[i] = phi_c[((int64_t)gz * n_c + gy) * n_c + gx];
+        switch (CS) {
+            case 13: stage_block<13, kBlock>(pc, phi_c, n_c, cx0 - 2, cy0 - 2, cz0 - 2); break;
+            case 9: stage_block<9, kBlock>(pc, phi_c, n_c, cx0 - 2, cy0 - 2, cz0 - 2); break;
+            default: stage_block<7, kBlock>(pc, phi_c, n_c, cx0 - 2, cy0 - 2, cz0 - 2); break;
         }
     }
     __syncthreads();
