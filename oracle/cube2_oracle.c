@@ -34,35 +34,43 @@ double orc_profile(double r, double b)
     return 0.0;
 }
 
-/* eq. (2): force magnitude between two eq.(1) profiles at distance r. */
-double orc_refforce(double r, double b)
+/* eq. (2): force magnitude between two eq.(1) profiles at distance r.
+ * The pair law of eq. (4d) subtracts two of these, which cancel as r
+ * approaches b_f (both tend to 1/r^2), so they are evaluated in x87 extended
+ * precision (64-bit significand) and the difference is rounded once. */
+typedef long double xreal;
+
+static xreal refforce_x(xreal r, xreal b)
 {
-    if (r >= b) return 1.0 / (r * r);
-    double b2 = b * b, b3 = b2 * b, b4 = b3 * b, b5 = b4 * b, b6 = b5 * b,
-           b7 = b6 * b, b8 = b7 * b;
-    double r2 = r * r, r3 = r2 * r, r4 = r3 * r, r5 = r4 * r, r6 = r5 * r;
+    if (r >= b) return 1.0L / (r * r);
+    xreal b2 = b * b, b3 = b2 * b, b4 = b3 * b, b5 = b4 * b, b6 = b5 * b,
+          b7 = b6 * b, b8 = b7 * b;
+    xreal r2 = r * r, r3 = r2 * r, r4 = r3 * r, r5 = r4 * r, r6 = r5 * r;
     if (r < b / 2)
-        return 64.0 * r / (5.0 * b3) - 256.0 * r3 / (5.0 * b5) + 32.0 * r4 / b6
-             + 1536.0 * r5 / (35.0 * b7) - 192.0 * r6 / (5.0 * b8);
-    return 3.0 / (35.0 * r2) - 32.0 / (5.0 * b2) + 256.0 * r / (5.0 * b3)
-         - 96.0 * r2 / b4 + 256.0 * r3 / (5.0 * b5) + 32.0 * r4 / b6
-         - 1536.0 * r5 / (35.0 * b7) + 64.0 * r6 / (5.0 * b8);
+        return 64.0L * r / (5.0L * b3) - 256.0L * r3 / (5.0L * b5) + 32.0L * r4 / b6
+             + 1536.0L * r5 / (35.0L * b7) - 192.0L * r6 / (5.0L * b8);
+    return 3.0L / (35.0L * r2) - 32.0L / (5.0L * b2) + 256.0L * r / (5.0L * b3)
+         - 96.0L * r2 / b4 + 256.0L * r3 / (5.0L * b5) + 32.0L * r4 / b6
+         - 1536.0L * r5 / (35.0L * b7) + 64.0L * r6 / (5.0L * b8);
 }
 
 /* d/dr of eq. (2), term by term. */
-double orc_refforce_dr(double r, double b)
+static xreal refforce_dr_x(xreal r, xreal b)
 {
-    if (r >= b) return -2.0 / (r * r * r);
-    double b2 = b * b, b3 = b2 * b, b4 = b3 * b, b5 = b4 * b, b6 = b5 * b,
-           b7 = b6 * b, b8 = b7 * b;
-    double r2 = r * r, r3 = r2 * r, r4 = r3 * r, r5 = r4 * r;
+    if (r >= b) return -2.0L / (r * r * r);
+    xreal b2 = b * b, b3 = b2 * b, b4 = b3 * b, b5 = b4 * b, b6 = b5 * b,
+          b7 = b6 * b, b8 = b7 * b;
+    xreal r2 = r * r, r3 = r2 * r, r4 = r3 * r, r5 = r4 * r;
     if (r < b / 2)
-        return 64.0 / (5.0 * b3) - 768.0 * r2 / (5.0 * b5) + 128.0 * r3 / b6
-             + 1536.0 * r4 / (7.0 * b7) - 1152.0 * r5 / (5.0 * b8);
-    return -6.0 / (35.0 * r3) + 256.0 / (5.0 * b3) - 192.0 * r / b4
-         + 768.0 * r2 / (5.0 * b5) + 128.0 * r3 / b6 - 1536.0 * r4 / (7.0 * b7)
-         + 384.0 * r5 / (5.0 * b8);
+        return 64.0L / (5.0L * b3) - 768.0L * r2 / (5.0L * b5) + 128.0L * r3 / b6
+             + 1536.0L * r4 / (7.0L * b7) - 1152.0L * r5 / (5.0L * b8);
+    return -6.0L / (35.0L * r3) + 256.0L / (5.0L * b3) - 192.0L * r / b4
+         + 768.0L * r2 / (5.0L * b5) + 128.0L * r3 / b6 - 1536.0L * r4 / (7.0L * b7)
+         + 384.0L * r5 / (5.0L * b8);
 }
+
+double orc_refforce(double r, double b) { return (double)refforce_x(r, b); }
+double orc_refforce_dr(double r, double b) { return (double)refforce_dr_x(r, b); }
 
 /* eq. (13): Fourier transform of eq.(1).  b <= 0 stands for b = infinity,
  * where S vanishes (b_0 = infinity, so the coarsest level is untruncated).
@@ -393,19 +401,28 @@ void orc_deposit_adjoint_pos(int64_t N, const double *x, int n, double H, int qu
 /* ------------------------------------------------------------------ */
 
 /* g(r) = [R(r, b_pp) - R(r, b_f)] / r for 0 < r < b_f, else 0. */
-double orc_pp_g(double r, double b_pp, double b_f)
+static xreal pp_g_x(xreal r, xreal b_pp, xreal b_f)
 {
-    if (!(r > 0.0) || r >= b_f) return 0.0;
-    return (orc_refforce(r, b_pp) - orc_refforce(r, b_f)) / r;
+    if (!(r > 0.0L) || r >= b_f) return 0.0L;
+    return (refforce_x(r, b_pp) - refforce_x(r, b_f)) / r;
 }
 
 /* g'(r) */
-double orc_pp_dg(double r, double b_pp, double b_f)
+static xreal pp_dg_x(xreal r, xreal b_pp, xreal b_f)
 {
-    if (!(r > 0.0) || r >= b_f) return 0.0;
-    double R = orc_refforce(r, b_pp) - orc_refforce(r, b_f);
-    double dR = orc_refforce_dr(r, b_pp) - orc_refforce_dr(r, b_f);
+    if (!(r > 0.0L) || r >= b_f) return 0.0L;
+    xreal R = refforce_x(r, b_pp) - refforce_x(r, b_f);
+    xreal dR = refforce_dr_x(r, b_pp) - refforce_dr_x(r, b_f);
     return dR / r - R / (r * r);
+}
+
+double orc_pp_g(double r, double b_pp, double b_f) { return (double)pp_g_x(r, b_pp, b_f); }
+double orc_pp_dg(double r, double b_pp, double b_f) { return (double)pp_dg_x(r, b_pp, b_f); }
+
+/* g at the squared separation r2 (exact in FP64 for quantised positions). */
+static inline double pp_g_r2(double r2, double b_pp, double b_f)
+{
+    return (double)pp_g_x(sqrtl((xreal)r2), b_pp, b_f);
 }
 
 static inline double minimg(double d, double L)
@@ -428,7 +445,7 @@ void orc_pp_brute(int64_t N, const double *x, double L, double b_pp, double b_f,
                 D[d] = minimg(x[d * N + j] - x[d * N + i], L);
                 r2 += D[d] * D[d];
             }
-            double g = orc_pp_g(sqrt(r2), b_pp, b_f);
+            double g = pp_g_r2(r2, b_pp, b_f);
             for (int d = 0; d < 3; ++d) a[d] += g * D[d];
         }
         for (int d = 0; d < 3; ++d) acc[d * N + i] += a[d];
@@ -481,7 +498,7 @@ void orc_pp(int64_t N, const double *x, double L, double b_pp, double b_f, doubl
                             D[d] = minimg(x[d * N + j] - x[d * N + i], L);
                             r2 += D[d] * D[d];
                         }
-                        double g = orc_pp_g(sqrt(r2), b_pp, b_f);
+                        double g = pp_g_r2(r2, b_pp, b_f);
                         for (int d = 0; d < 3; ++d) a[d] += g * D[d];
                     }
         for (int d = 0; d < 3; ++d) acc[d * N + i] += a[d];
@@ -513,7 +530,7 @@ void orc_pp_subset(int64_t N, const double *x, double L, double b_pp, double b_f
                                 D[d] = minimg(x[d * N + j] - x[d * N + i], L);
                                 r2 += D[d] * D[d];
                             }
-                            double g = orc_pp_g(sqrt(r2), b_pp, b_f);
+                            double g = pp_g_r2(r2, b_pp, b_f);
                             for (int d = 0; d < 3; ++d) a[d] += g * D[d];
                         }
         } else {
@@ -524,7 +541,7 @@ void orc_pp_subset(int64_t N, const double *x, double L, double b_pp, double b_f
                     D[d] = minimg(x[d * N + j] - x[d * N + i], L);
                     r2 += D[d] * D[d];
                 }
-                double g = orc_pp_g(sqrt(r2), b_pp, b_f);
+                double g = pp_g_r2(r2, b_pp, b_f);
                 for (int d = 0; d < 3; ++d) a[d] += g * D[d];
             }
         }
@@ -590,9 +607,10 @@ void orc_pp_adjoint(int64_t N, const double *x, double L, double b_pp, double b_
                     D[d] = minimg(x[d * N + j] - x[d * N + k], L);
                     r2 += D[d] * D[d];
                 }
-                double r = sqrt(r2);
-                if (!(r > 0.0) || r >= b_f) continue;
-                double g = orc_pp_g(r, b_pp, b_f), gp = orc_pp_dg(r, b_pp, b_f);
+                xreal rx = sqrtl((xreal)r2);
+                if (!(rx > 0.0L) || rx >= b_f) continue;
+                double r = (double)rx;
+                double g = (double)pp_g_x(rx, b_pp, b_f), gp = (double)pp_dg_x(rx, b_pp, b_f);
                 double u[3], Du = 0.0;
                 for (int d = 0; d < 3; ++d) {
                     u[d] = abar[d * N + j] - abar[d * N + k];
