@@ -160,6 +160,43 @@ def cpu_baseline(workload: str):
                       f"fine mesh {n_f}^3, full FP64 PM+PP force, {dt:.2f} s"}
 
 
+def fp64_comparison(m, cfg, c, pos, cs, N, ms32, stream, timed):
+    """The FP64 plain form on the same particles: its force time, the FP32
+    speedup over it, and the per-particle error of the FP32 force (and the
+    norm-relative error of the FP32 fine potential) against it."""
+    import dataclasses
+    import torch
+    a32 = c.force(pos, cs)
+    rho32, fx = c.deposit(pos, cs, 0, fx=True)
+    phi32 = c.potential(rho32, 0)
+    del rho32
+    cfg64 = dataclasses.replace(cfg, flags=cfg.flags | m.CUBE2_FP64_FORM)
+    c64 = m.Cube2(cfg64, n_max=N)
+    acc64 = torch.empty((3, N), dtype=torch.float64, device="cuda")
+
+    def force64():
+        m.cube2_pm_force_f64(c64.ctx, pos, cs, acc64, c64.work)
+        m.cube2_pp_force_f64(c64.ctx, pos, cs, acc64, c64.work, accumulate=True)
+
+    force64()
+    t64 = timed(force64, 3)
+    num = torch.linalg.vector_norm(a32.double() - acc64, dim=0)
+    den = torch.linalg.vector_norm(acc64, dim=0).clamp_min(1e-300)
+    e = (num / den).cpu().numpy()
+    k99 = int(0.99 * (e.size - 1))
+    part = np.partition(e, [e.size // 2, k99])
+    rho64 = fx.to(torch.float64).mul_(2.0 ** -45)
+    del fx
+    phi64 = c64.potential_f64(rho64, 0)
+    perr = float(torch.linalg.vector_norm(phi32.double() - phi64) / torch.linalg.vector_norm(phi64))
+    del c64, acc64, rho64, phi64, phi32, a32
+    torch.cuda.empty_cache()
+    ms64 = float(np.median(t64))
+    return {"force_ms": ms64, "fp32_speedup": ms64 / ms32,
+            "force_rel_err_median": float(part[e.size // 2]), "force_rel_err_p99": float(part[k99]),
+            "force_rel_err_max": float(e.max()), "fine_potential_rel_err": perr}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +206,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="time only the force step (for profiler runs)")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the comparison with the FP64 plain form")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timing, run a plain copy kernel (y = -x) of this many MiB "
                          "read + the same written, as the reference for HBM counter passes")
@@ -240,6 +279,8 @@ def main():
         "wall_s_timed": wall, "table_init_s": t_init, "status": status,
     }
     pairs = None
+    if not args.no_extras and not args.no_fp64:
+        out["fp64_form"] = fp64_comparison(m, cfg, c, pos, cs, N, ms, stream, timed)
     if not args.no_extras:
         # stages (each is one C-ABI entry point on the same stream)
         n_f, pitch_f = c.level_shape(0)

@@ -69,8 +69,10 @@ enum cube2_status_code {
 };
 
 enum cube2_flags {
-    CUBE2_PP_OFF = 1          /* cube2_pp_force becomes a no-op (paper, sec. 4:
+    CUBE2_PP_OFF = 1,         /* cube2_pp_force becomes a no-op (paper, sec. 4:
                                  PP may be disabled for fast runs) */
+    CUBE2_FP64_FORM = 2       /* also build the FP64 tables and size the work
+                                 buffer for the *_f64 entry points */
 };
 
 /* Force parameters (section 2.1.1 and 2.2.2).  All lengths in fine cells. */
@@ -230,6 +232,33 @@ int cube2_kick_drift_backward(cube2_ctx *ctx, int64_t n, const int32_t *perm,
                               const float *xbar_out, const float *vbar_out, double kick,
                               double drift, float *xbar_in, float *vbar_in, float *acc_bar,
                               cube2_stream_t stream);
+
+/* ---- FP64 plain form ---------------------------------------------------
+ * The same force evaluated in FP64 throughout on the device: the density is
+ * the deposit's exact integer accumulator times 2^-45, the Green's tables
+ * (eq. 11) and FFT twiddles are stored in FP64, the FFT-G-IFFT pipeline,
+ * the eq. (7) stencil and the CIC interpolation run in FP64, and the PP pair
+ * law (eqs. 2, 4d) is the same exact piecewise polynomial evaluated in FP64.
+ * It is the reference the FP32 path is measured against on sizes the host
+ * cannot evaluate.  All three return CUBE2_ESTATE unless the context was
+ * created with CUBE2_FP64_FORM and its tables are initialised. */
+
+/* FP64 potential of a level: phi = IFFT(G * FFT(rho)) / n^3; rho and phi
+ * (device, n^3 FP64, [z][y][x]) may alias. */
+int cube2_potential_f64(cube2_ctx *ctx, int level, const double *rho, double *phi, void *work,
+                        size_t work_bytes, cube2_stream_t stream);
+
+/* FP64 PM force of all levels (deposit, potential, interpolation) into acc
+ * (device, 3*n FP64); accumulate != 0 adds. */
+int cube2_pm_force_f64(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                       int64_t n, double *acc, int accumulate, void *work, size_t work_bytes,
+                       cube2_stream_t stream);
+
+/* FP64 PP force (eq. 4d) into acc (device, 3*n FP64); accumulate != 0 adds.
+ * A no-op (or a zero fill) with CUBE2_PP_OFF, like cube2_pp_force. */
+int cube2_pp_force_f64(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                       int64_t n, double *acc, int accumulate, void *work, size_t work_bytes,
+                       cube2_stream_t stream);
 
 /* Text of a status code. */
 const char *cube2_strerror(int code);

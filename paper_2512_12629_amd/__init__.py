@@ -29,6 +29,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libcube2.so")
 
 CUBE2_PP_OFF = 1
+CUBE2_FP64_FORM = 2
 _ERRORS = {0: "ok", -1: "invalid argument", -2: "unsupported configuration",
            -3: "tables or work buffer too small", -4: "deposit overflow guard",
            -5: "HIP runtime error", -6: "tables not initialised"}
@@ -75,6 +76,9 @@ def _load():
         "cube2_pm_force_backward": [P, P, P, I64, P, P, I, P, S, P],
         "cube2_pp_force_backward": [P, P, P, I64, P, P, I, P, S, P],
         "cube2_kick_drift_backward": [P, I64, P, P, P, D, D, P, P, P, P],
+        "cube2_potential_f64": [P, I, P, P, P, S, P],
+        "cube2_pm_force_f64": [P, P, P, I64, P, I, P, S, P],
+        "cube2_pp_force_f64": [P, P, P, I64, P, I, P, S, P],
         "cube2_strerror": [I],
     }
     for name, args in sigs.items():
@@ -234,6 +238,23 @@ def cube2_kick_drift_backward(ctx, perm, xbar_out, vbar_out, kick, drift, xbar_i
                                           _stream(stream)), "cube2_kick_drift_backward")
 
 
+def cube2_potential_f64(ctx, level, rho, phi, work, stream=None):
+    _check(_lib.cube2_potential_f64(ctx, int(level), _ptr(rho), _ptr(phi), _ptr(work),
+                                    work.numel(), _stream(stream)), "cube2_potential_f64")
+
+
+def cube2_pm_force_f64(ctx, pos, cell_start, acc, work, accumulate=False, stream=None):
+    _check(_lib.cube2_pm_force_f64(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], _ptr(acc),
+                                   int(bool(accumulate)), _ptr(work), work.numel(),
+                                   _stream(stream)), "cube2_pm_force_f64")
+
+
+def cube2_pp_force_f64(ctx, pos, cell_start, acc, work, accumulate=False, stream=None):
+    _check(_lib.cube2_pp_force_f64(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], _ptr(acc),
+                                   int(bool(accumulate)), _ptr(work), work.numel(),
+                                   _stream(stream)), "cube2_pp_force_f64")
+
+
 def cube2_strerror(code: int) -> str:
     return _lib.cube2_strerror(int(code)).decode()
 
@@ -385,6 +406,30 @@ class Cube2:
         cube2_pp_force_backward(self.ctx, pos, cs, acc_bar.contiguous(), x_bar, self.work,
                                 accumulate)
         return x_bar
+
+    # -- FP64 plain form (context created with CUBE2_FP64_FORM) ---------------
+    def potential_f64(self, rho, level=0):
+        phi = torch.empty_like(rho, dtype=torch.float64)
+        cube2_potential_f64(self.ctx, level, rho.to(torch.float64).contiguous(), phi, self.work)
+        return phi
+
+    def pm_force_f64(self, pos, cs, acc=None):
+        accumulate = acc is not None
+        if acc is None:
+            acc = torch.empty((3, pos.shape[1]), dtype=torch.float64, device=self.device)
+        cube2_pm_force_f64(self.ctx, pos, cs, acc, self.work, accumulate)
+        return acc
+
+    def pp_force_f64(self, pos, cs, acc=None):
+        accumulate = acc is not None
+        if acc is None:
+            acc = torch.empty((3, pos.shape[1]), dtype=torch.float64, device=self.device)
+        cube2_pp_force_f64(self.ctx, pos, cs, acc, self.work, accumulate)
+        return acc
+
+    def force_f64(self, pos, cs):
+        acc = self.pm_force_f64(pos, cs)
+        return self.pp_force_f64(pos, cs, acc)
 
     def kick_drift_backward(self, perm, xbar_out, vbar_out, kick, drift):
         xb = torch.empty_like(xbar_out)

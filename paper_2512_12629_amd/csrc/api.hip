@@ -30,6 +30,18 @@ size_t table_layout(cube2_ctx *c) {
     }
     c->pp_off = off;
     off = align_up(off + (size_t)(kPairKMax + 1) * kPairRow * sizeof(float), 256);
+    if (c->fp64) {
+        for (int l = 0; l < c->n_levels; ++l) {
+            Level &L = c->lv[l];
+            size_t h = (size_t)(L.n / 2 + 1);
+            L.tw64_off = off;
+            off = align_up(off + (size_t)L.n * sizeof(double2), 256);
+            L.g64_off = off;
+            off = align_up(off + h * h * h * sizeof(double), 256);
+        }
+        c->pp64_off = off;
+        off = align_up(off + (size_t)(kPairKMax + 1) * kPairRow * sizeof(double), 256);
+    }
     return off;
 }
 
@@ -62,6 +74,11 @@ WorkLayout work_layout(const cube2_ctx *c, int64_t n) {
     L.scan_tmp = take((scan_len / 1024 + 64) * 4 * 2 + 4096);
     L.offs_tmp = take(nn * 3 * sizeof(uint16_t));
     L.red = take(8192 * 8 * sizeof(double));
+    if (c->fp64) {
+        L.real64_f = take(nf3 * sizeof(double));
+        L.real64_c = take(nc3 * sizeof(double));
+        L.spec64 = take((size_t)c->n_f * c->n_f * c->lv[0].pitch * sizeof(double2));
+    }
     L.total = off;
     return L;
 }
@@ -103,6 +120,7 @@ int cube2_create(const cube2_config *cfg, cube2_ctx **out) {
     ctx->nt = ctx->n_ios / kTileIos;
     ctx->n_cells = (int64_t)ctx->n_ios * ctx->n_ios * ctx->n_ios;
     ctx->n_levels = c.coarse_ratio ? 2 : 1;
+    ctx->fp64 = (c.flags & CUBE2_FP64_FORM) != 0;
     Level &F = ctx->lv[0];
     F.n = c.n_fine;
     F.H = 1;
@@ -149,6 +167,10 @@ int cube2_init_tables(cube2_ctx *ctx, void *tables, size_t table_bytes, cube2_st
     CUBE2_CHECK_HIP(hipMemsetAsync(ctx->tables, 0, 256, s));
     CUBE2_CHECK_HIP(hipMemcpyAsync(ctx->tables + ctx->pp_off, ctx->pp_rows.data(),
                                    ctx->pp_rows.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    if (ctx->fp64)
+        CUBE2_CHECK_HIP(hipMemcpyAsync(ctx->tables + ctx->pp64_off, ctx->pp_rows64.data(),
+                                       ctx->pp_rows64.size() * sizeof(double),
+                                       hipMemcpyHostToDevice, s));
     return launch_green(ctx, s);
 }
 
@@ -346,6 +368,66 @@ int cube2_kick_drift_backward(cube2_ctx *ctx, int64_t n, const int32_t *perm,
     if (n == 0) return CUBE2_OK;
     return launch_kick_drift_backward(ctx, n, perm, xbar_out, vbar_out, kick, drift, xbar_in,
                                       vbar_in, acc_bar, reinterpret_cast<hipStream_t>(stream));
+}
+
+int cube2_potential_f64(cube2_ctx *ctx, int level, const double *rho, double *phi, void *work,
+                        size_t work_bytes, cube2_stream_t stream) {
+    CHECK_READY();
+    if (!ctx->fp64) return CUBE2_ESTATE;
+    if (level < 0 || level >= ctx->n_levels || !rho || !phi) return CUBE2_EINVAL;
+    CHECK_WORK(0);
+    return launch_potential64(ctx, level, rho, phi,
+                              reinterpret_cast<double2 *>(work_ + L_.spec64),
+                              reinterpret_cast<hipStream_t>(stream));
+}
+
+int cube2_pm_force_f64(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                       int64_t n, double *acc, int accumulate, void *work, size_t work_bytes,
+                       cube2_stream_t stream) {
+    CHECK_READY();
+    if (!ctx->fp64) return CUBE2_ESTATE;
+    if (n < 0 || n > INT32_MAX || !cell_start || (n > 0 && (!pos || !acc))) return CUBE2_EINVAL;
+    CHECK_WORK(n);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const bool two = ctx->n_levels > 1;
+    // the deposit writes its FP32 density into the FP32 scratch meshes and the
+    // exact accumulators into the FP64 meshes, converted there in place
+    float *rf = reinterpret_cast<float *>(work_ + L_.real_f);
+    float *rc = two ? reinterpret_cast<float *>(work_ + L_.real_c) : nullptr;
+    uint64_t *ff = reinterpret_cast<uint64_t *>(work_ + L_.real64_f);
+    uint64_t *fc = two ? reinterpret_cast<uint64_t *>(work_ + L_.real64_c) : nullptr;
+    double2 *spec = reinterpret_cast<double2 *>(work_ + L_.spec64);
+    int rcode = launch_deposit(ctx, pos, cell_start, n, rf, ff, rc, fc, work_, L_, s);
+    if (rcode) return rcode;
+    for (int l = 0; l < ctx->n_levels; ++l) {
+        uint64_t *m = l == 0 ? ff : fc;
+        const int64_t nl = ctx->lv[l].n;
+        rcode = launch_fx_to_f64(m, nl * nl * nl, s);
+        if (rcode) return rcode;
+        double *md = reinterpret_cast<double *>(m);
+        rcode = launch_potential64(ctx, l, md, md, spec, s);
+        if (rcode) return rcode;
+    }
+    if (n == 0) return CUBE2_OK;
+    return launch_interp64(ctx, pos, cell_start, n, reinterpret_cast<double *>(ff),
+                           reinterpret_cast<double *>(fc), acc, accumulate, s);
+}
+
+int cube2_pp_force_f64(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                       int64_t n, double *acc, int accumulate, void *work, size_t work_bytes,
+                       cube2_stream_t stream) {
+    CHECK_READY();
+    if (!ctx->fp64) return CUBE2_ESTATE;
+    if (n < 0 || n > INT32_MAX || !cell_start || (n > 0 && (!pos || !acc))) return CUBE2_EINVAL;
+    CHECK_WORK(n);
+    (void)work_;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (n == 0) return CUBE2_OK;
+    if (ctx->cfg.flags & CUBE2_PP_OFF) {
+        if (!accumulate) CUBE2_CHECK_HIP(hipMemsetAsync(acc, 0, (size_t)n * 3 * 8, s));
+        return CUBE2_OK;
+    }
+    return launch_pp64(ctx, pos, cell_start, n, acc, accumulate, s);
 }
 
 const char *cube2_strerror(int code) {

@@ -143,20 +143,20 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
 // (wrapped) into LDS, x fastest.  The loads of one thread are issued as a
 // batch (all in flight before the LDS stores), so a block pays one memory
 // latency per batch instead of one per element.
-template <int S, int BLOCK>
-__device__ __forceinline__ void stage_block(float *__restrict__ dst, const float *__restrict__ mesh,
-                                            int n, int x0, int y0, int z0) {
+template <int S, int BLOCK, typename T>
+__device__ __forceinline__ void stage_block(T *__restrict__ dst, const T *__restrict__ mesh, int n,
+                                            int x0, int y0, int z0) {
     constexpr int TOT = S * S * S;
     constexpr int PER = (TOT + BLOCK - 1) / BLOCK;
     constexpr int BATCH = PER < 12 ? PER : 12;
     const int tid = threadIdx.x;
 #pragma unroll
     for (int k0 = 0; k0 < PER; k0 += BATCH) {
-        float v[BATCH];
+        T v[BATCH];
 #pragma unroll
         for (int k = 0; k < BATCH; ++k) {
             const int i = tid + (k0 + k) * BLOCK;
-            v[k] = 0.0f;
+            v[k] = T(0);
             if (k0 + k < PER && i < TOT) {
                 const int lx = i % S, ly = (i / S) % S, lz = i / (S * S);
                 v[k] = mesh[((int64_t)((z0 + lz) & (n - 1)) * n + ((y0 + ly) & (n - 1))) * n +
@@ -194,6 +194,14 @@ int launch_green(cube2_ctx *ctx, hipStream_t s);
 int launch_fft_r2c(cube2_ctx *ctx, int level, const float *mesh, float2 *spec, hipStream_t s);
 int launch_potential(cube2_ctx *ctx, int level, const float *rho, float *phi, float2 *spec,
                      hipStream_t s);
+int launch_potential64(cube2_ctx *ctx, int level, const double *rho, double *phi, double2 *spec,
+                       hipStream_t s);
+int launch_interp64(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                    const double *phi_f, const double *phi_c, double *acc, int accumulate,
+                    hipStream_t s);
+int launch_pp64(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, double *acc,
+                int accumulate, hipStream_t s);
+int launch_fx_to_f64(uint64_t *buf, int64_t m, hipStream_t s);
 int launch_interp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                   const float *phi_f, const float *phi_c, float *acc, int accumulate,
                   hipStream_t s);

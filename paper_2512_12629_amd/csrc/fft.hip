@@ -17,6 +17,8 @@
 // Every line transform is a four-step FFT N = N1*N2: each thread holds one
 // N1-point sub-sequence in registers (radix-2, compile-time twiddles), the
 // N1 x N2 transpose goes through LDS, then an N2-point register FFT.
+// Every kernel is templated on the real type: float for the production path,
+// double for the FP64 plain form (same passes, FP64 twiddles and G).
 #include "common.hpp"
 
 namespace cube2 {
@@ -76,13 +78,13 @@ constexpr double cx_sin_frac(int p, int q) {
 }
 
 template <int R>
-struct RootTable {  // exp(-2 pi i k / R), k = 0..R-1
-    float re[R];
-    float im[R];
+struct RootTable {  // exp(-2 pi i k / R), k = 0..R-1, rounded per use
+    double re[R];
+    double im[R];
     constexpr RootTable() : re(), im() {
         for (int k = 0; k < R; ++k) {
-            re[k] = (float)cx_cos_frac(k, R);
-            im[k] = (float)-cx_sin_frac(k, R);
+            re[k] = cx_cos_frac(k, R);
+            im[k] = -cx_sin_frac(k, R);
         }
     }
 };
@@ -92,13 +94,19 @@ struct Roots {
     static constexpr RootTable<R> t{};
 };
 
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+template <typename T> struct Cx;
+template <> struct Cx<float> { using c = float2; };
+template <> struct Cx<double> { using c = double2; };
+
+__device__ __forceinline__ float2 cmk(float x, float y) { return make_float2(x, y); }
+__device__ __forceinline__ double2 cmk(double x, double y) { return make_double2(x, y); }
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return cmk(a.x + b.x, a.y + b.y); }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return cmk(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+    return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
-    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {  // a * conj(b)
+    return cmk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
@@ -110,14 +118,15 @@ constexpr int bitrev(int v, int bits) {
 
 // In-register radix-2 DIT DFT of size R, natural order in and out.
 // SIGN = -1: forward (exp(-i...)), +1: inverse (unnormalised).
-template <int R, int SIGN>
-__device__ __forceinline__ void dft(float2 (&v)[R]) {
+template <int R, int SIGN, typename C>
+__device__ __forceinline__ void dft(C (&v)[R]) {
+    using S = decltype(v[0].x);
     constexpr int B = ilog2c(R);
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const int j = bitrev(i, B);
         if (j > i) {
-            float2 t = v[i];
+            C t = v[i];
             v[i] = v[j];
             v[j] = t;
         }
@@ -129,16 +138,16 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
         for (int i = 0; i < R; i += len) {
 #pragma unroll
             for (int j = 0; j < half; ++j) {
-                float2 u = v[i + j], t = v[i + j + half];
+                C u = v[i + j], t = v[i + j + half];
                 if (j == 0) {
                 } else if (4 * j == len) {
                     // w = exp(SIGN * i * pi / 2) = SIGN * i
-                    t = SIGN < 0 ? make_float2(t.y, -t.x) : make_float2(-t.y, t.x);
+                    t = SIGN < 0 ? cmk(t.y, -t.x) : cmk(-t.y, t.x);
                 } else {
                     const int k = j * (R / len);
-                    const float wr = Roots<R>::t.re[k];
-                    const float wi = SIGN < 0 ? Roots<R>::t.im[k] : -Roots<R>::t.im[k];
-                    t = make_float2(t.x * wr - t.y * wi, t.x * wi + t.y * wr);
+                    const S wr = (S)Roots<R>::t.re[k];
+                    const S wi = SIGN < 0 ? (S)Roots<R>::t.im[k] : (S)-Roots<R>::t.im[k];
+                    t = cmk(t.x * wr - t.y * wi, t.x * wi + t.y * wr);
                 }
                 v[i + j] = cadd(u, t);
                 v[i + j + half] = csub(u, t);
@@ -159,39 +168,40 @@ struct Split {
 
 // MODE 0: one transform with sign SIGN.  MODE 2: forward, times G/n^3,
 // inverse (the z pass).  Workgroup = COLS adjacent columns x one line.
-template <int N, int COLS, int SIGN, int MODE>
+template <int N, int COLS, int SIGN, int MODE, typename T>
 __global__ __launch_bounds__(COLS *Split<N>::TMAX) void col_fft(
-    float2 *__restrict__ data, int64_t jstride, int64_t line_stride, const float2 *__restrict__ tw,
-    const float *__restrict__ G, int n, int pitch, float scale) {
+    typename Cx<T>::c *__restrict__ data, int64_t jstride, int64_t line_stride,
+    const typename Cx<T>::c *__restrict__ tw, const T *__restrict__ G, int n, int pitch, T scale) {
+    using C = typename Cx<T>::c;
     constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
     constexpr int PAD = COLS < 16 ? COLS : 0;
     constexpr int RS1 = N2 * COLS + PAD;  // row stride of the forward exchange
     constexpr int RS2 = N1 * COLS + PAD;  // row stride of the inverse exchange
     constexpr int LDS1 = N1 * RS1, LDS2 = (MODE == 2) ? N2 * RS2 : 0;
     constexpr int LDSN = LDS1 > LDS2 ? LDS1 : LDS2;
-    __shared__ float2 sh[LDSN];
+    __shared__ C sh[LDSN];
 
     const int t = threadIdx.x;
     const int col = t % COLS;
     const int64_t base = (int64_t)blockIdx.y * line_stride + (int64_t)blockIdx.x * COLS + col;
-    float2 *line = data + base;
+    C *line = data + base;
 
     // forward (or the single) transform, phase 1: thread owns j2, all j1
     if (t < COLS * N2) {
         const int j2 = t / COLS;
-        float2 v[N1];
+        C v[N1];
 #pragma unroll
         for (int j1 = 0; j1 < N1; ++j1) v[j1] = line[(int64_t)(j1 * N2 + j2) * jstride];
         dft<N1, SIGN>(v);
 #pragma unroll
         for (int k1 = 0; k1 < N1; ++k1) {
-            float2 w = tw[(j2 * k1) & (N - 1)];
-            float2 y = (SIGN < 0) ? cmul(v[k1], w) : cmulc(v[k1], w);
+            C w = tw[(j2 * k1) & (N - 1)];
+            C y = (SIGN < 0) ? cmul(v[k1], w) : cmulc(v[k1], w);
             sh[k1 * RS1 + j2 * COLS + col] = y;
         }
     }
     __syncthreads();
-    float2 v2[N2];
+    C v2[N2];
     int k1 = t / COLS;
     if (t < COLS * N1) {
 #pragma unroll
@@ -216,21 +226,21 @@ __global__ __launch_bounds__(COLS *Split<N>::TMAX) void col_fft(
         for (int k2 = 0; k2 < N2; ++k2) {
             const int kz = k1 + N1 * k2;
             const int mz = kz <= n - kz ? kz : n - kz;
-            const float g = kx < h ? G[((int64_t)mz * h + my) * h + kx] * scale : 0.0f;
-            v2[k2] = make_float2(v2[k2].x * g, v2[k2].y * g);
+            const T g = kx < h ? G[((int64_t)mz * h + my) * h + kx] * scale : T(0);
+            v2[k2] = cmk(v2[k2].x * g, v2[k2].y * g);
         }
         // inverse phase 1: thread owns b = k1, holds X[a*N1 + b], a = k2
         dft<N2, +1>(v2);
 #pragma unroll
         for (int ka = 0; ka < N2; ++ka) {
-            float2 w = tw[(k1 * ka) & (N - 1)];
+            C w = tw[(k1 * ka) & (N - 1)];
             sh[ka * RS2 + k1 * COLS + col] = cmulc(v2[ka], w);
         }
     }
     __syncthreads();
     if (t < COLS * N2) {
         const int ka = t / COLS;
-        float2 v[N1];
+        C v[N1];
 #pragma unroll
         for (int b = 0; b < N1; ++b) v[b] = sh[ka * RS2 + b * COLS + col];
         dft<N1, +1>(v);  // v[kb] = x[ka + N2 kb]
@@ -249,23 +259,26 @@ struct RowGeo {
     static constexpr int XLEN = (M + 1) > M1 * RS ? (M + 1) : M1 * RS;  // per-row LDS
 };
 
-template <int M>
-__global__ __launch_bounds__(256) void r2c_x(const float *__restrict__ in, float2 *__restrict__ out,
-                                             int pitch, const float2 *__restrict__ tw, int64_t nrows) {
+template <int M, typename T>
+__global__ __launch_bounds__(256) void r2c_x(const T *__restrict__ in,
+                                             typename Cx<T>::c *__restrict__ out, int pitch,
+                                             const typename Cx<T>::c *__restrict__ tw,
+                                             int64_t nrows) {
+    using C = typename Cx<T>::c;
     using Gm = RowGeo<M>;
     constexpr int M1 = Gm::M1, M2 = Gm::M2, TR = Gm::TR, RS = Gm::RS, XL = Gm::XLEN;
     constexpr int N = 2 * M;
-    __shared__ float2 sh[Gm::ROWS * XL];
+    __shared__ C sh[Gm::ROWS * XL];
     const int t = threadIdx.x;
     const int rl = t / TR, tl = t % TR;
     const int64_t row = (int64_t)blockIdx.x * Gm::ROWS + rl;
     const bool live = row < nrows;
-    const float2 *src = reinterpret_cast<const float2 *>(in + (live ? row : 0) * N);
-    float2 *x = sh + rl * XL;
+    const C *src = reinterpret_cast<const C *>(in + (live ? row : 0) * N);
+    C *x = sh + rl * XL;
 
     if (tl < M2) {
         const int j2 = tl;
-        float2 v[M1];
+        C v[M1];
 #pragma unroll
         for (int j1 = 0; j1 < M1; ++j1) v[j1] = src[j1 * M2 + j2];
         dft<M1, -1>(v);
@@ -273,7 +286,7 @@ __global__ __launch_bounds__(256) void r2c_x(const float *__restrict__ in, float
         for (int k1 = 0; k1 < M1; ++k1) x[k1 * RS + j2] = cmul(v[k1], tw[(2 * j2 * k1) & (N - 1)]);
     }
     __syncthreads();
-    float2 v2[M2];
+    C v2[M2];
     if (tl < M1) {
 #pragma unroll
         for (int j2 = 0; j2 < M2; ++j2) v2[j2] = x[tl * RS + j2];
@@ -286,50 +299,54 @@ __global__ __launch_bounds__(256) void r2c_x(const float *__restrict__ in, float
     }
     __syncthreads();
     if (!live) return;
-    float2 *dst = out + row * pitch;
+    C *dst = out + row * pitch;
+    const T half = T(0.5);
     for (int k = tl; k < pitch; k += TR) {
-        float2 r = make_float2(0.f, 0.f);
+        C r = cmk(T(0), T(0));
         if (k <= M) {
-            const float2 zk = x[k & (M - 1)], zm = x[(M - k) & (M - 1)];
+            const C zk = x[k & (M - 1)], zm = x[(M - k) & (M - 1)];
             // even part E = (Zk + conj Zm)/2, odd part O = (Zk - conj Zm)/(2i)
-            const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-            const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+            const C e = cmk(half * (zk.x + zm.x), half * (zk.y - zm.y));
+            const C o = cmk(half * (zk.y + zm.y), -half * (zk.x - zm.x));
             r = cadd(e, cmul(o, tw[k]));  // X[k] = E + W_N^k O
         }
         dst[k] = r;
     }
 }
 
-template <int M>
-__global__ __launch_bounds__(256) void c2r_x(const float2 *__restrict__ in, float *__restrict__ out,
-                                             int pitch, const float2 *__restrict__ tw, int64_t nrows) {
+template <int M, typename T>
+__global__ __launch_bounds__(256) void c2r_x(const typename Cx<T>::c *__restrict__ in,
+                                             T *__restrict__ out, int pitch,
+                                             const typename Cx<T>::c *__restrict__ tw,
+                                             int64_t nrows) {
+    using C = typename Cx<T>::c;
     using Gm = RowGeo<M>;
     constexpr int M1 = Gm::M1, M2 = Gm::M2, TR = Gm::TR, RS = Gm::RS, XL = Gm::XLEN;
     constexpr int N = 2 * M;
-    __shared__ float2 sh[Gm::ROWS * XL];
+    __shared__ C sh[Gm::ROWS * XL];
     const int t = threadIdx.x;
     const int rl = t / TR, tl = t % TR;
     const int64_t row = (int64_t)blockIdx.x * Gm::ROWS + rl;
     const bool live = row < nrows;
-    const float2 *src = in + (live ? row : 0) * pitch;
-    float2 *x = sh + rl * XL;
+    const C *src = in + (live ? row : 0) * pitch;
+    C *x = sh + rl * XL;
     for (int k = tl; k <= M; k += TR) {
-        float2 v = src[k];
-        if (k == 0 || k == M) v.y = 0.0f;  // DC and Nyquist are real
+        C v = src[k];
+        if (k == 0 || k == M) v.y = T(0);  // DC and Nyquist are real
         x[k] = v;
     }
     __syncthreads();
-    float2 v[M1];
+    C v[M1];
     if (tl < M2) {
         const int b = tl;
 #pragma unroll
         for (int a = 0; a < M1; ++a) {
             const int k = a * M2 + b;
-            const float2 xk = x[k], xm = x[M - k];
+            const C xk = x[k], xm = x[M - k];
             // Z = (Xk + conj Xm) + i W_N^-k (Xk - conj Xm) = 2 (E + i O)
-            const float2 d = make_float2(xk.x - xm.x, xk.y + xm.y);
-            const float2 c = cmulc(d, tw[k]);
-            v[a] = make_float2(xk.x + xm.x - c.y, xk.y - xm.y + c.x);
+            const C d = cmk(xk.x - xm.x, xk.y + xm.y);
+            const C c = cmulc(d, tw[k]);
+            v[a] = cmk(xk.x + xm.x - c.y, xk.y - xm.y + c.x);
         }
         dft<M1, +1>(v);
     }
@@ -340,11 +357,11 @@ __global__ __launch_bounds__(256) void c2r_x(const float2 *__restrict__ in, floa
     }
     __syncthreads();
     if (tl < M1 && live) {
-        float2 w[M2];
+        C w[M2];
 #pragma unroll
         for (int b = 0; b < M2; ++b) w[b] = x[tl * RS + b];
         dft<M2, +1>(w);  // w[kb] = z[tl + M1 kb]
-        float2 *dst = reinterpret_cast<float2 *>(out + row * N);
+        C *dst = reinterpret_cast<C *>(out + row * N);
 #pragma unroll
         for (int kb = 0; kb < M2; ++kb) dst[tl + M1 * kb] = w[kb];
     }
@@ -352,61 +369,66 @@ __global__ __launch_bounds__(256) void c2r_x(const float2 *__restrict__ in, floa
 
 // ---- dispatch ------------------------------------------------------------
 
-template <int N>
-constexpr int cols_for() { return 16; }
+// Adjacent columns per col_fft workgroup: 16 complex64 (128 B rows) in FP32;
+// 8 complex128 in FP64, which keeps the 1024-point exchange within LDS.
+template <typename T>
+constexpr int cols_for() { return sizeof(T) == 8 ? 8 : 16; }
 
-template <int N, int SIGN, int MODE>
-int run_col(float2 *data, int64_t jstride, int64_t line_stride, int lines, const float2 *tw,
-            const float *G, int n, int pitch, float scale, hipStream_t s) {
-    constexpr int COLS = cols_for<N>();
+template <int N, int SIGN, int MODE, typename T>
+int run_col(typename Cx<T>::c *data, int64_t jstride, int64_t line_stride, int lines,
+            const typename Cx<T>::c *tw, const T *G, int n, int pitch, T scale, hipStream_t s) {
+    constexpr int COLS = cols_for<T>();
     dim3 grid(pitch / COLS, lines);
-    col_fft<N, COLS, SIGN, MODE><<<grid, COLS * Split<N>::TMAX, 0, s>>>(data, jstride, line_stride,
-                                                                       tw, G, n, pitch, scale);
+    col_fft<N, COLS, SIGN, MODE, T><<<grid, COLS * Split<N>::TMAX, 0, s>>>(
+        data, jstride, line_stride, tw, G, n, pitch, scale);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }
 
-template <int N>
-int run_level(int op, const float *rin, float *rout, float2 *spec, const float2 *tw, const float *G,
-              int pitch, hipStream_t s) {
+template <int N, typename T>
+int run_level(int op, const T *rin, T *rout, typename Cx<T>::c *spec,
+              const typename Cx<T>::c *tw, const T *G, int pitch, hipStream_t s) {
     constexpr int M = N / 2;
     using Gm = RowGeo<M>;
     const int64_t rows = (int64_t)N * N;
     const int64_t plane = (int64_t)N * pitch;
     int r;
     const unsigned xblocks = (unsigned)((rows + Gm::ROWS - 1) / Gm::ROWS);
-    r2c_x<M><<<xblocks, 256, 0, s>>>(rin, spec, pitch, tw, rows);
+    r2c_x<M, T><<<xblocks, 256, 0, s>>>(rin, spec, pitch, tw, rows);
     CUBE2_LAUNCH_CHECK();
     // y pass: lines along y inside each z plane
-    r = run_col<N, -1, 0>(spec, pitch, plane, N, tw, G, N, pitch, 1.0f, s);
+    r = run_col<N, -1, 0, T>(spec, pitch, plane, N, tw, G, N, pitch, T(1), s);
     if (r) return r;
     if (op == 0) {  // forward spectrum only: z pass forward
-        return run_col<N, -1, 0>(spec, plane, pitch, N, tw, G, N, pitch, 1.0f, s);
+        return run_col<N, -1, 0, T>(spec, plane, pitch, N, tw, G, N, pitch, T(1), s);
     }
-    const float scale = (float)(1.0 / ((double)N * N * N));
-    r = run_col<N, -1, 2>(spec, plane, pitch, N, tw, G, N, pitch, scale, s);
+    const T scale = (T)(1.0 / ((double)N * N * N));
+    r = run_col<N, -1, 2, T>(spec, plane, pitch, N, tw, G, N, pitch, scale, s);
     if (r) return r;
-    r = run_col<N, +1, 0>(spec, pitch, plane, N, tw, G, N, pitch, 1.0f, s);
+    r = run_col<N, +1, 0, T>(spec, pitch, plane, N, tw, G, N, pitch, T(1), s);
     if (r) return r;
-    c2r_x<M><<<xblocks, 256, 0, s>>>(spec, rout, pitch, tw, rows);
+    c2r_x<M, T><<<xblocks, 256, 0, s>>>(spec, rout, pitch, tw, rows);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }
 
-int run(cube2_ctx *ctx, int level, int op, const float *rin, float *rout, float2 *spec,
+template <typename T>
+int run(cube2_ctx *ctx, int level, int op, const T *rin, T *rout, typename Cx<T>::c *spec,
         hipStream_t s) {
+    using C = typename Cx<T>::c;
     const Level &L = ctx->lv[level];
-    const float2 *tw = reinterpret_cast<const float2 *>(ctx->tables + L.tw_off);
-    const float *G = reinterpret_cast<const float *>(ctx->tables + L.g_off);
+    const bool f64 = sizeof(T) == 8;
+    const C *tw = reinterpret_cast<const C *>(ctx->tables + (f64 ? L.tw64_off : L.tw_off));
+    const T *G = reinterpret_cast<const T *>(ctx->tables + (f64 ? L.g64_off : L.g_off));
     switch (L.n) {
-        case 8: return run_level<8>(op, rin, rout, spec, tw, G, L.pitch, s);
-        case 16: return run_level<16>(op, rin, rout, spec, tw, G, L.pitch, s);
-        case 32: return run_level<32>(op, rin, rout, spec, tw, G, L.pitch, s);
-        case 64: return run_level<64>(op, rin, rout, spec, tw, G, L.pitch, s);
-        case 128: return run_level<128>(op, rin, rout, spec, tw, G, L.pitch, s);
-        case 256: return run_level<256>(op, rin, rout, spec, tw, G, L.pitch, s);
-        case 512: return run_level<512>(op, rin, rout, spec, tw, G, L.pitch, s);
-        case 1024: return run_level<1024>(op, rin, rout, spec, tw, G, L.pitch, s);
+        case 8: return run_level<8, T>(op, rin, rout, spec, tw, G, L.pitch, s);
+        case 16: return run_level<16, T>(op, rin, rout, spec, tw, G, L.pitch, s);
+        case 32: return run_level<32, T>(op, rin, rout, spec, tw, G, L.pitch, s);
+        case 64: return run_level<64, T>(op, rin, rout, spec, tw, G, L.pitch, s);
+        case 128: return run_level<128, T>(op, rin, rout, spec, tw, G, L.pitch, s);
+        case 256: return run_level<256, T>(op, rin, rout, spec, tw, G, L.pitch, s);
+        case 512: return run_level<512, T>(op, rin, rout, spec, tw, G, L.pitch, s);
+        case 1024: return run_level<1024, T>(op, rin, rout, spec, tw, G, L.pitch, s);
         default: return CUBE2_EUNSUPPORTED;
     }
 }
@@ -414,12 +436,17 @@ int run(cube2_ctx *ctx, int level, int op, const float *rin, float *rout, float2
 }  // namespace
 
 int launch_fft_r2c(cube2_ctx *ctx, int level, const float *mesh, float2 *spec, hipStream_t s) {
-    return run(ctx, level, 0, mesh, nullptr, spec, s);
+    return run<float>(ctx, level, 0, mesh, nullptr, spec, s);
 }
 
 int launch_potential(cube2_ctx *ctx, int level, const float *rho, float *phi, float2 *spec,
                      hipStream_t s) {
-    return run(ctx, level, 1, rho, phi, spec, s);
+    return run<float>(ctx, level, 1, rho, phi, spec, s);
+}
+
+int launch_potential64(cube2_ctx *ctx, int level, const double *rho, double *phi, double2 *spec,
+                       hipStream_t s) {
+    return run<double>(ctx, level, 1, rho, phi, spec, s);
 }
 
 }  // namespace cube2

@@ -9,7 +9,8 @@
 // d_d = 4/3 sin k_d - 1/6 sin 2 k_d (eq. 10, D = i d),
 // dS2 = S^2(|k|, b_a) - S^2(|k|, b_prev) (eq. 12; S of eq. 13; S(k, inf) = 0).
 // This is eq. (11) with D . R* = -4 pi (d . k_a) dS2 / k_a^2.  G = 0 where
-// |d| = 0.  The table is stored as FP32 over the octant |m_d| <= n/2.
+// |d| = 0.  The table is stored as FP32 over the octant |m_d| <= n/2 (and,
+// for the FP64 plain form, a second time in FP64).
 #include "common.hpp"
 
 namespace cube2 {
@@ -30,7 +31,8 @@ __device__ double profile_k(double u) {
     return 12.0 * (2.0 - 2.0 * cos(u) - u * sin(u)) / (u2 * u2);
 }
 
-__global__ void green_kernel(float *__restrict__ out, int n, double ba, double bprev, int nmax) {
+template <typename T>
+__global__ void green_kernel(T *__restrict__ out, int n, double ba, double bprev, int nmax) {
     const int h = n / 2 + 1;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)h * h * h) return;
@@ -44,7 +46,7 @@ __global__ void green_kernel(float *__restrict__ out, int n, double ba, double b
         dd += d[a] * d[a];
     }
     if (dd == 0.0) {
-        out[idx] = 0.0f;
+        out[idx] = T(0);
         return;
     }
     // Per-axis alias windows w[a][j] = sinc^4((k_a + 2 pi j)/2), j = -nmax..nmax.
@@ -71,7 +73,7 @@ __global__ void green_kernel(float *__restrict__ out, int n, double ba, double b
                 const double sp = bprev > 0.0 ? profile_k(0.5 * km * bprev) : 0.0;
                 V += W2 * (d[0] * kx + d[1] * ky + d[2] * kz) * (sa * sa - sp * sp) / kk;
             }
-    out[idx] = (float)(-4.0 * kPi * V / (dd * U * U));
+    out[idx] = (T)(-4.0 * kPi * V / (dd * U * U));
 }
 
 // W_n^m = exp(-2 pi i m / n), m = 0..n-1, from FP64.
@@ -80,6 +82,13 @@ __global__ void twiddle_kernel(float2 *__restrict__ tw, int n) {
     if (m >= n) return;
     const double f = 2.0 * (double)m / (double)n;
     tw[m] = make_float2((float)cospi(f), (float)(-sinpi(f)));
+}
+
+__global__ void twiddle64_kernel(double2 *__restrict__ tw, int n) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const double f = 2.0 * (double)m / (double)n;
+    tw[m] = make_double2(cospi(f), -sinpi(f));
 }
 
 }  // namespace
@@ -95,9 +104,18 @@ int launch_green(cube2_ctx *ctx, hipStream_t s) {
         float *g = reinterpret_cast<float *>(ctx->tables + L.g_off);
         const double ba = L.b_a / L.H;
         const double bp = L.b_prev > 0.0 ? L.b_prev / L.H : -1.0;
-        green_kernel<<<(unsigned)((pts + 255) / 256), 256, 0, s>>>(g, L.n, ba, bp,
-                                                                   ctx->cfg.alias_nmax);
+        green_kernel<float><<<(unsigned)((pts + 255) / 256), 256, 0, s>>>(g, L.n, ba, bp,
+                                                                          ctx->cfg.alias_nmax);
         CUBE2_LAUNCH_CHECK();
+        if (ctx->fp64) {
+            twiddle64_kernel<<<(L.n + 255) / 256, 256, 0, s>>>(
+                reinterpret_cast<double2 *>(ctx->tables + L.tw64_off), L.n);
+            CUBE2_LAUNCH_CHECK();
+            green_kernel<double><<<(unsigned)((pts + 255) / 256), 256, 0, s>>>(
+                reinterpret_cast<double *>(ctx->tables + L.g64_off), L.n, ba, bp,
+                ctx->cfg.alias_nmax);
+            CUBE2_LAUNCH_CHECK();
+        }
     }
     return CUBE2_OK;
 }

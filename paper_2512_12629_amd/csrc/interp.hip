@@ -9,6 +9,8 @@
 // the 6 potential values along each axis around its 2x2 CIC footprint and
 // forms E = -[(2/3)(phi(+1) - phi(-1)) - (1/12)(phi(+2) - phi(-2))] at its two
 // nodes per axis, weighted with the deposit's 15-bit integer weights.
+// The kernel is templated on the real type: float for the production path,
+// double for the FP64 plain form.
 #include "common.hpp"
 
 namespace cube2 {
@@ -19,21 +21,23 @@ constexpr int kCSMax = kTileFine / 2 + 5; // 13: coarse tile with halo (ratio 2)
 
 // FD force at the particle's two nodes along one axis, CIC-weighted.
 // p points at phi(node j) on that axis; st is the axis stride in LDS.
-__device__ __forceinline__ float axis_force(const float *p, int st, float w0, float w1) {
-    const float pm2 = p[-2 * st], pm1 = p[-st], p0 = p[0], p1 = p[st], p2 = p[2 * st],
-                p3 = p[3 * st];
-    const float e0 = -((2.0f / 3.0f) * (p1 - pm1) - (1.0f / 12.0f) * (p2 - pm2));
-    const float e1 = -((2.0f / 3.0f) * (p2 - p0) - (1.0f / 12.0f) * (p3 - pm1));
+template <typename T>
+__device__ __forceinline__ T axis_force(const T *p, int st, T w0, T w1) {
+    const T pm2 = p[-2 * st], pm1 = p[-st], p0 = p[0], p1 = p[st], p2 = p[2 * st], p3 = p[3 * st];
+    const T c1 = T(2.0 / 3.0), c2 = T(1.0 / 12.0);
+    const T e0 = -(c1 * (p1 - pm1) - c2 * (p2 - pm2));
+    const T e1 = -(c1 * (p2 - p0) - c2 * (p3 - pm1));
     return w0 * e0 + w1 * e1;
 }
 
 // CIC-weighted force of a staged potential tile P (side S) at the particle
 // whose lower CIC node is (jx, jy, jz) in tile coordinates.
-__device__ __forceinline__ void gather(const float *P, int S, int jx, int jy, int jz,
-                                       const float (&wx)[2], const float (&wy)[2],
-                                       const float (&wz)[2], float &ax, float &ay, float &az) {
+template <typename T>
+__device__ __forceinline__ void gather(const T *P, int S, int jx, int jy, int jz,
+                                       const T (&wx)[2], const T (&wy)[2], const T (&wz)[2],
+                                       T &ax, T &ay, T &az) {
     const int SS = S * S;
-    ax = ay = az = 0.0f;
+    ax = ay = az = T(0);
 #pragma unroll
     for (int s1 = 0; s1 < 2; ++s1)
 #pragma unroll
@@ -47,13 +51,13 @@ __device__ __forceinline__ void gather(const float *P, int S, int jx, int jy, in
         }
 }
 
-template <bool TWO>
+template <bool TWO, typename T>
 __global__ __launch_bounds__(kBlock) void interp_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs, int n, int n_f, int nt,
-    const float *__restrict__ phi_f, const float *__restrict__ phi_c, int n_c, int hshift,
-    float scale_f, float scale_c, float *__restrict__ acc, int accumulate) {
-    __shared__ float pf[kFS * kFS * kFS];
-    __shared__ float pc[TWO ? kCSMax * kCSMax * kCSMax : 1];
+    const T *__restrict__ phi_f, const T *__restrict__ phi_c, int n_c, int hshift, T scale_f,
+    T scale_c, T *__restrict__ acc, int accumulate) {
+    __shared__ T pf[kFS * kFS * kFS];
+    __shared__ T pc[TWO ? kCSMax * kCSMax * kCSMax : 1];
     __shared__ uint32_t cst[kTileCells + 1];
 
     int tx, ty, tz;
@@ -74,34 +78,34 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(
     }
     __syncthreads();
     const uint32_t p0 = cst[0], p1 = cst[kTileCells];
-    const float inv = 1.0f / 32768.0f;
+    const T inv = T(1.0 / 32768.0);
     for (uint32_t p = p0 + tid; p < p1; p += kBlock) {
         const int u = seg_search(cst, kTileCells, p);
         const int uc[3] = {u & 7, (u >> 3) & 7, u >> 6};
         int jf[3], jc[3];
-        float wf[3][2], wc[3][2];
+        T wf[3][2], wc[3][2];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const uint32_t o = pos[(int64_t)d * n + p];
             const int f = (int)(o & 0x7FFFu);
             jf[d] = 2 * uc[d] + (int)(o >> 15) + 2;       // +2: LDS halo
-            wf[d][1] = (float)f * inv;
-            wf[d][0] = (float)(32768 - f) * inv;
+            wf[d][1] = (T)f * inv;
+            wf[d][0] = (T)(32768 - f) * inv;
             if (TWO) {
                 const uint32_t q = ((uint32_t)uc[d] << 16) + o;  // tile-relative, 2^-15 units
                 const int fc = (int)((q >> hshift) & 0x7FFFu);
                 jc[d] = (int)(q >> (kFracBits + hshift)) + 2;
-                wc[d][1] = (float)fc * inv;
-                wc[d][0] = (float)(32768 - fc) * inv;
+                wc[d][1] = (T)fc * inv;
+                wc[d][0] = (T)(32768 - fc) * inv;
             }
         }
-        float a[3];
+        T a[3];
         gather(pf, kFS, jf[0], jf[1], jf[2], wf[0], wf[1], wf[2], a[0], a[1], a[2]);
         a[0] *= scale_f;
         a[1] *= scale_f;
         a[2] *= scale_f;
         if (TWO) {
-            float c[3];
+            T c[3];
             gather(pc, CS, jc[0], jc[1], jc[2], wc[0], wc[1], wc[2], c[0], c[1], c[2]);
             a[0] += scale_c * c[0];
             a[1] += scale_c * c[1];
@@ -109,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(
         }
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            float *dst = acc + (int64_t)d * n + p;
+            T *dst = acc + (int64_t)d * n + p;
             *dst = accumulate ? *dst + a[d] : a[d];
         }
     }
@@ -117,25 +121,37 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(
 
 }  // namespace
 
-int launch_interp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
-                  const float *phi_f, const float *phi_c, float *acc, int accumulate,
-                  hipStream_t s) {
+template <typename T>
+int interp_levels(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                  const T *phi_f, const T *phi_c, T *acc, int accumulate, hipStream_t s) {
     const int nt = ctx->nt;
     const unsigned blocks = (unsigned)(nt * nt * nt);
     const double gm = ctx->cfg.g_newton * ctx->cfg.m_p;
     if (ctx->n_levels > 1) {
         const Level &C = ctx->lv[1];
-        interp_kernel<true><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, phi_f, phi_c,
-                                                     C.n, C.hshift, (float)gm,
-                                                     (float)(gm / ((double)C.H * C.H)), acc,
-                                                     accumulate);
+        interp_kernel<true, T><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, phi_f,
+                                                         phi_c, C.n, C.hshift, (T)gm,
+                                                         (T)(gm / ((double)C.H * C.H)), acc,
+                                                         accumulate);
     } else {
-        interp_kernel<false><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, phi_f,
-                                                      nullptr, 1, 0, (float)gm, 0.0f, acc,
-                                                      accumulate);
+        interp_kernel<false, T><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, phi_f,
+                                                          nullptr, 1, 0, (T)gm, T(0), acc,
+                                                          accumulate);
     }
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
+}
+
+int launch_interp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                  const float *phi_f, const float *phi_c, float *acc, int accumulate,
+                  hipStream_t s) {
+    return interp_levels<float>(ctx, pos, cs, n, phi_f, phi_c, acc, accumulate, s);
+}
+
+int launch_interp64(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                    const double *phi_f, const double *phi_c, double *acc, int accumulate,
+                    hipStream_t s) {
+    return interp_levels<double>(ctx, pos, cs, n, phi_f, phi_c, acc, accumulate, s);
 }
 
 }  // namespace cube2

@@ -56,6 +56,10 @@ template <bool ADJ> struct PPGeo {
 
 namespace {
 
+// The pair-law table in LDS, declared at namespace scope so that every access
+// is a 32-bit LDS address (each kernel that uses it gets its own copy).
+__shared__ float4 pair_rows[3 * (kPairKMax + 1)];
+
 __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
     const float y = v - c;
     const float t = s + y;
@@ -64,17 +68,18 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
 }
 
 // g(r) * D accumulated into (fx, fy, fz); rows (LDS) hold the pair-law table.
-__device__ __forceinline__ void pair_accumulate(float dx, float dy, float dz, const float4 *rows,
-                                                float kinv, int K, float &fx, float &fy,
-                                                float &fz) {
+__device__ __forceinline__ void pair_accumulate(float dx, float dy, float dz, float kinv, int K,
+                                                float &fx, float &fy, float &fz) {
     // coincident particles (D = 0, r2 = 0) are clamped to r2 = 1e-12, below the
     // smallest nonzero separation (2^-15 fine cells), so g stays finite and g D = 0
     const float r2 = fmaxf(dx * dx + dy * dy + dz * dz, 1e-12f);
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * rinv;
     const float f = r * kinv;
-    const int idx = min((int)f, K);
-    const float4 c0 = rows[3 * idx], c1 = rows[3 * idx + 1], c2 = rows[3 * idx + 2];
+    // idx <= K <= 64: the mask tells the compiler the row offset fits a
+    // 24-bit multiply (a full-rate v_mad_u32_u24 instead of a 64-bit one)
+    const int idx = min((int)f, K) & 127;
+    const float4 c0 = pair_rows[3 * idx], c1 = pair_rows[3 * idx + 1], c2 = pair_rows[3 * idx + 2];
     const float y = c2.y + c2.z * __builtin_amdgcn_fractf(f);
     const float U =
         c0.x + y * (c0.y + y * (c0.z + y * (c0.w + y * (c1.x + y * (c1.y + y * (c1.z + y * (c1.w + y * c2.x)))))));
@@ -88,14 +93,16 @@ __device__ __forceinline__ void pair_accumulate(float dx, float dy, float dz, co
 // abar_i and J = g I + g' D D^T / r.  g' = r^-3 (y_b K/b_f dU/dy - 3 U / r)
 // with U and dU/dy from the same table row (Horner with derivative).
 __device__ __forceinline__ void pair_adjoint(float dx, float dy, float dz, float ux, float uy,
-                                             float uz, const float4 *rows, float kinv, int K,
-                                             float &ox, float &oy, float &oz) {
+                                             float uz, float kinv, int K, float &ox, float &oy,
+                                             float &oz) {
     const float r2 = fmaxf(dx * dx + dy * dy + dz * dz, 1e-12f);
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * rinv;
     const float f = r * kinv;
-    const int idx = min((int)f, K);
-    const float4 c0 = rows[3 * idx], c1 = rows[3 * idx + 1], c2 = rows[3 * idx + 2];
+    // idx <= K <= 64: the mask tells the compiler the row offset fits a
+    // 24-bit multiply (a full-rate v_mad_u32_u24 instead of a 64-bit one)
+    const int idx = min((int)f, K) & 127;
+    const float4 c0 = pair_rows[3 * idx], c1 = pair_rows[3 * idx + 1], c2 = pair_rows[3 * idx + 2];
     const float y = c2.y + c2.z * __builtin_amdgcn_fractf(f);
     const float cf[9] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w, c2.x};
     float U = cf[8], dU = 0.0f;
@@ -135,7 +142,6 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
     __shared__ uint32_t seg_src[kPSegs];
     __shared__ float4 xs[CAP];
     __shared__ float4 as_[ADJ ? CAP : 1];
-    __shared__ float4 rows[3 * (kPairKMax + 1)];
     __shared__ uint32_t cst[kTileCells + 1];     // own cells: particle starts (tile-relative)
     __shared__ uint32_t scan_sh[kPPBlock / 64 + 1];
     __shared__ int chunk_sh;
@@ -145,7 +151,7 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
     const int tid = threadIdx.x;
     const int n_ios = nt * kTileIos;
     const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
-    for (int i = tid; i < 3 * (K + 1); i += kPPBlock) rows[i] = table[i];
+    for (int i = tid; i < 3 * (K + 1); i += kPPBlock) pair_rows[i] = table[i];
 
     // particle ranges of the 10^3 box of IOS cells [c0-1, c0+9)
     uint32_t cnt[kPSegPerThread], src[kPSegPerThread], sum = 0;
@@ -177,7 +183,7 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
     // own cells: particle starts relative to the tile's first particle
     const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
     const uint32_t p0 = cs[key0];
-    if (tid < kTileCells) cst[tid] = cs[key0 + tid] - p0;
+    for (int i = tid; i < kTileCells; i += kPPBlock) cst[i] = cs[key0 + i] - p0;
     if (tid == 0) {
         seg_pre[kPSegs] = total;
         cst[kTileCells] = cs[key0 + kTileCells] - p0;
@@ -248,17 +254,17 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                         for (; v < v1; ++v) {
                             const float4 qa = xs[v], aa = as_[v];
                             pair_adjoint(qa.x - xi, qa.y - yi, qa.z - zi, aa.x - aix, aa.y - aiy,
-                                         aa.z - aiz, rows, kinv, K, fx, fy, fz);
+                                         aa.z - aiz, kinv, K, fx, fy, fz);
                         }
                     } else {
                         for (; v + 1 < v1; v += 2) {
                             const float4 qa = xs[v], qb = xs[v + 1];
-                            pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, rows, kinv, K, fx, fy, fz);
-                            pair_accumulate(qb.x - xi, qb.y - yi, qb.z - zi, rows, kinv, K, fx, fy, fz);
+                            pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, kinv, K, fx, fy, fz);
+                            pair_accumulate(qb.x - xi, qb.y - yi, qb.z - zi, kinv, K, fx, fy, fz);
                         }
                         if (v < v1) {
                             const float4 qa = xs[v];
-                            pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, rows, kinv, K, fx, fy, fz);
+                            pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, kinv, K, fx, fy, fz);
                         }
                     }
                     kahan_add(sx, cx, fx);
@@ -281,9 +287,9 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                         if (ADJ)
                             pair_adjoint(xj - xi, yj - yi, zj - zi, abar[pj] - aix,
                                          abar[(int64_t)n + pj] - aiy, abar[2 * (int64_t)n + pj] - aiz,
-                                         rows, kinv, K, fx, fy, fz);
+                                         kinv, K, fx, fy, fz);
                         else
-                            pair_accumulate(xj - xi, yj - yi, zj - zi, rows, kinv, K, fx, fy, fz);
+                            pair_accumulate(xj - xi, yj - yi, zj - zi, kinv, K, fx, fy, fz);
                     }
                     kahan_add(sx, cx, fx);
                     kahan_add(sy, cy, fy);
@@ -338,6 +344,7 @@ void build_pair_table(cube2_ctx *ctx) {
     ctx->pp_K = K;
     ctx->pp_kinv = (float)(K / bf);
     ctx->pp_rows.assign((size_t)(K + 1) * kPairRow, 0.0f);
+    ctx->pp_rows64.assign((size_t)(K + 1) * kPairRow, 0.0);
     for (int k = 0; k < K; ++k) {
         const double mid = (k + 0.5) * w, rl = k * w, rr = (k + 1) * w;
         const int pb = mid < bpp / 2 ? 0 : (mid < bpp ? 1 : 2);  // in, out, Newtonian
@@ -373,9 +380,10 @@ void build_pair_table(cube2_ctx *ctx) {
             yb = 1.0;
         }
         float *row = &ctx->pp_rows[(size_t)k * kPairRow];
-        for (int j = 0; j < 9; ++j) row[j] = (float)Q[j];
-        row[9] = (float)ya;
-        row[10] = (float)yb;
+        double *row64 = &ctx->pp_rows64[(size_t)k * kPairRow];
+        for (int j = 0; j < 9; ++j) row[j] = (float)(row64[j] = Q[j]);
+        row[9] = (float)(row64[9] = ya);
+        row[10] = (float)(row64[10] = yb);
     }
 }
 

@@ -158,6 +158,36 @@ def test_pp_force_against_oracle(case):
     assert med < MED and p99 < P99, (med, p99)
 
 
+EXACT = {
+    "zel_32_ragged": (32, lambda: synthetic.zeldovich(13, 0.25, 103)),
+    "clustered_32": (32, lambda: synthetic.clustered(12, 0.25, 1, 256, 0.5 / 32, 105)),
+}
+
+
+@pytest.mark.parametrize("name", list(EXACT))
+def test_pp_force_against_exact(name):
+    """FP32 PP against the exact rational PP sum of oracle.exact (stored in
+    tests/golden/pp_exact_*.txt): median <= 1e-4, p99 <= 1e-3 with the
+    floor of the oracle comparison above."""
+    import os
+    import paper_2512_12629_amd as m
+    n_f, gen = EXACT[name]
+    x = gen()
+    ref = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                  f"pp_exact_{name}.txt")).T
+    c = m.Cube2(m.Config(n_fine=n_f), n_max=x.shape[1])
+    pos, cs, perm = c.pack(torch.from_numpy(x).cuda())
+    acc = np.empty_like(ref)
+    acc[:, _np(perm).astype(np.int64)] = _np(c.pp_force(pos, cs))
+    fr = np.linalg.norm(ref, axis=0)
+    has = fr > 0
+    assert np.all(acc[:, ~has] == 0)
+    floor = 1e-6 * np.median(fr[has])
+    e = np.linalg.norm(acc - ref, axis=0)[has] / np.maximum(fr[has], floor)
+    med, p99 = float(np.median(e)), float(np.percentile(e, 99))
+    assert med < MED and p99 < P99, (med, p99)
+
+
 def test_total_force_against_oracle(case):
     c, p = case["c"], case["p"]
     xf = _sorted_fine(case)
