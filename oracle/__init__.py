@@ -19,7 +19,11 @@ The oracle follows the paper's steps in order, in FP64:
   docstrings and pinned by finite differences in the tests).
 
 The loops live in ``cube2_oracle.c`` (plain C, built with gcc); the FFT is
-numpy's (a library primitive used as one step).
+numpy's (a library primitive used as one step).  One step departs from FP64:
+the PP pair law subtracts two eq. (2) forces that cancel near the cutoff, so
+eq. (2) and the difference are evaluated in x87 extended precision and
+rounded once.  ``oracle.exact`` evaluates the PP sum in exact rational
+arithmetic for small particle sets.
 
 Parity pins: see tests/test_oracle_*.py.  The IOS velocity codec is not
 implemented here (parity unpinned in the paper's terms).
