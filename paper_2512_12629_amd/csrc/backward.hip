@@ -18,39 +18,34 @@ namespace cube2 {
 namespace {
 
 // ---------------------------------------------------------------------------
-// fine level: phibar on a 16^3 node tile from the particles of an 11^3 box of
-// IOS cells (a particle in fine cell j reaches nodes j-2 .. j+3 along the
-// stencil axis and j, j+1 across it)
+// fine level: phibar on a 16^3 node tile.  The workgroup first scatters
+// c*abar with the CIC weights onto the nodes of the tile plus a 2-node halo
+// (20^3 nodes, 3 components, FP32 LDS atomics), from every particle whose
+// CIC footprint reaches that region (an 11^3 box of IOS cells: a particle in
+// fine cell j feeds nodes j and j+1), then applies the stencil transpose
+// phibar = D . Abar on the 16^3 interior from LDS.
 // ---------------------------------------------------------------------------
 
 constexpr int kAB = kTileIos + 3;            // 11 IOS cells per axis: [c0-2, c0+9)
 constexpr int kASegs = kAB * kAB * kAB;      // 1331
-constexpr int kASegPerThread = (kASegs + kBlock - 1) / kBlock;  // 6
+constexpr int kAN = kTileFine + 4;           // 20 nodes per axis: [a0-2, a0+18)
+constexpr int kAN3 = kAN * kAN * kAN;
+constexpr int kPhiBlock = 512;
+constexpr int kASegPerThread = (kASegs + kPhiBlock - 1) / kPhiBlock;  // 3
 
-// coefficients of the 1D "CIC then stencil transpose" kernel at offsets
-// -2..3 from the lower CIC node j, for node values A0 (at j) and A1 (at j+1)
-__device__ __forceinline__ void stencil_t(float A0, float A1, float (&o)[6]) {
-    o[0] = -A0 * (1.0f / 12.0f);
-    o[1] = (2.0f / 3.0f) * A0 - A1 * (1.0f / 12.0f);
-    o[2] = (2.0f / 3.0f) * A1;
-    o[3] = -(2.0f / 3.0f) * A0;
-    o[4] = A0 * (1.0f / 12.0f) - (2.0f / 3.0f) * A1;
-    o[5] = A1 * (1.0f / 12.0f);
-}
-
-__global__ __launch_bounds__(kBlock) void fine_phibar_kernel(
+__global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs,
     const float *__restrict__ abar, int n, int n_f, int nt, float c, float *__restrict__ phibar) {
     __shared__ uint32_t seg_pre[kASegs + 1];
     __shared__ uint32_t seg_src[kASegs];
-    __shared__ float acc[kTileFine * kTileFine * kTileFine];
-    __shared__ uint32_t scan_sh[kBlock / 64 + 1];
+    __shared__ float A[3 * kAN3];
+    __shared__ uint32_t scan_sh[kPhiBlock / 64 + 1];
     int tx, ty, tz;
     tile_of_block(blockIdx.x, nt, tx, ty, tz);
     const int tid = threadIdx.x;
     const int n_ios = nt * kTileIos;
     const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
-    for (int i = tid; i < kTileFine * kTileFine * kTileFine; i += kBlock) acc[i] = 0.0f;
+    for (int i = tid; i < 3 * kAN3; i += kPhiBlock) A[i] = 0.0f;
     uint32_t cnt[kASegPerThread], src[kASegPerThread], sum = 0;
 #pragma unroll
     for (int k = 0; k < kASegPerThread; ++k) {
@@ -67,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void fine_phibar_kernel(
         sum += cnt[k];
     }
     uint32_t total;
-    uint32_t pre = block_exclusive_scan(sum, scan_sh, total);
+    uint32_t pre = block_exclusive_scan<kPhiBlock>(sum, scan_sh, total);
 #pragma unroll
     for (int k = 0; k < kASegPerThread; ++k) {
         const int s = tid * kASegPerThread + k;
@@ -80,52 +75,73 @@ __global__ __launch_bounds__(kBlock) void fine_phibar_kernel(
     if (tid == 0) seg_pre[kASegs] = total;
     __syncthreads();
     const float inv = 1.0f / 32768.0f;
-    constexpr int T = kTileFine;
-    for (uint32_t v = tid; v < total; v += kBlock) {
-        const int s = seg_search(seg_pre, kASegs, v);
-        const uint32_t p = seg_src[s] + (v - seg_pre[s]);
-        const int b[3] = {s % kAB, (s / kAB) % kAB, s / (kAB * kAB)};
-        int j[3];
-        float w[3][2], ab[3];
+    constexpr int kBatch = 2;
+    for (uint32_t v0 = tid; v0 < total; v0 += kPhiBlock * kBatch) {
+        int sg[kBatch];
+        uint32_t o[kBatch][3];
+        float ab[kBatch][3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const uint32_t o = pos[(int64_t)d * n + p];
-            j[d] = 2 * (b[d] - 2) + (int)(o >> 15);
-            const int f = (int)(o & 0x7FFFu);
-            w[d][1] = (float)f * inv;
-            w[d][0] = (float)(32768 - f) * inv;
-            ab[d] = c * abar[(int64_t)d * n + p];
+        for (int k = 0; k < kBatch; ++k) {
+            const uint32_t v = v0 + k * kPhiBlock;
+            sg[k] = v < total ? seg_search(seg_pre, kASegs, v) : -1;
         }
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int e = d == 0 ? 1 : 0, f = d == 2 ? 1 : 2;  // the two other axes
-            float o[6];
-            stencil_t(w[d][0] * ab[d], w[d][1] * ab[d], o);
+        for (int k = 0; k < kBatch; ++k) {
+            if (sg[k] < 0) continue;
+            const uint32_t p = seg_src[sg[k]] + (v0 + k * kPhiBlock - seg_pre[sg[k]]);
 #pragma unroll
-            for (int se = 0; se < 2; ++se)
+            for (int d = 0; d < 3; ++d) {
+                o[k][d] = pos[(int64_t)d * n + p];
+                ab[k][d] = c * abar[(int64_t)d * n + p];
+            }
+        }
 #pragma unroll
-                for (int sf = 0; sf < 2; ++sf) {
-                    const int ne = j[e] + se, nf = j[f] + sf;
-                    if ((unsigned)ne >= (unsigned)T || (unsigned)nf >= (unsigned)T) continue;
-                    const float wef = w[e][se] * w[f][sf];
+        for (int k = 0; k < kBatch; ++k) {
+            if (sg[k] < 0) continue;
+            const int s = sg[k];
+            const int b[3] = {s % kAB, (s / kAB) % kAB, s / (kAB * kAB)};
+            int j[3];
+            float w[3][2];
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) {
-                        const int nd = j[d] - 2 + k;
-                        if ((unsigned)nd >= (unsigned)T) continue;
-                        int nn[3];
-                        nn[d] = nd;
-                        nn[e] = ne;
-                        nn[f] = nf;
-                        atomicAdd(&acc[(nn[2] * T + nn[1]) * T + nn[0]], wef * o[k]);
+            for (int d = 0; d < 3; ++d) {
+                j[d] = 2 * (b[d] - 2) + (int)(o[k][d] >> 15) + 2;  // node index in the 20^3 box
+                const int f = (int)(o[k][d] & 0x7FFFu);
+                w[d][1] = (float)f * inv;
+                w[d][0] = (float)(32768 - f) * inv;
+            }
+#pragma unroll
+            for (int sz = 0; sz < 2; ++sz)
+#pragma unroll
+                for (int sy = 0; sy < 2; ++sy) {
+                    const int nz = j[2] + sz, ny = j[1] + sy;
+                    if ((unsigned)nz >= (unsigned)kAN || (unsigned)ny >= (unsigned)kAN) continue;
+                    const float wyz = w[1][sy] * w[2][sz];
+#pragma unroll
+                    for (int sx = 0; sx < 2; ++sx) {
+                        const int nx = j[0] + sx;
+                        if ((unsigned)nx >= (unsigned)kAN) continue;
+                        const float W = wyz * w[0][sx];
+                        const int idx = (nz * kAN + ny) * kAN + nx;
+                        atomicAdd(&A[idx], W * ab[k][0]);
+                        atomicAdd(&A[kAN3 + idx], W * ab[k][1]);
+                        atomicAdd(&A[2 * kAN3 + idx], W * ab[k][2]);
                     }
                 }
         }
     }
     __syncthreads();
+    // phibar(m) = sum_d (2/3)(A_d(m+e_d) - A_d(m-e_d)) - (1/12)(A_d(m+2e_d) - A_d(m-2e_d))
+    constexpr int T = kTileFine;
     const int a0x = tx * T, a0y = ty * T, a0z = tz * T;
-    for (int i = tid; i < T * T * T; i += kBlock) {
+    for (int i = tid; i < T * T * T; i += kPhiBlock) {
         const int lx = i % T, ly = (i / T) % T, lz = i / (T * T);
-        phibar[((int64_t)(a0z + lz) * n_f + (a0y + ly)) * n_f + (a0x + lx)] = acc[i];
+        const int m = ((lz + 2) * kAN + ly + 2) * kAN + lx + 2;
+        const float *Ax = A, *Ay = A + kAN3, *Az = A + 2 * kAN3;
+        constexpr int SY = kAN, SZ = kAN * kAN;
+        float v = (2.0f / 3.0f) * (Ax[m + 1] - Ax[m - 1]) - (1.0f / 12.0f) * (Ax[m + 2] - Ax[m - 2]);
+        v += (2.0f / 3.0f) * (Ay[m + SY] - Ay[m - SY]) - (1.0f / 12.0f) * (Ay[m + 2 * SY] - Ay[m - 2 * SY]);
+        v += (2.0f / 3.0f) * (Az[m + SZ] - Az[m - SZ]) - (1.0f / 12.0f) * (Az[m + 2 * SZ] - Az[m - 2 * SZ]);
+        phibar[((int64_t)(a0z + lz) * n_f + (a0y + ly)) * n_f + (a0x + lx)] = v;
     }
 }
 
@@ -151,20 +167,35 @@ __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
     for (int i = tid; i <= kTileCells; i += kBlock) cst[i] = cs[key0 + i];
     __syncthreads();
     const float inv = 1.0f / 32768.0f;
-    for (uint32_t p = cst[0] + tid; p < cst[kTileCells]; p += kBlock) {
-        const int u = seg_search(cst, kTileCells, p);
-        const int uc[3] = {u & 7, (u >> 3) & 7, u >> 6};
-        int j[3];
-        float w[3][2], ab[3];
+    // Wave-uniform loop over the tile's particles.  An IOS cell lies in one
+    // coarse cell, so in a dense cell all lanes feed the same 8 nodes: the 24
+    // weighted values are then summed over the wave (fixed order) and one
+    // lane adds them, instead of 64 lanes contending for each address.
+    const int lane = tid & 63;
+    const uint32_t pbeg = cst[0], pend = cst[kTileCells];
+    for (uint32_t w0 = pbeg + (uint32_t)(tid - lane); w0 < pend; w0 += kBlock) {
+        const uint32_t p = w0 + lane;
+        const bool valid = p < pend;
+        int j[3] = {0, 0, 0};
+        float w[3][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}}, ab[3] = {0.f, 0.f, 0.f};
+        if (valid) {
+            const int u = seg_search(cst, kTileCells, p);
+            const int uc[3] = {u & 7, (u >> 3) & 7, u >> 6};
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const uint32_t q = ((uint32_t)uc[d] << 16) + pos[(int64_t)d * n + p];
-            j[d] = (int)(q >> (kFracBits + hshift));
-            const int f = (int)((q >> hshift) & 0x7FFFu);
-            w[d][1] = (float)f * inv;
-            w[d][0] = (float)(32768 - f) * inv;
-            ab[d] = c * abar[(int64_t)d * n + p];
+            for (int d = 0; d < 3; ++d) {
+                const uint32_t q = ((uint32_t)uc[d] << 16) + pos[(int64_t)d * n + p];
+                j[d] = (int)(q >> (kFracBits + hshift));
+                const int f = (int)((q >> hshift) & 0x7FFFu);
+                w[d][1] = (float)f * inv;
+                w[d][0] = (float)(32768 - f) * inv;
+                ab[d] = c * abar[(int64_t)d * n + p];
+            }
         }
+        const int key = valid ? (j[2] * NC + j[1]) * NC + j[0] : -1;
+        const unsigned long long vm = __ballot(valid);
+        const int lead = first_lane(vm);
+        const int key0 = __shfl(key, lead, 64);
+        const bool uniform = __ballot(valid && key != key0) == 0ull;
 #pragma unroll
         for (int sz = 0; sz < 2; ++sz)
 #pragma unroll
@@ -172,10 +203,20 @@ __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
 #pragma unroll
                 for (int sx = 0; sx < 2; ++sx) {
                     const float W = w[0][sx] * w[1][sy] * w[2][sz];
-                    const int idx = ((j[2] + sz) * NC + j[1] + sy) * NC + j[0] + sx;
-                    atomicAdd(&A[0][idx], W * ab[0]);
-                    atomicAdd(&A[1][idx], W * ab[1]);
-                    atomicAdd(&A[2][idx], W * ab[2]);
+                    const int off = (sz * NC + sy) * NC + sx;
+                    if (uniform) {
+                        const float t0 = wave_sum(W * ab[0]), t1 = wave_sum(W * ab[1]),
+                                    t2 = wave_sum(W * ab[2]);
+                        if (lane == lead) {
+                            atomicAdd(&A[0][key0 + off], t0);
+                            atomicAdd(&A[1][key0 + off], t1);
+                            atomicAdd(&A[2][key0 + off], t2);
+                        }
+                    } else if (valid) {
+                        atomicAdd(&A[0][key + off], W * ab[0]);
+                        atomicAdd(&A[1][key + off], W * ab[1]);
+                        atomicAdd(&A[2][key + off], W * ab[2]);
+                    }
                 }
     }
     __syncthreads();
@@ -375,7 +416,7 @@ int launch_pm_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, 
         if (r) return r;
     }
     // phibar of the fine level, then rhobar = K phibar in place
-    fine_phibar_kernel<<<blocks, kBlock, 0, s>>>(pos, cs, acc_bar, (int)n, ctx->n_f, nt,
+    fine_phibar_kernel<<<blocks, kPhiBlock, 0, s>>>(pos, cs, acc_bar, (int)n, ctx->n_f, nt,
                                                  (float)gm, bf);
     CUBE2_LAUNCH_CHECK();
     r = launch_potential(ctx, 0, bf, bf, spec, s);

@@ -139,6 +139,24 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
     return off + x - v;
 }
 
+// Sums over the 64 lanes of a wave (butterfly; every lane must be active).
+// The order of the additions is fixed, so float sums are deterministic.
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// Lane of the first set bit of a nonzero wave mask.
+__device__ __forceinline__ int first_lane(unsigned long long mask) {
+    return __ffsll((long long)mask) - 1;
+}
+
 // Copy the periodic S^3 block of an n^3 mesh starting at node (x0, y0, z0)
 // (wrapped) into LDS, x fastest.  The loads of one thread are issued as a
 // batch (all in flight before the LDS stores), so a block pays one memory

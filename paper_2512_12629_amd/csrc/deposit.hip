@@ -33,6 +33,81 @@ __global__ void fill_u64(unsigned long long *p, int64_t n) {
     if (i < n) p[i] = 0ull;
 }
 
+// Fine CIC weights of one particle of box segment b (IOS cell coordinates in
+// the 9^3 box, own cells at 1..8) with in-cell offsets o, added to the
+// tile's fine nodes that it reaches.
+__device__ __forceinline__ void deposit_fine(const int (&b)[3], const uint32_t (&o)[3],
+                                             unsigned long long *acc_f) {
+    int j[3];
+    uint32_t w[3][2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        j[d] = 2 * (b[d] - 1) + (int)(o[d] >> 15);  // fine cell rel. to the tile
+        const uint32_t f = o[d] & 0x7FFFu;
+        w[d][0] = 32768u - f;
+        w[d][1] = f;
+    }
+#pragma unroll
+    for (int sz = 0; sz < 2; ++sz)
+#pragma unroll
+        for (int sy = 0; sy < 2; ++sy) {
+            const int nz = j[2] + sz, ny = j[1] + sy;
+            if ((unsigned)nz >= (unsigned)kTileFine || (unsigned)ny >= (unsigned)kTileFine)
+                continue;
+            const uint32_t wyz = w[1][sy] * w[2][sz];  // <= 2^30
+#pragma unroll
+            for (int sx = 0; sx < 2; ++sx) {
+                const int nx = j[0] + sx;
+                if ((unsigned)nx >= (unsigned)kTileFine) continue;
+                atomicAdd(&acc_f[(nz * kTileFine + ny) * kTileFine + nx],
+                          (unsigned long long)wyz * w[0][sx]);
+            }
+        }
+}
+
+// Coarse CIC weights of the wave's own-tile particles (own = true), added to
+// the tile's coarse footprint.  Called by all 64 lanes.  An IOS cell lies in
+// one coarse cell, so in a dense cell every lane feeds the same 8 nodes:
+// then the 8 weights are summed over the wave first (exact integer sums) and
+// one lane adds them, instead of 64 lanes contending for each node.
+__device__ __forceinline__ void deposit_coarse_wave(bool own, const int (&b)[3],
+                                                    const uint32_t (&o)[3], int hshift, int NC,
+                                                    unsigned long long *acc_c) {
+    const unsigned long long om = __ballot(own);
+    if (om == 0ull) return;
+    int j[3];
+    uint32_t w[3][2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const uint32_t q = ((uint32_t)(b[d] - 1) << 16) + o[d];  // tile-relative
+        j[d] = (int)(q >> (kFracBits + hshift));
+        const uint32_t f = (q >> hshift) & 0x7FFFu;
+        w[d][0] = own ? 32768u - f : 0u;
+        w[d][1] = own ? f : 0u;
+    }
+    const int key = own ? (j[2] * NC + j[1]) * NC + j[0] : -1;
+    const int lead = first_lane(om);
+    const int key0 = __shfl(key, lead, 64);
+    const bool uniform = __ballot(own && key != key0) == 0ull;
+#pragma unroll
+    for (int sz = 0; sz < 2; ++sz)
+#pragma unroll
+        for (int sy = 0; sy < 2; ++sy) {
+            const uint32_t wyz = w[1][sy] * w[2][sz];
+#pragma unroll
+            for (int sx = 0; sx < 2; ++sx) {
+                const unsigned long long v = (unsigned long long)wyz * w[0][sx];
+                const int off = (sz * NC + sy) * NC + sx;
+                if (uniform) {
+                    const unsigned long long t = wave_sum(v);
+                    if ((int)(threadIdx.x & 63) == lead) atomicAdd(&acc_c[key0 + off], t);
+                } else if (own) {
+                    atomicAdd(&acc_c[key + off], v);
+                }
+            }
+        }
+}
+
 template <bool FINE, bool COARSE>
 __global__ __launch_bounds__(kBlock) void deposit_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs, int n, int n_f, int nt,
@@ -96,62 +171,24 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
     }
     __syncthreads();
 
-    for (uint32_t v = tid; v < total; v += kBlock) {
-        const int s = seg_search(seg_pre, kSegs, v);
-        const uint32_t p = seg_src[s] + (v - seg_pre[s]);
+    // The loop runs wave-uniformly (every lane of a wave takes the same
+    // trips) so that the coarse weights can be summed over the wave.
+    const int lane = tid & 63;
+    for (uint32_t w0 = (uint32_t)(tid - lane); w0 < total; w0 += kBlock) {
+        const uint32_t v = w0 + lane;
+        const bool valid = v < total;
+        int s = 0;
+        uint32_t o[3] = {0u, 0u, 0u};
+        if (valid) {
+            s = seg_search(seg_pre, kSegs, v);
+            const uint32_t p = seg_src[s] + (v - seg_pre[s]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) o[d] = pos[(int64_t)d * n + p];
+        }
         const int b[3] = {s % kBox, (s / kBox) % kBox, s / (kBox * kBox)};
-        uint32_t o[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) o[d] = pos[(int64_t)d * n + p];
-        if (FINE) {
-            int j[3];
-            uint32_t w[3][2];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                j[d] = 2 * (b[d] - 1) + (int)(o[d] >> 15);  // fine cell rel. to the tile
-                const uint32_t f = o[d] & 0x7FFFu;
-                w[d][0] = 32768u - f;
-                w[d][1] = f;
-            }
-#pragma unroll
-            for (int sz = 0; sz < 2; ++sz)
-#pragma unroll
-                for (int sy = 0; sy < 2; ++sy) {
-                    const int nz = j[2] + sz, ny = j[1] + sy;
-                    if ((unsigned)nz >= (unsigned)kTileFine || (unsigned)ny >= (unsigned)kTileFine)
-                        continue;
-                    const uint32_t wyz = w[1][sy] * w[2][sz];  // <= 2^30
-#pragma unroll
-                    for (int sx = 0; sx < 2; ++sx) {
-                        const int nx = j[0] + sx;
-                        if ((unsigned)nx >= (unsigned)kTileFine) continue;
-                        atomicAdd(&acc_f[(nz * kTileFine + ny) * kTileFine + nx],
-                                  (unsigned long long)wyz * w[0][sx]);
-                    }
-                }
-        }
-        if (COARSE && b[0] > 0 && b[1] > 0 && b[2] > 0) {
-            int j[3];
-            uint32_t w[3][2];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const uint32_t q = ((uint32_t)(b[d] - 1) << 16) + o[d];  // tile-relative
-                j[d] = (int)(q >> (kFracBits + hshift));
-                const uint32_t f = (q >> hshift) & 0x7FFFu;
-                w[d][0] = 32768u - f;
-                w[d][1] = f;
-            }
-#pragma unroll
-            for (int sz = 0; sz < 2; ++sz)
-#pragma unroll
-                for (int sy = 0; sy < 2; ++sy) {
-                    const uint32_t wyz = w[1][sy] * w[2][sz];
-#pragma unroll
-                    for (int sx = 0; sx < 2; ++sx)
-                        atomicAdd(&acc_c[((j[2] + sz) * NC + j[1] + sy) * NC + j[0] + sx],
-                                  (unsigned long long)wyz * w[0][sx]);
-                }
-        }
+        if (FINE && valid) deposit_fine(b, o, acc_f);
+        if (COARSE)
+            deposit_coarse_wave(valid && b[0] > 0 && b[1] > 0 && b[2] > 0, b, o, hshift, NC, acc_c);
     }
     __syncthreads();
 

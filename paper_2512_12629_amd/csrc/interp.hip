@@ -79,42 +79,63 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(
     __syncthreads();
     const uint32_t p0 = cst[0], p1 = cst[kTileCells];
     const T inv = T(1.0 / 32768.0);
-    for (uint32_t p = p0 + tid; p < p1; p += kBlock) {
-        const int u = seg_search(cst, kTileCells, p);
-        const int uc[3] = {u & 7, (u >> 3) & 7, u >> 6};
-        int jf[3], jc[3];
-        T wf[3][2], wc[3][2];
+    // two particles per thread at a time: both cell searches and all position
+    // loads are issued before the first particle is processed
+    constexpr int kBatch = 2;
+    for (uint32_t pb = p0 + tid; pb < p1; pb += kBlock * kBatch) {
+        int ub[kBatch];
+        uint32_t ob[kBatch][3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const uint32_t o = pos[(int64_t)d * n + p];
-            const int f = (int)(o & 0x7FFFu);
-            jf[d] = 2 * uc[d] + (int)(o >> 15) + 2;       // +2: LDS halo
-            wf[d][1] = (T)f * inv;
-            wf[d][0] = (T)(32768 - f) * inv;
-            if (TWO) {
-                const uint32_t q = ((uint32_t)uc[d] << 16) + o;  // tile-relative, 2^-15 units
-                const int fc = (int)((q >> hshift) & 0x7FFFu);
-                jc[d] = (int)(q >> (kFracBits + hshift)) + 2;
-                wc[d][1] = (T)fc * inv;
-                wc[d][0] = (T)(32768 - fc) * inv;
+        for (int k = 0; k < kBatch; ++k) {
+            const uint32_t p = pb + k * kBlock;
+            ub[k] = p < p1 ? seg_search(cst, kTileCells, p) : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            if (ub[k] < 0) continue;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ob[k][d] = pos[(int64_t)d * n + pb + k * kBlock];
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            if (ub[k] < 0) continue;
+            const uint32_t p = pb + k * kBlock;
+            const int u = ub[k];
+            const int uc[3] = {u & 7, (u >> 3) & 7, u >> 6};
+            int jf[3], jc[3];
+            T wf[3][2], wc[3][2];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const uint32_t o = ob[k][d];
+                const int f = (int)(o & 0x7FFFu);
+                jf[d] = 2 * uc[d] + (int)(o >> 15) + 2;       // +2: LDS halo
+                wf[d][1] = (T)f * inv;
+                wf[d][0] = (T)(32768 - f) * inv;
+                if (TWO) {
+                    const uint32_t q = ((uint32_t)uc[d] << 16) + o;  // tile-relative, 2^-15 units
+                    const int fc = (int)((q >> hshift) & 0x7FFFu);
+                    jc[d] = (int)(q >> (kFracBits + hshift)) + 2;
+                    wc[d][1] = (T)fc * inv;
+                    wc[d][0] = (T)(32768 - fc) * inv;
+                }
             }
-        }
-        T a[3];
-        gather(pf, kFS, jf[0], jf[1], jf[2], wf[0], wf[1], wf[2], a[0], a[1], a[2]);
-        a[0] *= scale_f;
-        a[1] *= scale_f;
-        a[2] *= scale_f;
-        if (TWO) {
-            T c[3];
-            gather(pc, CS, jc[0], jc[1], jc[2], wc[0], wc[1], wc[2], c[0], c[1], c[2]);
-            a[0] += scale_c * c[0];
-            a[1] += scale_c * c[1];
-            a[2] += scale_c * c[2];
-        }
+            T a[3];
+            gather(pf, kFS, jf[0], jf[1], jf[2], wf[0], wf[1], wf[2], a[0], a[1], a[2]);
+            a[0] *= scale_f;
+            a[1] *= scale_f;
+            a[2] *= scale_f;
+            if (TWO) {
+                T c[3];
+                gather(pc, CS, jc[0], jc[1], jc[2], wc[0], wc[1], wc[2], c[0], c[1], c[2]);
+                a[0] += scale_c * c[0];
+                a[1] += scale_c * c[1];
+                a[2] += scale_c * c[2];
+            }
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            T *dst = acc + (int64_t)d * n + p;
-            *dst = accumulate ? *dst + a[d] : a[d];
+            for (int d = 0; d < 3; ++d) {
+                T *dst = acc + (int64_t)d * n + p;
+                *dst = accumulate ? *dst + a[d] : a[d];
+            }
         }
     }
 }

@@ -210,18 +210,44 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
         const bool staged = ve - vb <= (uint32_t)CAP;
         if (c > 0) __syncthreads();  // previous chunk done with xs
         if (staged) {
-            for (uint32_t v = vb + tid; v < ve; v += kPPBlock) {
-                const int s = seg_search(seg_pre, kPSegs, v);
-                const uint32_t p = seg_src[s] + (v - seg_pre[s]);
-                const int bx = s % kPB, by = (s / kPB) % kPB, bz = s / (kPB * kPB);
-                float4 q;
-                q.x = (float)(2 * (bx - 1)) + (float)pos[p] * inv;
-                q.y = (float)(2 * (by - 1)) + (float)pos[(int64_t)n + p] * inv;
-                q.z = (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv;
-                q.w = 0.0f;
-                xs[v - vb] = q;
-                if (ADJ)
-                    as_[v - vb] = make_float4(abar[p], abar[(int64_t)n + p], abar[2 * (int64_t)n + p], 0.f);
+            // kStage particles per thread at a time: the segment searches and
+            // the loads of a batch are issued before the LDS stores
+            constexpr int kStage = 4;
+            for (uint32_t v0 = vb + tid; v0 < ve; v0 += kPPBlock * kStage) {
+                int sg[kStage];
+                uint32_t pj[kStage];
+#pragma unroll
+                for (int k = 0; k < kStage; ++k) {
+                    const uint32_t v = v0 + k * kPPBlock;
+                    sg[k] = v < ve ? seg_search(seg_pre, kPSegs, v) : -1;
+                    pj[k] = sg[k] < 0 ? 0u : seg_src[sg[k]] + (v - seg_pre[sg[k]]);
+                }
+                uint32_t o[kStage][3];
+                float4 ab[kStage];
+#pragma unroll
+                for (int k = 0; k < kStage; ++k) {
+                    if (sg[k] < 0) continue;
+                    const uint32_t p = pj[k];
+                    o[k][0] = pos[p];
+                    o[k][1] = pos[(int64_t)n + p];
+                    o[k][2] = pos[2 * (int64_t)n + p];
+                    if (ADJ)
+                        ab[k] = make_float4(abar[p], abar[(int64_t)n + p], abar[2 * (int64_t)n + p], 0.f);
+                }
+#pragma unroll
+                for (int k = 0; k < kStage; ++k) {
+                    if (sg[k] < 0) continue;
+                    const int s = sg[k];
+                    const int bx = s % kPB, by = (s / kPB) % kPB, bz = s / (kPB * kPB);
+                    float4 q;
+                    q.x = (float)(2 * (bx - 1)) + (float)o[k][0] * inv;
+                    q.y = (float)(2 * (by - 1)) + (float)o[k][1] * inv;
+                    q.z = (float)(2 * (bz - 1)) + (float)o[k][2] * inv;
+                    q.w = 0.0f;
+                    const uint32_t v = v0 + k * kPPBlock;
+                    xs[v - vb] = q;
+                    if (ADJ) as_[v - vb] = ab[k];
+                }
             }
         }
         __syncthreads();
