@@ -11,19 +11,54 @@
 // grad W of the CIC weights is piecewise constant: (1/H) (+-1) times the two
 // other weights (left-continuous at cell faces).
 //
+// The scatters of c*abar onto the meshes accumulate in LDS in 64-bit fixed
+// point (integer LDS atomics are an order of magnitude faster than FP32 ones
+// on gfx950, and integer sums are exact and order independent): a
+// contribution v becomes rint(v S) with S = 2^(41 - e), 2^e > c max|abar|, so
+// a node can take 2^21 contributions before its sum could leave 63 bits.
+//
 // The PP adjoint lives with the PP kernel (pp.hip).
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace cube2 {
 namespace {
 
+// max |x| over m floats as the bit pattern of a non-negative float (which
+// orders like the float); *out must be zero on entry
+__global__ void absmax_kernel(const float *__restrict__ x, int64_t m, unsigned int *out) {
+    float v = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        v = fmaxf(v, fabsf(x[i]));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(v));
+}
+
+__global__ void set_u32(unsigned int *p, unsigned int v) { *p = v; }
+
+// fixed-point scale S = 2^(41 - e) with c * max|abar| < 2^e
+__device__ __forceinline__ float fixed_scale(const unsigned int *amax_bits, float c) {
+    const float m = __uint_as_float(*amax_bits) * fabsf(c);
+    if (!(m > 0.0f) || !(m < 3.0e38f)) return 1.0f;
+    int e;
+    (void)frexpf(m, &e);
+    return ldexpf(1.0f, min(41 - e, 100));
+}
+
+__device__ __forceinline__ unsigned long long to_fixed(float v) {
+    return (unsigned long long)__float2ll_rn(v);
+}
+
 // ---------------------------------------------------------------------------
-// fine level: phibar on a 16^3 node tile.  The workgroup first scatters
-// c*abar with the CIC weights onto the nodes of the tile plus a 2-node halo
-// (20^3 nodes, 3 components, FP32 LDS atomics), from every particle whose
-// CIC footprint reaches that region (an 11^3 box of IOS cells: a particle in
-// fine cell j feeds nodes j and j+1), then applies the stencil transpose
-// phibar = D . Abar on the 16^3 interior from LDS.
+// fine level: phibar on a 16^3 node tile.  For each component d in turn, the
+// workgroup scatters c*abar_d with the CIC weights onto the nodes of the
+// tile plus a 2-node halo (20^3 nodes, fixed point in LDS), from every
+// particle whose CIC footprint reaches that region (an 11^3 box of IOS cells:
+// a particle in fine cell j feeds nodes j and j+1), then adds the d term of
+// the stencil transpose phibar = D . Abar on the 16^3 interior.
 // ---------------------------------------------------------------------------
 
 constexpr int kAB = kTileIos + 3;            // 11 IOS cells per axis: [c0-2, c0+9)
@@ -35,17 +70,17 @@ constexpr int kASegPerThread = (kASegs + kPhiBlock - 1) / kPhiBlock;  // 3
 
 __global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs,
-    const float *__restrict__ abar, int n, int n_f, int nt, float c, float *__restrict__ phibar) {
+    const float *__restrict__ abar, int n, int n_f, int nt, float c,
+    const unsigned int *__restrict__ amax_bits, float *__restrict__ phibar) {
     __shared__ uint32_t seg_pre[kASegs + 1];
     __shared__ uint32_t seg_src[kASegs];
-    __shared__ float A[3 * kAN3];
+    __shared__ unsigned long long A[kAN3];   // one component at a time, fixed point
     __shared__ uint32_t scan_sh[kPhiBlock / 64 + 1];
     int tx, ty, tz;
     tile_of_block(blockIdx.x, nt, tx, ty, tz);
     const int tid = threadIdx.x;
     const int n_ios = nt * kTileIos;
     const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
-    for (int i = tid; i < 3 * kAN3; i += kPhiBlock) A[i] = 0.0f;
     uint32_t cnt[kASegPerThread], src[kASegPerThread], sum = 0;
 #pragma unroll
     for (int k = 0; k < kASegPerThread; ++k) {
@@ -73,75 +108,86 @@ __global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
         pre += cnt[k];
     }
     if (tid == 0) seg_pre[kASegs] = total;
-    __syncthreads();
+    const float S = fixed_scale(amax_bits, c), invS = 1.0f / S;
+    const float cS = c * S;
     const float inv = 1.0f / 32768.0f;
-    constexpr int kBatch = 2;
-    for (uint32_t v0 = tid; v0 < total; v0 += kPhiBlock * kBatch) {
-        int sg[kBatch];
-        uint32_t o[kBatch][3];
-        float ab[kBatch][3];
-#pragma unroll
-        for (int k = 0; k < kBatch; ++k) {
-            const uint32_t v = v0 + k * kPhiBlock;
-            sg[k] = v < total ? seg_search(seg_pre, kASegs, v) : -1;
-        }
-#pragma unroll
-        for (int k = 0; k < kBatch; ++k) {
-            if (sg[k] < 0) continue;
-            const uint32_t p = seg_src[sg[k]] + (v0 + k * kPhiBlock - seg_pre[sg[k]]);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                o[k][d] = pos[(int64_t)d * n + p];
-                ab[k][d] = c * abar[(int64_t)d * n + p];
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kBatch; ++k) {
-            if (sg[k] < 0) continue;
-            const int s = sg[k];
-            const int b[3] = {s % kAB, (s / kAB) % kAB, s / (kAB * kAB)};
-            int j[3];
-            float w[3][2];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                j[d] = 2 * (b[d] - 2) + (int)(o[k][d] >> 15) + 2;  // node index in the 20^3 box
-                const int f = (int)(o[k][d] & 0x7FFFu);
-                w[d][1] = (float)f * inv;
-                w[d][0] = (float)(32768 - f) * inv;
-            }
-#pragma unroll
-            for (int sz = 0; sz < 2; ++sz)
-#pragma unroll
-                for (int sy = 0; sy < 2; ++sy) {
-                    const int nz = j[2] + sz, ny = j[1] + sy;
-                    if ((unsigned)nz >= (unsigned)kAN || (unsigned)ny >= (unsigned)kAN) continue;
-                    const float wyz = w[1][sy] * w[2][sz];
-#pragma unroll
-                    for (int sx = 0; sx < 2; ++sx) {
-                        const int nx = j[0] + sx;
-                        if ((unsigned)nx >= (unsigned)kAN) continue;
-                        const float W = wyz * w[0][sx];
-                        const int idx = (nz * kAN + ny) * kAN + nx;
-                        atomicAdd(&A[idx], W * ab[k][0]);
-                        atomicAdd(&A[kAN3 + idx], W * ab[k][1]);
-                        atomicAdd(&A[2 * kAN3 + idx], W * ab[k][2]);
-                    }
-                }
-        }
-    }
-    __syncthreads();
-    // phibar(m) = sum_d (2/3)(A_d(m+e_d) - A_d(m-e_d)) - (1/12)(A_d(m+2e_d) - A_d(m-2e_d))
     constexpr int T = kTileFine;
+    constexpr int NPT = T * T * T / kPhiBlock;   // interior nodes per thread
+    float out[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) out[k] = 0.0f;
+    // phibar(m) = sum_d (2/3)(A_d(m+e_d) - A_d(m-e_d)) - (1/12)(A_d(m+2e_d) - A_d(m-2e_d)),
+    // one component d per pass
+    for (int d = 0; d < 3; ++d) {
+        for (int i = tid; i < kAN3; i += kPhiBlock) A[i] = 0ull;
+        __syncthreads();
+        constexpr int kBatch = 2;
+        for (uint32_t v0 = tid; v0 < total; v0 += kPhiBlock * kBatch) {
+            int sg[kBatch];
+            uint32_t o[kBatch][3];
+            float ab[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const uint32_t v = v0 + k * kPhiBlock;
+                sg[k] = v < total ? seg_search(seg_pre, kASegs, v) : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                if (sg[k] < 0) continue;
+                const uint32_t p = seg_src[sg[k]] + (v0 + k * kPhiBlock - seg_pre[sg[k]]);
+#pragma unroll
+                for (int e = 0; e < 3; ++e) o[k][e] = pos[(int64_t)e * n + p];
+                ab[k] = cS * abar[(int64_t)d * n + p];
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                if (sg[k] < 0) continue;
+                const int s = sg[k];
+                const int b[3] = {s % kAB, (s / kAB) % kAB, s / (kAB * kAB)};
+                int j[3];
+                float w[3][2];
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    j[e] = 2 * (b[e] - 2) + (int)(o[k][e] >> 15) + 2;  // node in the 20^3 box
+                    const int f = (int)(o[k][e] & 0x7FFFu);
+                    w[e][1] = (float)f * inv;
+                    w[e][0] = (float)(32768 - f) * inv;
+                }
+#pragma unroll
+                for (int sz = 0; sz < 2; ++sz)
+#pragma unroll
+                    for (int sy = 0; sy < 2; ++sy) {
+                        const int nz = j[2] + sz, ny = j[1] + sy;
+                        if ((unsigned)nz >= (unsigned)kAN || (unsigned)ny >= (unsigned)kAN) continue;
+                        const float wyz = w[1][sy] * w[2][sz] * ab[k];
+#pragma unroll
+                        for (int sx = 0; sx < 2; ++sx) {
+                            const int nx = j[0] + sx;
+                            if ((unsigned)nx >= (unsigned)kAN) continue;
+                            atomicAdd(&A[(nz * kAN + ny) * kAN + nx], to_fixed(wyz * w[0][sx]));
+                        }
+                    }
+            }
+        }
+        __syncthreads();
+        const int st = d == 0 ? 1 : (d == 1 ? kAN : kAN * kAN);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int i = tid + k * kPhiBlock;
+            const int lx = i % T, ly = (i / T) % T, lz = i / (T * T);
+            const int m = ((lz + 2) * kAN + ly + 2) * kAN + lx + 2;
+            const long long d1 = (long long)(A[m + st] - A[m - st]);
+            const long long d2 = (long long)(A[m + 2 * st] - A[m - 2 * st]);
+            out[k] += invS * ((2.0f / 3.0f) * (float)d1 - (1.0f / 12.0f) * (float)d2);
+        }
+        __syncthreads();  // the next pass clears A
+    }
     const int a0x = tx * T, a0y = ty * T, a0z = tz * T;
-    for (int i = tid; i < T * T * T; i += kPhiBlock) {
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int i = tid + k * kPhiBlock;
         const int lx = i % T, ly = (i / T) % T, lz = i / (T * T);
-        const int m = ((lz + 2) * kAN + ly + 2) * kAN + lx + 2;
-        const float *Ax = A, *Ay = A + kAN3, *Az = A + 2 * kAN3;
-        constexpr int SY = kAN, SZ = kAN * kAN;
-        float v = (2.0f / 3.0f) * (Ax[m + 1] - Ax[m - 1]) - (1.0f / 12.0f) * (Ax[m + 2] - Ax[m - 2]);
-        v += (2.0f / 3.0f) * (Ay[m + SY] - Ay[m - SY]) - (1.0f / 12.0f) * (Ay[m + 2 * SY] - Ay[m - 2 * SY]);
-        v += (2.0f / 3.0f) * (Az[m + SZ] - Az[m - SZ]) - (1.0f / 12.0f) * (Az[m + 2 * SZ] - Az[m - 2 * SZ]);
-        phibar[((int64_t)(a0z + lz) * n_f + (a0y + ly)) * n_f + (a0x + lx)] = v;
+        phibar[((int64_t)(a0z + lz) * n_f + (a0y + ly)) * n_f + (a0x + lx)] = out[k];
     }
 }
 
@@ -155,14 +201,15 @@ constexpr int kCN = kTileFine / 2 + 1;  // 9 coarse nodes per axis (ratio 2)
 __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs,
     const float *__restrict__ abar, int n, int nt, int n_c, int hshift, float c,
-    float *__restrict__ Amesh) {
-    __shared__ float A[3][kCN * kCN * kCN];
+    const unsigned int *__restrict__ amax_bits, float *__restrict__ Amesh) {
+    __shared__ unsigned long long A[3][kCN * kCN * kCN];   // fixed point
     __shared__ uint32_t cst[kTileCells + 1];
     int tx, ty, tz;
     tile_of_block(blockIdx.x, nt, tx, ty, tz);
     const int tid = threadIdx.x;
     const int NC = (kTileFine >> hshift) + 1;
-    for (int i = tid; i < 3 * kCN * kCN * kCN; i += kBlock) (&A[0][0])[i] = 0.0f;
+    for (int i = tid; i < 3 * kCN * kCN * kCN; i += kBlock) (&A[0][0])[i] = 0ull;
+    const float S = fixed_scale(amax_bits, c), invS = 1.0f / S;
     const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
     for (int i = tid; i <= kTileCells; i += kBlock) cst[i] = cs[key0 + i];
     __syncthreads();
@@ -188,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
                 const int f = (int)((q >> hshift) & 0x7FFFu);
                 w[d][1] = (float)f * inv;
                 w[d][0] = (float)(32768 - f) * inv;
-                ab[d] = c * abar[(int64_t)d * n + p];
+                ab[d] = c * S * abar[(int64_t)d * n + p];
             }
         }
         const int key = valid ? (j[2] * NC + j[1]) * NC + j[0] : -1;
@@ -204,18 +251,20 @@ __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
                 for (int sx = 0; sx < 2; ++sx) {
                     const float W = w[0][sx] * w[1][sy] * w[2][sz];
                     const int off = (sz * NC + sy) * NC + sx;
+                    const unsigned long long q0 = to_fixed(W * ab[0]), q1 = to_fixed(W * ab[1]),
+                                             q2 = to_fixed(W * ab[2]);
                     if (uniform) {
-                        const float t0 = wave_sum(W * ab[0]), t1 = wave_sum(W * ab[1]),
-                                    t2 = wave_sum(W * ab[2]);
+                        const unsigned long long t0 = wave_sum(q0), t1 = wave_sum(q1),
+                                                 t2 = wave_sum(q2);
                         if (lane == lead) {
                             atomicAdd(&A[0][key0 + off], t0);
                             atomicAdd(&A[1][key0 + off], t1);
                             atomicAdd(&A[2][key0 + off], t2);
                         }
                     } else if (valid) {
-                        atomicAdd(&A[0][key + off], W * ab[0]);
-                        atomicAdd(&A[1][key + off], W * ab[1]);
-                        atomicAdd(&A[2][key + off], W * ab[2]);
+                        atomicAdd(&A[0][key + off], q0);
+                        atomicAdd(&A[1][key + off], q1);
+                        atomicAdd(&A[2][key + off], q2);
                     }
                 }
     }
@@ -228,8 +277,8 @@ __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
         const int64_t g = ((int64_t)wrapn(A0z + lz, n_c) * n_c + wrapn(A0y + ly, n_c)) * n_c +
                           wrapn(A0x + lx, n_c);
         for (int d = 0; d < 3; ++d) {
-            const float v = A[d][i];
-            if (v != 0.0f) atomicAdd(&Amesh[d * m + g], v);
+            const long long q = (long long)A[d][i];
+            if (q != 0) atomicAdd(&Amesh[d * m + g], (float)q * invS);
         }
     }
 }
@@ -415,9 +464,19 @@ int launch_pm_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, 
         r = launch_potential(ctx, l, m, m, spec, s);
         if (r) return r;
     }
+    // max |abar| for the fixed-point scale of the scatters
+    unsigned int *amax = reinterpret_cast<unsigned int *>(work + L.red);
+    set_u32<<<1, 1, 0, s>>>(amax, 0u);
+    CUBE2_LAUNCH_CHECK();
+    if (n > 0) {
+        const int64_t m3 = 3 * n;
+        const unsigned gb = (unsigned)std::min<int64_t>(4096, (m3 + 255) / 256);
+        absmax_kernel<<<gb, 256, 0, s>>>(acc_bar, m3, amax);
+        CUBE2_LAUNCH_CHECK();
+    }
     // phibar of the fine level, then rhobar = K phibar in place
     fine_phibar_kernel<<<blocks, kPhiBlock, 0, s>>>(pos, cs, acc_bar, (int)n, ctx->n_f, nt,
-                                                 (float)gm, bf);
+                                                 (float)gm, amax, bf);
     CUBE2_LAUNCH_CHECK();
     r = launch_potential(ctx, 0, bf, bf, spec, s);
     if (r) return r;
@@ -431,7 +490,7 @@ int launch_pm_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, 
         fill_f32<<<(unsigned)((3 * m + 255) / 256), 256, 0, s>>>(Am, 3 * m);
         CUBE2_LAUNCH_CHECK();
         coarse_abar_kernel<<<blocks, kBlock, 0, s>>>(pos, cs, acc_bar, (int)n, nt, C.n, C.hshift,
-                                                     cc, Am);
+                                                     cc, amax, Am);
         CUBE2_LAUNCH_CHECK();
         divergence_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(Am, C.n, bc);
         CUBE2_LAUNCH_CHECK();
