@@ -67,8 +67,10 @@ WorkLayout work_layout(const cube2_ctx *c, int64_t n) {
     L.vals = take(nn * 4);
     L.keys2 = take(nn * 4);
     L.vals2 = take(nn * 4);
-    size_t nblk = (nn + 4095) / 4096;
+    const size_t ntiles = (size_t)c->nt * c->nt * c->nt;
+    size_t nblk = (std::max(nn, ntiles) + 4095) / 4096;
     L.hist = take(nblk * 256 * 4 + 1024);
+    L.tile_order = take(ntiles * 4 * sizeof(uint32_t));
     L.counts = take((size_t)(c->n_cells + 1) * 4);
     const size_t scan_len = std::max((size_t)(c->n_cells + 1), nblk * 256);
     L.scan_tmp = take((scan_len / 1024 + 64) * 4 * 2 + 4096);
@@ -271,7 +273,7 @@ int cube2_pp_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_sta
         if (!accumulate) CUBE2_CHECK_HIP(hipMemsetAsync(acc, 0, (size_t)n * 3 * 4, s));
         return CUBE2_OK;
     }
-    return launch_pp(ctx, pos, cell_start, n, acc, accumulate, s);
+    return launch_pp(ctx, pos, cell_start, n, acc, accumulate, work_, L_, s);
 }
 
 int cube2_kick_drift(cube2_ctx *ctx, const uint16_t *pos_in, const uint32_t *cell_start_in,
@@ -345,15 +347,14 @@ int cube2_pp_force_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t 
     CHECK_READY();
     if (n < 0 || n > INT32_MAX || !cell_start || (n > 0 && (!pos || !acc_bar || !x_bar)))
         return CUBE2_EINVAL;
-    (void)work;
-    (void)work_bytes;
+    CHECK_WORK(n);
     if (n == 0) return CUBE2_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (ctx->cfg.flags & CUBE2_PP_OFF) {
         if (!accumulate) CUBE2_CHECK_HIP(hipMemsetAsync(x_bar, 0, (size_t)n * 3 * 4, s));
         return CUBE2_OK;
     }
-    return launch_pp_backward(ctx, pos, cell_start, n, acc_bar, x_bar, accumulate, s);
+    return launch_pp_backward(ctx, pos, cell_start, n, acc_bar, x_bar, accumulate, work_, L_, s);
 }
 
 int cube2_kick_drift_backward(cube2_ctx *ctx, int64_t n, const int32_t *perm,

@@ -69,6 +69,7 @@ struct WorkLayout {
     size_t real_f, real_c, bar_f, bar_c, spec, coarse_acc;
     size_t real64_f, real64_c, spec64;  // FP64 form (zero-sized without it)
     size_t keys, vals, keys2, vals2, hist, counts, scan_tmp, offs_tmp, red;
+    size_t tile_order;  // 4 x (tiles) uint32: PP tile order and its sort buffers
     size_t total;
 };
 
@@ -223,8 +224,10 @@ int launch_fx_to_f64(uint64_t *buf, int64_t m, hipStream_t s);
 int launch_interp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                   const float *phi_f, const float *phi_c, float *acc, int accumulate,
                   hipStream_t s);
+int launch_order_tiles(cube2_ctx *ctx, const uint32_t *cs, unsigned char *work,
+                       const WorkLayout &L, hipStream_t s);
 int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, float *acc,
-              int accumulate, hipStream_t s);
+              int accumulate, unsigned char *work, const WorkLayout &L, hipStream_t s);
 void build_pair_table(cube2_ctx *ctx);
 int launch_kick_drift(cube2_ctx *ctx, const uint16_t *pos_in, const uint32_t *cs_in,
                       const float *vel_in, const float *acc, int64_t n, double kick,
@@ -240,7 +243,8 @@ int launch_pm_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, 
                        const float *acc_bar, float *x_bar, int accumulate, unsigned char *work,
                        const WorkLayout &L, hipStream_t s);
 int launch_pp_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
-                       const float *acc_bar, float *x_bar, int accumulate, hipStream_t s);
+                       const float *acc_bar, float *x_bar, int accumulate, unsigned char *work,
+                       const WorkLayout &L, hipStream_t s);
 int launch_kick_drift_backward(cube2_ctx *ctx, int64_t n, const int32_t *perm,
                                const float *xbar_out, const float *vbar_out, double kick,
                                double drift, float *xbar_in, float *vbar_in, float *acc_bar,

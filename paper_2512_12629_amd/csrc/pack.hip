@@ -170,7 +170,46 @@ __global__ void gather_offsets(const uint32_t *__restrict__ perm, const uint16_t
     if (perm_out) perm_out[i] = (int32_t)p;
 }
 
+// Tiles in dispatch order b (the XCD-slab order of tile_of_block), keyed by
+// how many thousand particles they own, largest first.
+__global__ void tile_keys_kernel(const uint32_t *__restrict__ cs, int nt, uint32_t *__restrict__ keys,
+                                 uint32_t *__restrict__ vals) {
+    const int ntiles = nt * nt * nt;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= ntiles) return;
+    int tx, ty, tz;
+    tile_of_block(b, nt, tx, ty, tz);
+    const uint32_t t = (uint32_t)((tz * nt + ty) * nt + tx);
+    const uint32_t cnt = cs[(t + 1) * kTileCells] - cs[t * kTileCells];
+    keys[b] = 255u - min(cnt >> 10, 255u);
+    vals[b] = t;
+}
+
 }  // namespace
+
+// PP work order: the tiles sorted (stably, one 8-bit radix pass) by their
+// particle count in units of 1024, descending, so that the heaviest tiles
+// start first and the light ones keep the XCD-slab order.  The tile indices
+// land in the first ntiles words of the tile_order region.
+int launch_order_tiles(cube2_ctx *ctx, const uint32_t *cs, unsigned char *work,
+                       const WorkLayout &L, hipStream_t s) {
+    const int nt = ctx->nt;
+    const int ntiles = nt * nt * nt;
+    uint32_t *base = reinterpret_cast<uint32_t *>(work + L.tile_order);
+    uint32_t *order = base, *vin = base + ntiles, *kin = base + 2 * ntiles, *kout = base + 3 * ntiles;
+    uint32_t *tmp = reinterpret_cast<uint32_t *>(work + L.scan_tmp);
+    uint32_t *ghist = reinterpret_cast<uint32_t *>(work + L.hist);
+    tile_keys_kernel<<<(ntiles + 255) / 256, 256, 0, s>>>(cs, nt, kin, vin);
+    CUBE2_LAUNCH_CHECK();
+    const int nblk = (ntiles + kSortTile - 1) / kSortTile;
+    radix_count<<<nblk, kBlock, 0, s>>>(kin, ntiles, 0, nblk, ghist);
+    CUBE2_LAUNCH_CHECK();
+    int r = exclusive_scan(ghist, ghist, (int64_t)nblk * 256, tmp, s);
+    if (r) return r;
+    radix_scatter<<<nblk, kBlock, 0, s>>>(kin, vin, kout, order, ntiles, 0, nblk, ghist);
+    CUBE2_LAUNCH_CHECK();
+    return CUBE2_OK;
+}
 
 // keys/vals (work) and offs_tmp (work) hold the unsorted particles.
 int launch_sort_by_cell(cube2_ctx *ctx, int64_t n64, const uint16_t *offs, uint16_t *pos,

@@ -134,7 +134,8 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                                                      int nt, const float4 *__restrict__ table,
                                                      int K, float kinv, float gm,
                                                      const float *__restrict__ abar,
-                                                     float *__restrict__ acc, int accumulate) {
+                                                     float *__restrict__ acc, int accumulate,
+                                                     const uint32_t *__restrict__ order) {
     constexpr int CAP = PPGeo<ADJ>::CAP;
     constexpr int kPPBlock = PPGeo<ADJ>::BLOCK;
     constexpr int kPSegPerThread = PPGeo<ADJ>::SEG_PER_THREAD;
@@ -147,7 +148,13 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
     __shared__ int chunk_sh;
 
     int tx, ty, tz;
-    tile_of_block(blockIdx.x, nt, tx, ty, tz);
+    {
+        // heaviest tiles first (see launch_order_tiles)
+        const int t = (int)order[blockIdx.x];
+        tx = t % nt;
+        ty = (t / nt) % nt;
+        tz = t / (nt * nt);
+    }
     const int tid = threadIdx.x;
     const int n_ios = nt * kTileIos;
     const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
@@ -414,23 +421,30 @@ void build_pair_table(cube2_ctx *ctx) {
 }
 
 int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, float *acc,
-              int accumulate, hipStream_t s) {
+              int accumulate, unsigned char *work, const WorkLayout &L, hipStream_t s) {
     const float4 *table = reinterpret_cast<const float4 *>(ctx->tables + ctx->pp_off);
     const int nt = ctx->nt;
+    int r = launch_order_tiles(ctx, cs, work, L, s);
+    if (r) return r;
+    const uint32_t *order = reinterpret_cast<const uint32_t *>(work + L.tile_order);
     pp_kernel<false><<<(unsigned)(nt * nt * nt), PPGeo<false>::BLOCK, 0, s>>>(
         pos, cs, (int)n, nt, table, ctx->pp_K, ctx->pp_kinv,
-        (float)(ctx->cfg.g_newton * ctx->cfg.m_p), nullptr, acc, accumulate);
+        (float)(ctx->cfg.g_newton * ctx->cfg.m_p), nullptr, acc, accumulate, order);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }
 
 int launch_pp_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
-                       const float *acc_bar, float *x_bar, int accumulate, hipStream_t s) {
+                       const float *acc_bar, float *x_bar, int accumulate, unsigned char *work,
+                       const WorkLayout &L, hipStream_t s) {
     const float4 *table = reinterpret_cast<const float4 *>(ctx->tables + ctx->pp_off);
     const int nt = ctx->nt;
+    int r = launch_order_tiles(ctx, cs, work, L, s);
+    if (r) return r;
+    const uint32_t *order = reinterpret_cast<const uint32_t *>(work + L.tile_order);
     pp_kernel<true><<<(unsigned)(nt * nt * nt), PPGeo<true>::BLOCK, 0, s>>>(
         pos, cs, (int)n, nt, table, ctx->pp_K, ctx->pp_kinv,
-        (float)(ctx->cfg.g_newton * ctx->cfg.m_p), acc_bar, x_bar, accumulate);
+        (float)(ctx->cfg.g_newton * ctx->cfg.m_p), acc_bar, x_bar, accumulate, order);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }
