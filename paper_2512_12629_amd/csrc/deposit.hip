@@ -172,23 +172,37 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
     __syncthreads();
 
     // The loop runs wave-uniformly (every lane of a wave takes the same
-    // trips) so that the coarse weights can be summed over the wave.
+    // trips) so that the coarse weights can be summed over the wave; each
+    // trip takes kBatch particles per lane, whose segment searches and
+    // position loads are all issued before the first deposit.
+    constexpr int kBatch = 4;
     const int lane = tid & 63;
-    for (uint32_t w0 = (uint32_t)(tid - lane); w0 < total; w0 += kBlock) {
-        const uint32_t v = w0 + lane;
-        const bool valid = v < total;
-        int s = 0;
-        uint32_t o[3] = {0u, 0u, 0u};
-        if (valid) {
-            s = seg_search(seg_pre, kSegs, v);
-            const uint32_t p = seg_src[s] + (v - seg_pre[s]);
+    for (uint32_t w0 = (uint32_t)(tid - lane); w0 < total; w0 += kBlock * kBatch) {
+        int sg[kBatch];
+        uint32_t o[kBatch][3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) o[d] = pos[(int64_t)d * n + p];
+        for (int k = 0; k < kBatch; ++k) {
+            const uint32_t v = w0 + k * kBlock + lane;
+            sg[k] = v < total ? seg_search(seg_pre, kSegs, v) : -1;
         }
-        const int b[3] = {s % kBox, (s / kBox) % kBox, s / (kBox * kBox)};
-        if (FINE && valid) deposit_fine(b, o, acc_f);
-        if (COARSE)
-            deposit_coarse_wave(valid && b[0] > 0 && b[1] > 0 && b[2] > 0, b, o, hshift, NC, acc_c);
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            o[k][0] = o[k][1] = o[k][2] = 0u;
+            if (sg[k] < 0) continue;
+            const uint32_t p = seg_src[sg[k]] + (w0 + k * kBlock + lane - seg_pre[sg[k]]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) o[k][d] = pos[(int64_t)d * n + p];
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const bool valid = sg[k] >= 0;
+            const int s = valid ? sg[k] : 0;
+            const int b[3] = {s % kBox, (s / kBox) % kBox, s / (kBox * kBox)};
+            if (FINE && valid) deposit_fine(b, o[k], acc_f);
+            if (COARSE)
+                deposit_coarse_wave(valid && b[0] > 0 && b[1] > 0 && b[2] > 0, b, o[k], hshift, NC,
+                                    acc_c);
+        }
     }
     __syncthreads();
 

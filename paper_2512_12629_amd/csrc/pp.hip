@@ -135,7 +135,8 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                                                      int K, float kinv, float gm,
                                                      const float *__restrict__ abar,
                                                      float *__restrict__ acc, int accumulate,
-                                                     const uint32_t *__restrict__ order) {
+                                                     const uint32_t *__restrict__ order,
+                                                     uint32_t *__restrict__ queue, int ntiles) {
     constexpr int CAP = PPGeo<ADJ>::CAP;
     constexpr int kPPBlock = PPGeo<ADJ>::BLOCK;
     constexpr int kPSegPerThread = PPGeo<ADJ>::SEG_PER_THREAD;
@@ -145,197 +146,248 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
     __shared__ float4 as_[ADJ ? CAP : 1];
     __shared__ uint32_t cst[kTileCells + 1];     // own cells: particle starts (tile-relative)
     __shared__ uint32_t scan_sh[kPPBlock / 64 + 1];
-    __shared__ int chunk_sh;
+    __shared__ int chunk_sh, tile_sh;
+    __shared__ uint32_t maxcnt_sh;
 
-    int tx, ty, tz;
-    {
-        // heaviest tiles first (see launch_order_tiles)
-        const int t = (int)order[blockIdx.x];
-        tx = t % nt;
-        ty = (t / nt) % nt;
-        tz = t / (nt * nt);
-    }
     const int tid = threadIdx.x;
     const int n_ios = nt * kTileIos;
-    const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
+    const float inv = 1.0f / 32768.0f;
     for (int i = tid; i < 3 * (K + 1); i += kPPBlock) pair_rows[i] = table[i];
 
-    // particle ranges of the 10^3 box of IOS cells [c0-1, c0+9)
-    uint32_t cnt[kPSegPerThread], src[kPSegPerThread], sum = 0;
-#pragma unroll
-    for (int k = 0; k < kPSegPerThread; ++k) {
-        const int s = tid * kPSegPerThread + k;
-        cnt[k] = 0;
-        src[k] = 0;
-        if (s < kPSegs) {
-            const int bx = s % kPB, by = (s / kPB) % kPB, bz = s / (kPB * kPB);
-            const uint32_t key = cell_key(wrapn(c0x + bx - 1, n_ios), wrapn(c0y + by - 1, n_ios),
-                                          wrapn(c0z + bz - 1, n_ios), nt);
-            src[k] = cs[key];
-            cnt[k] = cs[key + 1] - src[k];
-        }
-        sum += cnt[k];
-    }
-    uint32_t total;
-    uint32_t pre = block_exclusive_scan<kPPBlock>(sum, scan_sh, total);
-#pragma unroll
-    for (int k = 0; k < kPSegPerThread; ++k) {
-        const int s = tid * kPSegPerThread + k;
-        if (s < kPSegs) {
-            seg_pre[s] = pre;
-            seg_src[s] = src[k];
-        }
-        pre += cnt[k];
-    }
-    // own cells: particle starts relative to the tile's first particle
-    const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
-    const uint32_t p0 = cs[key0];
-    for (int i = tid; i < kTileCells; i += kPPBlock) cst[i] = cs[key0 + i] - p0;
-    if (tid == 0) {
-        seg_pre[kPSegs] = total;
-        cst[kTileCells] = cs[key0 + kTileCells] - p0;
-        // z-chunks: the smallest power-of-two count whose staged slices fit
-        int C = 1;
-        for (; C < 8; C <<= 1) {
-            bool fits = true;
-            for (int c = 0; c < C; ++c) {
-                const int z0 = c * 8 / C, z1 = (c + 1) * 8 / C;
-                if (seg_pre[(z1 + 2) * kPB * kPB] - seg_pre[z0 * kPB * kPB] > (uint32_t)CAP)
-                    fits = false;
-            }
-            if (fits) break;
-        }
-        chunk_sh = C;
-    }
-    __syncthreads();
-    const int C = chunk_sh;
-    const float inv = 1.0f / 32768.0f;
-
-    for (int c = 0; c < C; ++c) {
-        const int z0 = c * 8 / C, z1 = (c + 1) * 8 / C;
-        const uint32_t vb = seg_pre[z0 * kPB * kPB], ve = seg_pre[(z1 + 2) * kPB * kPB];
-        const bool staged = ve - vb <= (uint32_t)CAP;
-        if (c > 0) __syncthreads();  // previous chunk done with xs
-        if (staged) {
-            // kStage particles per thread at a time: the segment searches and
-            // the loads of a batch are issued before the LDS stores
-            constexpr int kStage = 4;
-            for (uint32_t v0 = vb + tid; v0 < ve; v0 += kPPBlock * kStage) {
-                int sg[kStage];
-                uint32_t pj[kStage];
-#pragma unroll
-                for (int k = 0; k < kStage; ++k) {
-                    const uint32_t v = v0 + k * kPPBlock;
-                    sg[k] = v < ve ? seg_search(seg_pre, kPSegs, v) : -1;
-                    pj[k] = sg[k] < 0 ? 0u : seg_src[sg[k]] + (v - seg_pre[sg[k]]);
-                }
-                uint32_t o[kStage][3];
-                float4 ab[kStage];
-#pragma unroll
-                for (int k = 0; k < kStage; ++k) {
-                    if (sg[k] < 0) continue;
-                    const uint32_t p = pj[k];
-                    o[k][0] = pos[p];
-                    o[k][1] = pos[(int64_t)n + p];
-                    o[k][2] = pos[2 * (int64_t)n + p];
-                    if (ADJ)
-                        ab[k] = make_float4(abar[p], abar[(int64_t)n + p], abar[2 * (int64_t)n + p], 0.f);
-                }
-#pragma unroll
-                for (int k = 0; k < kStage; ++k) {
-                    if (sg[k] < 0) continue;
-                    const int s = sg[k];
-                    const int bx = s % kPB, by = (s / kPB) % kPB, bz = s / (kPB * kPB);
-                    float4 q;
-                    q.x = (float)(2 * (bx - 1)) + (float)o[k][0] * inv;
-                    q.y = (float)(2 * (by - 1)) + (float)o[k][1] * inv;
-                    q.z = (float)(2 * (bz - 1)) + (float)o[k][2] * inv;
-                    q.w = 0.0f;
-                    const uint32_t v = v0 + k * kPPBlock;
-                    xs[v - vb] = q;
-                    if (ADJ) as_[v - vb] = ab[k];
-                }
-            }
+    // Persistent workgroups: each takes the next tile of the heaviest-first
+    // order from a global counter until the order is exhausted (the exit
+    // test is block-uniform).
+    for (;;) {
+        if (tid == 0) {
+            tile_sh = (int)atomicAdd(queue, 1u);
+            maxcnt_sh = 0u;
         }
         __syncthreads();
-        // own particles of the cells [z0*64, z1*64): a contiguous range
-        const uint32_t q0 = cst[z0 * 64], q1 = cst[z1 * 64];
-        for (uint32_t lp = q0 + tid; lp < q1; lp += kPPBlock) {
-            const int u = seg_search(cst, kTileCells, lp);
-            const uint32_t p = p0 + lp;
-            const int bx = (u & 7) + 1, by = ((u >> 3) & 7) + 1, bz = (u >> 6) + 1;
-            const float xi = (float)(2 * (bx - 1)) + (float)pos[p] * inv;
-            const float yi = (float)(2 * (by - 1)) + (float)pos[(int64_t)n + p] * inv;
-            const float zi = (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv;
-            float aix = 0.f, aiy = 0.f, aiz = 0.f;
-            if (ADJ) {
-                aix = abar[p];
-                aiy = abar[(int64_t)n + p];
-                aiz = abar[2 * (int64_t)n + p];
-            }
-            float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
-            if (staged) {
-                // the three x-neighbours of a cell are consecutive box segments,
-                // so the 27 neighbour cells are 9 contiguous ranges of xs
-                for (int row = 0; row < 9; ++row) {
-                    const int oy = row % 3 - 1, oz = row / 3 - 1;
-                    const int sm = ((bz + oz) * kPB + (by + oy)) * kPB + bx;
-                    const uint32_t v0 = seg_pre[sm - 1] - vb, v1 = seg_pre[sm + 2] - vb;
-                    float fx = 0.f, fy = 0.f, fz = 0.f;
-                    uint32_t v = v0;
-                    if (ADJ) {
-                        for (; v < v1; ++v) {
-                            const float4 qa = xs[v], aa = as_[v];
-                            pair_adjoint(qa.x - xi, qa.y - yi, qa.z - zi, aa.x - aix, aa.y - aiy,
-                                         aa.z - aiz, kinv, K, fx, fy, fz);
-                        }
-                    } else {
-                        for (; v + 1 < v1; v += 2) {
-                            const float4 qa = xs[v], qb = xs[v + 1];
-                            pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, kinv, K, fx, fy, fz);
-                            pair_accumulate(qb.x - xi, qb.y - yi, qb.z - zi, kinv, K, fx, fy, fz);
-                        }
-                        if (v < v1) {
-                            const float4 qa = xs[v];
-                            pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, kinv, K, fx, fy, fz);
-                        }
-                    }
-                    kahan_add(sx, cx, fx);
-                    kahan_add(sy, cy, fy);
-                    kahan_add(sz, cz, fz);
-                }
-            } else {
-                for (int nb = 0; nb < 27; ++nb) {
-                    const int ox = nb % 3 - 1, oy = (nb / 3) % 3 - 1, oz = nb / 9 - 1;
-                    const int s = ((bz + oz) * kPB + (by + oy)) * kPB + (bx + ox);
-                    const uint32_t v0 = seg_pre[s], v1 = seg_pre[s + 1];
-                    const float bxo = (float)(2 * (bx + ox - 1)), byo = (float)(2 * (by + oy - 1)),
-                                bzo = (float)(2 * (bz + oz - 1));
-                    float fx = 0.f, fy = 0.f, fz = 0.f;
-                    for (uint32_t v = v0; v < v1; ++v) {
-                        const uint32_t pj = seg_src[s] + (v - v0);
-                        const float xj = bxo + (float)pos[pj] * inv;
-                        const float yj = byo + (float)pos[(int64_t)n + pj] * inv;
-                        const float zj = bzo + (float)pos[2 * (int64_t)n + pj] * inv;
-                        if (ADJ)
-                            pair_adjoint(xj - xi, yj - yi, zj - zi, abar[pj] - aix,
-                                         abar[(int64_t)n + pj] - aiy, abar[2 * (int64_t)n + pj] - aiz,
-                                         kinv, K, fx, fy, fz);
-                        else
-                            pair_accumulate(xj - xi, yj - yi, zj - zi, kinv, K, fx, fy, fz);
-                    }
-                    kahan_add(sx, cx, fx);
-                    kahan_add(sy, cy, fy);
-                    kahan_add(sz, cz, fz);
-                }
-            }
-            const float a[3] = {gm * sx, gm * sy, gm * sz};
+        const int ti = tile_sh;
+        if (ti >= ntiles) break;
+        const int t = (int)order[ti];
+        const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
+        const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
+
+        // particle ranges of the 10^3 box of IOS cells [c0-1, c0+9)
+        uint32_t cnt[kPSegPerThread], src[kPSegPerThread], pre_k[kPSegPerThread];
+        uint32_t sum = 0, mx = 0;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                float *dst = acc + (int64_t)d * n + p;
-                *dst = accumulate ? *dst + a[d] : a[d];
+        for (int k = 0; k < kPSegPerThread; ++k) {
+            const int s = tid * kPSegPerThread + k;
+            cnt[k] = 0;
+            src[k] = 0;
+            if (s < kPSegs) {
+                const int bx = s % kPB, by = (s / kPB) % kPB, bz = s / (kPB * kPB);
+                const uint32_t key = cell_key(wrapn(c0x + bx - 1, n_ios), wrapn(c0y + by - 1, n_ios),
+                                              wrapn(c0z + bz - 1, n_ios), nt);
+                src[k] = cs[key];
+                cnt[k] = cs[key + 1] - src[k];
+            }
+            sum += cnt[k];
+            mx = max(mx, cnt[k]);
+        }
+        atomicMax(&maxcnt_sh, mx);
+        uint32_t total;
+        uint32_t pre = block_exclusive_scan<kPPBlock>(sum, scan_sh, total);
+#pragma unroll
+        for (int k = 0; k < kPSegPerThread; ++k) {
+            const int s = tid * kPSegPerThread + k;
+            if (s < kPSegs) {
+                seg_pre[s] = pre;
+                seg_src[s] = src[k];
+            }
+            pre_k[k] = pre;
+            pre += cnt[k];
+        }
+        // own cells: particle starts relative to the tile's first particle
+        const uint32_t key0 = (uint32_t)t * kTileCells;
+        const uint32_t p0 = cs[key0];
+        for (int i = tid; i < kTileCells; i += kPPBlock) cst[i] = cs[key0 + i] - p0;
+        if (tid == 0) {
+            seg_pre[kPSegs] = total;
+            cst[kTileCells] = cs[key0 + kTileCells] - p0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            // z-chunks: the smallest power-of-two count whose staged slices fit
+            int C = 1;
+            for (; C < 8; C <<= 1) {
+                bool fits = true;
+                for (int c = 0; c < C; ++c) {
+                    const int z0 = c * 8 / C, z1 = (c + 1) * 8 / C;
+                    if (seg_pre[(z1 + 2) * kPB * kPB] - seg_pre[z0 * kPB * kPB] > (uint32_t)CAP)
+                        fits = false;
+                }
+                if (fits) break;
+            }
+            chunk_sh = C;
+        }
+        __syncthreads();
+        const int C = chunk_sh;
+        const uint32_t maxcnt = maxcnt_sh;
+
+        for (int c = 0; c < C; ++c) {
+            const int z0 = c * 8 / C, z1 = (c + 1) * 8 / C;
+            const uint32_t vb = seg_pre[z0 * kPB * kPB], ve = seg_pre[(z1 + 2) * kPB * kPB];
+            const bool staged = ve - vb <= (uint32_t)CAP;
+            if (c > 0) __syncthreads();  // previous chunk done with xs
+            if (!ADJ && staged && C == 1 && maxcnt <= 4) {
+                // sparse box: every thread copies the particles of its own
+                // segments (at most 4 each), no search needed; one segment at
+                // a time keeps the register footprint of the staging small
+#pragma unroll 1
+                for (int k = 0; k < kPSegPerThread; ++k) {
+                    const int s = tid * kPSegPerThread + k;
+                    const int bx = s % kPB, by = (s / kPB) % kPB, bz = s / (kPB * kPB);
+                    uint32_t o[4][3];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if ((uint32_t)i >= cnt[k]) continue;
+                        const uint32_t p = src[k] + i;
+                        o[i][0] = pos[p];
+                        o[i][1] = pos[(int64_t)n + p];
+                        o[i][2] = pos[2 * (int64_t)n + p];
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if ((uint32_t)i >= cnt[k]) continue;
+                        float4 q;
+                        q.x = (float)(2 * (bx - 1)) + (float)o[i][0] * inv;
+                        q.y = (float)(2 * (by - 1)) + (float)o[i][1] * inv;
+                        q.z = (float)(2 * (bz - 1)) + (float)o[i][2] * inv;
+                        q.w = 0.0f;
+                        xs[pre_k[k] + i] = q;
+                        if (ADJ) {
+                            const uint32_t p = src[k] + i;
+                            as_[pre_k[k] + i] = make_float4(abar[p], abar[(int64_t)n + p],
+                                                            abar[2 * (int64_t)n + p], 0.f);
+                        }
+                    }
+                }
+            } else if (staged) {
+                // kStage particles per thread at a time: the segment searches and
+                // the loads of a batch are issued before the LDS stores
+                constexpr int kStage = 4;
+                for (uint32_t v0 = vb + tid; v0 < ve; v0 += kPPBlock * kStage) {
+                    int sg[kStage];
+                    uint32_t pj[kStage];
+#pragma unroll
+                    for (int k = 0; k < kStage; ++k) {
+                        const uint32_t v = v0 + k * kPPBlock;
+                        sg[k] = v < ve ? seg_search(seg_pre, kPSegs, v) : -1;
+                        pj[k] = sg[k] < 0 ? 0u : seg_src[sg[k]] + (v - seg_pre[sg[k]]);
+                    }
+                    uint32_t o[kStage][3];
+                    float4 ab[kStage];
+#pragma unroll
+                    for (int k = 0; k < kStage; ++k) {
+                        if (sg[k] < 0) continue;
+                        const uint32_t p = pj[k];
+                        o[k][0] = pos[p];
+                        o[k][1] = pos[(int64_t)n + p];
+                        o[k][2] = pos[2 * (int64_t)n + p];
+                        if (ADJ)
+                            ab[k] = make_float4(abar[p], abar[(int64_t)n + p],
+                                                abar[2 * (int64_t)n + p], 0.f);
+                    }
+#pragma unroll
+                    for (int k = 0; k < kStage; ++k) {
+                        if (sg[k] < 0) continue;
+                        const int s = sg[k];
+                        const int bx = s % kPB, by = (s / kPB) % kPB, bz = s / (kPB * kPB);
+                        float4 q;
+                        q.x = (float)(2 * (bx - 1)) + (float)o[k][0] * inv;
+                        q.y = (float)(2 * (by - 1)) + (float)o[k][1] * inv;
+                        q.z = (float)(2 * (bz - 1)) + (float)o[k][2] * inv;
+                        q.w = 0.0f;
+                        const uint32_t v = v0 + k * kPPBlock;
+                        xs[v - vb] = q;
+                        if (ADJ) as_[v - vb] = ab[k];
+                    }
+                }
+            }
+            __syncthreads();
+            // own particles of the cells [z0*64, z1*64): a contiguous range
+            const uint32_t q0 = cst[z0 * 64], q1 = cst[z1 * 64];
+            for (uint32_t lp = q0 + tid; lp < q1; lp += kPPBlock) {
+                const int u = seg_search(cst, kTileCells, lp);
+                const uint32_t p = p0 + lp;
+                const int bx = (u & 7) + 1, by = ((u >> 3) & 7) + 1, bz = (u >> 6) + 1;
+                const float xi = (float)(2 * (bx - 1)) + (float)pos[p] * inv;
+                const float yi = (float)(2 * (by - 1)) + (float)pos[(int64_t)n + p] * inv;
+                const float zi = (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv;
+                float aix = 0.f, aiy = 0.f, aiz = 0.f;
+                if (ADJ) {
+                    aix = abar[p];
+                    aiy = abar[(int64_t)n + p];
+                    aiz = abar[2 * (int64_t)n + p];
+                }
+                float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+                if (staged) {
+                    // the three x-neighbours of a cell are consecutive box segments,
+                    // so the 27 neighbour cells are 9 contiguous ranges of xs
+                    for (int row = 0; row < 9; ++row) {
+                        const int oy = row % 3 - 1, oz = row / 3 - 1;
+                        const int sm = ((bz + oz) * kPB + (by + oy)) * kPB + bx;
+                        const uint32_t v0 = seg_pre[sm - 1] - vb, v1 = seg_pre[sm + 2] - vb;
+                        float fx = 0.f, fy = 0.f, fz = 0.f;
+                        uint32_t v = v0;
+                        if (ADJ) {
+                            for (; v < v1; ++v) {
+                                const float4 qa = xs[v], aa = as_[v];
+                                pair_adjoint(qa.x - xi, qa.y - yi, qa.z - zi, aa.x - aix, aa.y - aiy,
+                                             aa.z - aiz, kinv, K, fx, fy, fz);
+                            }
+                        } else {
+                            for (; v + 1 < v1; v += 2) {
+                                const float4 qa = xs[v], qb = xs[v + 1];
+                                pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, kinv, K, fx, fy, fz);
+                                pair_accumulate(qb.x - xi, qb.y - yi, qb.z - zi, kinv, K, fx, fy, fz);
+                            }
+                            if (v < v1) {
+                                const float4 qa = xs[v];
+                                pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, kinv, K, fx, fy, fz);
+                            }
+                        }
+                        kahan_add(sx, cx, fx);
+                        kahan_add(sy, cy, fy);
+                        kahan_add(sz, cz, fz);
+                    }
+                } else {
+                    for (int nb = 0; nb < 27; ++nb) {
+                        const int ox = nb % 3 - 1, oy = (nb / 3) % 3 - 1, oz = nb / 9 - 1;
+                        const int s = ((bz + oz) * kPB + (by + oy)) * kPB + (bx + ox);
+                        const uint32_t v0 = seg_pre[s], v1 = seg_pre[s + 1];
+                        const float bxo = (float)(2 * (bx + ox - 1)), byo = (float)(2 * (by + oy - 1)),
+                                    bzo = (float)(2 * (bz + oz - 1));
+                        float fx = 0.f, fy = 0.f, fz = 0.f;
+                        for (uint32_t v = v0; v < v1; ++v) {
+                            const uint32_t pj = seg_src[s] + (v - v0);
+                            const float xj = bxo + (float)pos[pj] * inv;
+                            const float yj = byo + (float)pos[(int64_t)n + pj] * inv;
+                            const float zj = bzo + (float)pos[2 * (int64_t)n + pj] * inv;
+                            if (ADJ)
+                                pair_adjoint(xj - xi, yj - yi, zj - zi, abar[pj] - aix,
+                                             abar[(int64_t)n + pj] - aiy, abar[2 * (int64_t)n + pj] - aiz,
+                                             kinv, K, fx, fy, fz);
+                            else
+                                pair_accumulate(xj - xi, yj - yi, zj - zi, kinv, K, fx, fy, fz);
+                        }
+                        kahan_add(sx, cx, fx);
+                        kahan_add(sy, cy, fy);
+                        kahan_add(sz, cz, fz);
+                    }
+                }
+                const float a[3] = {gm * sx, gm * sy, gm * sz};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    float *dst = acc + (int64_t)d * n + p;
+                    *dst = accumulate ? *dst + a[d] : a[d];
+                }
             }
         }
+        __syncthreads();  // this tile is done with the LDS arrays
     }
 }
 
@@ -420,33 +472,55 @@ void build_pair_table(cube2_ctx *ctx) {
     }
 }
 
-int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, float *acc,
-              int accumulate, unsigned char *work, const WorkLayout &L, hipStream_t s) {
+namespace {
+
+__global__ void reset_queue(uint32_t *q) { *q = 0u; }
+
+// Persistent grid for pp_kernel<ADJ>: as many workgroups as fit on the device
+// at once (never more than there are tiles).
+template <bool ADJ>
+unsigned persistent_grid(int ntiles) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pp_kernel<ADJ>, PPGeo<ADJ>::BLOCK,
+                                                     0) != hipSuccess)
+        return (unsigned)ntiles;
+    const long g = (long)std::max(1, cus) * std::max(1, per_cu);
+    return (unsigned)std::min<long>(g, ntiles);
+}
+
+template <bool ADJ>
+int launch_pp_kernel(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                     const float *abar, float *out, int accumulate, unsigned char *work,
+                     const WorkLayout &L, hipStream_t s) {
     const float4 *table = reinterpret_cast<const float4 *>(ctx->tables + ctx->pp_off);
     const int nt = ctx->nt;
+    const int ntiles = nt * nt * nt;
     int r = launch_order_tiles(ctx, cs, work, L, s);
     if (r) return r;
     const uint32_t *order = reinterpret_cast<const uint32_t *>(work + L.tile_order);
-    pp_kernel<false><<<(unsigned)(nt * nt * nt), PPGeo<false>::BLOCK, 0, s>>>(
+    uint32_t *queue = reinterpret_cast<uint32_t *>(work + L.tile_order) + 4 * (size_t)ntiles;
+    reset_queue<<<1, 1, 0, s>>>(queue);
+    CUBE2_LAUNCH_CHECK();
+    pp_kernel<ADJ><<<persistent_grid<ADJ>(ntiles), PPGeo<ADJ>::BLOCK, 0, s>>>(
         pos, cs, (int)n, nt, table, ctx->pp_K, ctx->pp_kinv,
-        (float)(ctx->cfg.g_newton * ctx->cfg.m_p), nullptr, acc, accumulate, order);
+        (float)(ctx->cfg.g_newton * ctx->cfg.m_p), abar, out, accumulate, order, queue, ntiles);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
+}
+
+}  // namespace
+
+int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, float *acc,
+              int accumulate, unsigned char *work, const WorkLayout &L, hipStream_t s) {
+    return launch_pp_kernel<false>(ctx, pos, cs, n, nullptr, acc, accumulate, work, L, s);
 }
 
 int launch_pp_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                        const float *acc_bar, float *x_bar, int accumulate, unsigned char *work,
                        const WorkLayout &L, hipStream_t s) {
-    const float4 *table = reinterpret_cast<const float4 *>(ctx->tables + ctx->pp_off);
-    const int nt = ctx->nt;
-    int r = launch_order_tiles(ctx, cs, work, L, s);
-    if (r) return r;
-    const uint32_t *order = reinterpret_cast<const uint32_t *>(work + L.tile_order);
-    pp_kernel<true><<<(unsigned)(nt * nt * nt), PPGeo<true>::BLOCK, 0, s>>>(
-        pos, cs, (int)n, nt, table, ctx->pp_K, ctx->pp_kinv,
-        (float)(ctx->cfg.g_newton * ctx->cfg.m_p), acc_bar, x_bar, accumulate, order);
-    CUBE2_LAUNCH_CHECK();
-    return CUBE2_OK;
+    return launch_pp_kernel<true>(ctx, pos, cs, n, acc_bar, x_bar, accumulate, work, L, s);
 }
 
 }  // namespace cube2
