@@ -157,14 +157,18 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
     // Persistent workgroups: each takes the next tile of the heaviest-first
     // order from a global counter until the order is exhausted (the exit
     // test is block-uniform).
+    // thread 0 claims the next tile while the current one is processed
+    int next = 0;
+    if (tid == 0) next = (int)atomicAdd(queue, 1u);
     for (;;) {
         if (tid == 0) {
-            tile_sh = (int)atomicAdd(queue, 1u);
+            tile_sh = next;
             maxcnt_sh = 0u;
         }
         __syncthreads();
         const int ti = tile_sh;
         if (ti >= ntiles) break;
+        if (tid == 0) next = (int)atomicAdd(queue, 1u);
         const int t = (int)order[ti];
         const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
         const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
@@ -200,15 +204,21 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
             pre_k[k] = pre;
             pre += cnt[k];
         }
-        // own cells: particle starts relative to the tile's first particle
-        const uint32_t key0 = (uint32_t)t * kTileCells;
-        const uint32_t p0 = cs[key0];
-        for (int i = tid; i < kTileCells; i += kPPBlock) cst[i] = cs[key0 + i] - p0;
-        if (tid == 0) {
-            seg_pre[kPSegs] = total;
-            cst[kTileCells] = cs[key0 + kTileCells] - p0;
-        }
+        if (tid == 0) seg_pre[kPSegs] = total;
         __syncthreads();
+        // own cells (box segments with coordinates 1..8): their particle
+        // starts relative to the tile's first particle, from the box ranges
+        // (the own cells' particles are one contiguous range)
+        const uint32_t p0 = seg_src[(1 * kPB + 1) * kPB + 1];
+        for (int i = tid; i <= kTileCells; i += kPPBlock) {
+            if (i < kTileCells) {
+                const int s = (((i >> 6) + 1) * kPB + ((i >> 3) & 7) + 1) * kPB + (i & 7) + 1;
+                cst[i] = seg_src[s] - p0;
+            } else {
+                const int s = (8 * kPB + 8) * kPB + 8;  // last own cell
+                cst[i] = seg_src[s] + (seg_pre[s + 1] - seg_pre[s]) - p0;
+            }
+        }
         if (tid == 0) {
             // z-chunks: the smallest power-of-two count whose staged slices fit
             int C = 1;
@@ -314,9 +324,19 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                 const int u = seg_search(cst, kTileCells, lp);
                 const uint32_t p = p0 + lp;
                 const int bx = (u & 7) + 1, by = ((u >> 3) & 7) + 1, bz = (u >> 6) + 1;
-                const float xi = (float)(2 * (bx - 1)) + (float)pos[p] * inv;
-                const float yi = (float)(2 * (by - 1)) + (float)pos[(int64_t)n + p] * inv;
-                const float zi = (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv;
+                float xi, yi, zi;
+                if (staged) {
+                    // the particle itself is staged: same exact floats, no HBM read
+                    const int su = (bz * kPB + by) * kPB + bx;
+                    const float4 qi = xs[seg_pre[su] + (lp - cst[u]) - vb];
+                    xi = qi.x;
+                    yi = qi.y;
+                    zi = qi.z;
+                } else {
+                    xi = (float)(2 * (bx - 1)) + (float)pos[p] * inv;
+                    yi = (float)(2 * (by - 1)) + (float)pos[(int64_t)n + p] * inv;
+                    zi = (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv;
+                }
                 float aix = 0.f, aiy = 0.f, aiz = 0.f;
                 if (ADJ) {
                     aix = abar[p];
