@@ -70,7 +70,7 @@ WorkLayout work_layout(const cube2_ctx *c, int64_t n) {
     const size_t ntiles = (size_t)c->nt * c->nt * c->nt;
     size_t nblk = (std::max(nn, ntiles) + 4095) / 4096;
     L.hist = take(nblk * 256 * 4 + 1024);
-    L.tile_order = take((ntiles * 4 + 64) * sizeof(uint32_t));  // + the PP work counter
+    L.tile_order = take((ntiles * 4 + 64) * sizeof(uint32_t));  // + the tile work counter
     L.counts = take((size_t)(c->n_cells + 1) * 4);
     const size_t scan_len = std::max((size_t)(c->n_cells + 1), nblk * 256);
     L.scan_tmp = take((scan_len / 1024 + 64) * 4 * 2 + 4096);

@@ -140,6 +140,42 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
     return off + x - v;
 }
 
+// Tile scheduling of the per-tile kernels.  With a work queue (queue != 0)
+// the workgroups are persistent: each takes the next tile of the
+// heaviest-first order (launch_order_tiles) from one global counter until the
+// order is exhausted.  Without a queue, workgroup b takes the tile
+// tile_of_block(b) once.  claim_tile is called by all threads of the
+// workgroup and returns false when the workgroup is done (a block-uniform
+// result).
+
+// One claim on the work counter (a single thread calls it): the position in
+// `order` of the next tile, or a value >= ntiles when all are taken.
+__device__ __forceinline__ int claim_slot(uint32_t *queue, int ntiles) {
+    const uint32_t v = atomicAdd(queue, 1u);
+    return v < (uint32_t)ntiles ? (int)v : ntiles;
+}
+
+__device__ __forceinline__ bool claim_tile(const uint32_t *order, uint32_t *queue, int ntiles,
+                                          int nt, int &round, int *tile_sh, int &tx, int &ty,
+                                          int &tz) {
+    if (queue) {
+        __syncthreads();  // the previous tile is done with the LDS arrays
+        if (threadIdx.x == 0) *tile_sh = claim_slot(queue, ntiles);
+        __syncthreads();
+        const int ti = *tile_sh;
+        if (ti >= ntiles) return false;
+        const int t = (int)order[ti];
+        tx = t % nt;
+        ty = (t / nt) % nt;
+        tz = t / (nt * nt);
+    } else {
+        if (round > 0) return false;
+        tile_of_block(blockIdx.x, nt, tx, ty, tz);
+    }
+    ++round;
+    return true;
+}
+
 // Sums over the 64 lanes of a wave (butterfly; every lane must be active).
 // The order of the additions is fixed, so float sums are deterministic.
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
@@ -226,6 +262,29 @@ int launch_interp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64
                   hipStream_t s);
 int launch_order_tiles(cube2_ctx *ctx, const uint32_t *cs, unsigned char *work,
                        const WorkLayout &L, hipStream_t s);
+int launch_reset_tile_queue(cube2_ctx *ctx, unsigned char *work, const WorkLayout &L,
+                            hipStream_t s);
+
+// The tile order and work counter written by launch_order_tiles.
+inline const uint32_t *tile_order_ptr(unsigned char *work, const WorkLayout &L) {
+    return reinterpret_cast<const uint32_t *>(work + L.tile_order);
+}
+inline uint32_t *tile_queue_ptr(const cube2_ctx *ctx, unsigned char *work, const WorkLayout &L) {
+    return reinterpret_cast<uint32_t *>(work + L.tile_order) + 4 * (size_t)ctx->nt * ctx->nt * ctx->nt;
+}
+
+// Workgroups of `kernel` (block threads, no dynamic LDS) that fit on the
+// device at once, at most `ntiles`: the grid of a persistent launch.
+template <typename K>
+inline unsigned persistent_grid(K kernel, int block, int ntiles) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess)
+        return (unsigned)ntiles;
+    const long g = (long)(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+    return (unsigned)(g < ntiles ? g : ntiles);
+}
 int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, float *acc,
               int accumulate, unsigned char *work, const WorkLayout &L, hipStream_t s);
 void build_pair_table(cube2_ctx *ctx);

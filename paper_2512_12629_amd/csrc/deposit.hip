@@ -112,123 +112,126 @@ template <bool FINE, bool COARSE>
 __global__ __launch_bounds__(kBlock) void deposit_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs, int n, int n_f, int nt,
     float *__restrict__ rho_f, unsigned long long *__restrict__ rho_f_fx,
-    unsigned long long *__restrict__ coarse_acc, int n_c, int hshift, uint32_t *status) {
+    unsigned long long *__restrict__ coarse_acc, int n_c, int hshift, uint32_t *status,
+    const uint32_t *__restrict__ order, uint32_t *__restrict__ queue) {
     __shared__ uint32_t seg_pre[kSegs + 1];
     __shared__ uint32_t seg_src[kSegs];
     __shared__ unsigned long long acc_f[FINE ? kTileFine * kTileFine * kTileFine : 1];
     __shared__ unsigned long long acc_c[COARSE ? kCoarseMax * kCoarseMax * kCoarseMax : 1];
     __shared__ uint32_t scan_sh[kBlock / 64 + 1];
+    __shared__ int tile_sh;
 
-    int tx, ty, tz;
-    tile_of_block(blockIdx.x, nt, tx, ty, tz);
     const int tid = threadIdx.x;
     const int n_ios = nt * kTileIos;
-    const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
     const int NC = (kTileFine >> hshift) + 1;  // coarse nodes per axis touched by the tile
+    int round = 0, tx, ty, tz;
+    while (claim_tile(order, queue, nt * nt * nt, nt, round, &tile_sh, tx, ty, tz)) {
+        const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
 
-    if (FINE)
-        for (int i = tid; i < kTileFine * kTileFine * kTileFine; i += kBlock) acc_f[i] = 0ull;
-    if (COARSE)
-        for (int i = tid; i < NC * NC * NC; i += kBlock) acc_c[i] = 0ull;
+        if (FINE)
+            for (int i = tid; i < kTileFine * kTileFine * kTileFine; i += kBlock) acc_f[i] = 0ull;
+        if (COARSE)
+            for (int i = tid; i < NC * NC * NC; i += kBlock) acc_c[i] = 0ull;
 
-    // particle ranges of the 9^3 box of IOS cells [c0-1, c0+8)
-    uint32_t cnt[kSegPerThread], src[kSegPerThread], sum = 0;
+        // particle ranges of the 9^3 box of IOS cells [c0-1, c0+8)
+        uint32_t cnt[kSegPerThread], src[kSegPerThread], sum = 0;
 #pragma unroll
-    for (int k = 0; k < kSegPerThread; ++k) {
-        const int s = tid * kSegPerThread + k;
-        cnt[k] = 0;
-        src[k] = 0;
-        if (s < kSegs) {
-            const int bx = s % kBox, by = (s / kBox) % kBox, bz = s / (kBox * kBox);
-            const bool own = bx > 0 && by > 0 && bz > 0;
-            if (FINE || own) {
-                const uint32_t key = cell_key(wrapn(c0x + bx - 1, n_ios), wrapn(c0y + by - 1, n_ios),
-                                              wrapn(c0z + bz - 1, n_ios), nt);
-                src[k] = cs[key];
-                cnt[k] = cs[key + 1] - src[k];
+        for (int k = 0; k < kSegPerThread; ++k) {
+            const int s = tid * kSegPerThread + k;
+            cnt[k] = 0;
+            src[k] = 0;
+            if (s < kSegs) {
+                const int bx = s % kBox, by = (s / kBox) % kBox, bz = s / (kBox * kBox);
+                const bool own = bx > 0 && by > 0 && bz > 0;
+                if (FINE || own) {
+                    const uint32_t key = cell_key(wrapn(c0x + bx - 1, n_ios), wrapn(c0y + by - 1, n_ios),
+                                                  wrapn(c0z + bz - 1, n_ios), nt);
+                    src[k] = cs[key];
+                    cnt[k] = cs[key + 1] - src[k];
+                }
+            }
+            sum += cnt[k];
+        }
+        uint32_t total;
+        uint32_t pre = block_exclusive_scan(sum, scan_sh, total);
+#pragma unroll
+        for (int k = 0; k < kSegPerThread; ++k) {
+            const int s = tid * kSegPerThread + k;
+            if (s < kSegs) {
+                seg_pre[s] = pre;
+                seg_src[s] = src[k];
+            }
+            pre += cnt[k];
+        }
+        if (tid == 0) {
+            seg_pre[kSegs] = total;
+            // Overflow guard: a fine node sums at most `total` weights of 2^45
+            // each; a coarse node sums the own particles of at most 8 tiles.
+            const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
+            const uint32_t own = cs[key0 + kTileCells] - cs[key0];
+            if ((FINE && total >= (1u << 19)) || (COARSE && own >= (1u << 16))) atomicOr(status, 1u);
+        }
+        __syncthreads();
+
+        // The loop runs wave-uniformly (every lane of a wave takes the same
+        // trips) so that the coarse weights can be summed over the wave; each
+        // trip takes kBatch particles per lane, whose segment searches and
+        // position loads are all issued before the first deposit.
+        constexpr int kBatch = 4;
+        const int lane = tid & 63;
+        for (uint32_t w0 = (uint32_t)(tid - lane); w0 < total; w0 += kBlock * kBatch) {
+            int sg[kBatch];
+            uint32_t o[kBatch][3];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const uint32_t v = w0 + k * kBlock + lane;
+                sg[k] = v < total ? seg_search(seg_pre, kSegs, v) : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                o[k][0] = o[k][1] = o[k][2] = 0u;
+                if (sg[k] < 0) continue;
+                const uint32_t p = seg_src[sg[k]] + (w0 + k * kBlock + lane - seg_pre[sg[k]]);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) o[k][d] = pos[(int64_t)d * n + p];
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const bool valid = sg[k] >= 0;
+                const int s = valid ? sg[k] : 0;
+                const int b[3] = {s % kBox, (s / kBox) % kBox, s / (kBox * kBox)};
+                if (FINE && valid) deposit_fine(b, o[k], acc_f);
+                if (COARSE)
+                    deposit_coarse_wave(valid && b[0] > 0 && b[1] > 0 && b[2] > 0, b, o[k], hshift, NC,
+                                        acc_c);
             }
         }
-        sum += cnt[k];
-    }
-    uint32_t total;
-    uint32_t pre = block_exclusive_scan(sum, scan_sh, total);
-#pragma unroll
-    for (int k = 0; k < kSegPerThread; ++k) {
-        const int s = tid * kSegPerThread + k;
-        if (s < kSegs) {
-            seg_pre[s] = pre;
-            seg_src[s] = src[k];
-        }
-        pre += cnt[k];
-    }
-    if (tid == 0) {
-        seg_pre[kSegs] = total;
-        // Overflow guard: a fine node sums at most `total` weights of 2^45
-        // each; a coarse node sums the own particles of at most 8 tiles.
-        const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
-        const uint32_t own = cs[key0 + kTileCells] - cs[key0];
-        if ((FINE && total >= (1u << 19)) || (COARSE && own >= (1u << 16))) atomicOr(status, 1u);
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // The loop runs wave-uniformly (every lane of a wave takes the same
-    // trips) so that the coarse weights can be summed over the wave; each
-    // trip takes kBatch particles per lane, whose segment searches and
-    // position loads are all issued before the first deposit.
-    constexpr int kBatch = 4;
-    const int lane = tid & 63;
-    for (uint32_t w0 = (uint32_t)(tid - lane); w0 < total; w0 += kBlock * kBatch) {
-        int sg[kBatch];
-        uint32_t o[kBatch][3];
-#pragma unroll
-        for (int k = 0; k < kBatch; ++k) {
-            const uint32_t v = w0 + k * kBlock + lane;
-            sg[k] = v < total ? seg_search(seg_pre, kSegs, v) : -1;
+        if (FINE) {
+            const int a0x = tx * kTileFine, a0y = ty * kTileFine, a0z = tz * kTileFine;
+            for (int i = tid; i < kTileFine * kTileFine * kTileFine; i += kBlock) {
+                const int lx = i % kTileFine, ly = (i / kTileFine) % kTileFine,
+                          lz = i / (kTileFine * kTileFine);
+                const int64_t g = ((int64_t)(a0z + lz) * n_f + (a0y + ly)) * n_f + (a0x + lx);
+                const unsigned long long v = acc_f[i];
+                rho_f[g] = (float)v * 0x1p-45f;
+                if (rho_f_fx) rho_f_fx[g] = v;
+            }
         }
-#pragma unroll
-        for (int k = 0; k < kBatch; ++k) {
-            o[k][0] = o[k][1] = o[k][2] = 0u;
-            if (sg[k] < 0) continue;
-            const uint32_t p = seg_src[sg[k]] + (w0 + k * kBlock + lane - seg_pre[sg[k]]);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) o[k][d] = pos[(int64_t)d * n + p];
+        if (COARSE) {
+            const int A0x = (tx * kTileFine) >> hshift, A0y = (ty * kTileFine) >> hshift,
+                      A0z = (tz * kTileFine) >> hshift;
+            for (int i = tid; i < NC * NC * NC; i += kBlock) {
+                const unsigned long long v = acc_c[i];
+                if (!v) continue;
+                const int lx = i % NC, ly = (i / NC) % NC, lz = i / (NC * NC);
+                const int64_t g = ((int64_t)wrapn(A0z + lz, n_c) * n_c + wrapn(A0y + ly, n_c)) * n_c +
+                                  wrapn(A0x + lx, n_c);
+                atomicAdd(&coarse_acc[g], v);
+            }
         }
-#pragma unroll
-        for (int k = 0; k < kBatch; ++k) {
-            const bool valid = sg[k] >= 0;
-            const int s = valid ? sg[k] : 0;
-            const int b[3] = {s % kBox, (s / kBox) % kBox, s / (kBox * kBox)};
-            if (FINE && valid) deposit_fine(b, o[k], acc_f);
-            if (COARSE)
-                deposit_coarse_wave(valid && b[0] > 0 && b[1] > 0 && b[2] > 0, b, o[k], hshift, NC,
-                                    acc_c);
-        }
-    }
-    __syncthreads();
-
-    if (FINE) {
-        const int a0x = tx * kTileFine, a0y = ty * kTileFine, a0z = tz * kTileFine;
-        for (int i = tid; i < kTileFine * kTileFine * kTileFine; i += kBlock) {
-            const int lx = i % kTileFine, ly = (i / kTileFine) % kTileFine,
-                      lz = i / (kTileFine * kTileFine);
-            const int64_t g = ((int64_t)(a0z + lz) * n_f + (a0y + ly)) * n_f + (a0x + lx);
-            const unsigned long long v = acc_f[i];
-            rho_f[g] = (float)v * 0x1p-45f;
-            if (rho_f_fx) rho_f_fx[g] = v;
-        }
-    }
-    if (COARSE) {
-        const int A0x = (tx * kTileFine) >> hshift, A0y = (ty * kTileFine) >> hshift,
-                  A0z = (tz * kTileFine) >> hshift;
-        for (int i = tid; i < NC * NC * NC; i += kBlock) {
-            const unsigned long long v = acc_c[i];
-            if (!v) continue;
-            const int lx = i % NC, ly = (i / NC) % NC, lz = i / (NC * NC);
-            const int64_t g = ((int64_t)wrapn(A0z + lz, n_c) * n_c + wrapn(A0y + ly, n_c)) * n_c +
-                              wrapn(A0x + lx, n_c);
-            atomicAdd(&coarse_acc[g], v);
-        }
-    }
+    }  // tiles
 }
 
 __global__ void coarse_finalize(const unsigned long long *__restrict__ accum, int64_t m,
@@ -259,18 +262,26 @@ int launch_deposit(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int6
         CUBE2_LAUNCH_CHECK();
     }
     auto *ffx = reinterpret_cast<unsigned long long *>(rho_f_fx);
+    if (!fine && !coarse) return CUBE2_EINVAL;
+    // persistent workgroups over the tiles, heaviest first
+    int r = launch_order_tiles(ctx, cs, work, L, s);
+    if (r) return r;
+    const uint32_t *order = tile_order_ptr(work, L);
+    uint32_t *queue = tile_queue_ptr(ctx, work, L);
+    const int ntiles = (int)blocks;
     if (fine && coarse)
-        deposit_kernel<true, true><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, rho_f,
-                                                             ffx, cacc, n_c, hshift, status);
+        deposit_kernel<true, true><<<persistent_grid(deposit_kernel<true, true>, kBlock, ntiles),
+                                     kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, rho_f, ffx, cacc,
+                                                     n_c, hshift, status, order, queue);
     else if (fine)
-        deposit_kernel<true, false><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, rho_f,
-                                                              ffx, cacc, n_c, hshift, status);
-    else if (coarse)
-        deposit_kernel<false, true><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt,
-                                                              nullptr, nullptr, cacc, n_c, hshift,
-                                                              status);
+        deposit_kernel<true, false><<<persistent_grid(deposit_kernel<true, false>, kBlock, ntiles),
+                                      kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, rho_f, ffx,
+                                                      cacc, n_c, hshift, status, order, queue);
     else
-        return CUBE2_EINVAL;
+        deposit_kernel<false, true><<<persistent_grid(deposit_kernel<false, true>, kBlock, ntiles),
+                                      kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, nullptr,
+                                                      nullptr, cacc, n_c, hshift, status, order,
+                                                      queue);
     CUBE2_LAUNCH_CHECK();
     if (coarse) {
         coarse_finalize<<<(unsigned)((mc + 255) / 256), 256, 0, s>>>(

@@ -187,10 +187,11 @@ __global__ void tile_keys_kernel(const uint32_t *__restrict__ cs, int nt, uint32
 
 }  // namespace
 
-// PP work order: the tiles sorted (stably, one 8-bit radix pass) by their
-// particle count in units of 1024, descending, so that the heaviest tiles
-// start first and the light ones keep the XCD-slab order.  The tile indices
-// land in the first ntiles words of the tile_order region.
+// Work order of the persistent per-tile kernels: the tiles sorted (stably,
+// one 8-bit radix pass) by their particle count in units of 1024, descending,
+// so that the heaviest tiles start first and the light ones keep the
+// XCD-slab order.  The tile indices land in the first ntiles words of the
+// tile_order region; the work counter (tile_queue_ptr) is reset to zero.
 int launch_order_tiles(cube2_ctx *ctx, const uint32_t *cs, unsigned char *work,
                        const WorkLayout &L, hipStream_t s) {
     const int nt = ctx->nt;
@@ -207,6 +208,13 @@ int launch_order_tiles(cube2_ctx *ctx, const uint32_t *cs, unsigned char *work,
     int r = exclusive_scan(ghist, ghist, (int64_t)nblk * 256, tmp, s);
     if (r) return r;
     radix_scatter<<<nblk, kBlock, 0, s>>>(kin, vin, kout, order, ntiles, 0, nblk, ghist);
+    CUBE2_LAUNCH_CHECK();
+    return launch_reset_tile_queue(ctx, work, L, s);
+}
+
+int launch_reset_tile_queue(cube2_ctx *ctx, unsigned char *work, const WorkLayout &L,
+                            hipStream_t s) {
+    fill_u32<<<1, 64, 0, s>>>(tile_queue_ptr(ctx, work, L), 0u, 1);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }

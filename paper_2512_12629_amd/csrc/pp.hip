@@ -155,11 +155,11 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
     for (int i = tid; i < 3 * (K + 1); i += kPPBlock) pair_rows[i] = table[i];
 
     // Persistent workgroups: each takes the next tile of the heaviest-first
-    // order from a global counter until the order is exhausted (the exit
-    // test is block-uniform).
-    // thread 0 claims the next tile while the current one is processed
+    // order (claim_slot) until all are taken (the exit test is
+    // block-uniform).  Thread 0 claims the next tile while the current one
+    // is processed.
     int next = 0;
-    if (tid == 0) next = (int)atomicAdd(queue, 1u);
+    if (tid == 0) next = claim_slot(queue, ntiles);
     for (;;) {
         if (tid == 0) {
             tile_sh = next;
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
         __syncthreads();
         const int ti = tile_sh;
         if (ti >= ntiles) break;
-        if (tid == 0) next = (int)atomicAdd(queue, 1u);
+        if (tid == 0) next = claim_slot(queue, ntiles);
         const int t = (int)order[ti];
         const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
         const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
@@ -494,22 +494,6 @@ void build_pair_table(cube2_ctx *ctx) {
 
 namespace {
 
-__global__ void reset_queue(uint32_t *q) { *q = 0u; }
-
-// Persistent grid for pp_kernel<ADJ>: as many workgroups as fit on the device
-// at once (never more than there are tiles).
-template <bool ADJ>
-unsigned persistent_grid(int ntiles) {
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pp_kernel<ADJ>, PPGeo<ADJ>::BLOCK,
-                                                     0) != hipSuccess)
-        return (unsigned)ntiles;
-    const long g = (long)std::max(1, cus) * std::max(1, per_cu);
-    return (unsigned)std::min<long>(g, ntiles);
-}
-
 template <bool ADJ>
 int launch_pp_kernel(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                      const float *abar, float *out, int accumulate, unsigned char *work,
@@ -519,11 +503,9 @@ int launch_pp_kernel(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, in
     const int ntiles = nt * nt * nt;
     int r = launch_order_tiles(ctx, cs, work, L, s);
     if (r) return r;
-    const uint32_t *order = reinterpret_cast<const uint32_t *>(work + L.tile_order);
-    uint32_t *queue = reinterpret_cast<uint32_t *>(work + L.tile_order) + 4 * (size_t)ntiles;
-    reset_queue<<<1, 1, 0, s>>>(queue);
-    CUBE2_LAUNCH_CHECK();
-    pp_kernel<ADJ><<<persistent_grid<ADJ>(ntiles), PPGeo<ADJ>::BLOCK, 0, s>>>(
+    const uint32_t *order = tile_order_ptr(work, L);
+    uint32_t *queue = tile_queue_ptr(ctx, work, L);
+    pp_kernel<ADJ><<<persistent_grid(pp_kernel<ADJ>, PPGeo<ADJ>::BLOCK, ntiles), PPGeo<ADJ>::BLOCK, 0, s>>>(
         pos, cs, (int)n, nt, table, ctx->pp_K, ctx->pp_kinv,
         (float)(ctx->cfg.g_newton * ctx->cfg.m_p), abar, out, accumulate, order, queue, ntiles);
     CUBE2_LAUNCH_CHECK();
