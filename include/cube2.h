@@ -94,8 +94,10 @@ typedef struct cube2_config {
 typedef struct cube2_ctx cube2_ctx;
 
 /* Validate `cfg` and create a host-side context (no device work).
- * Returns CUBE2_EUNSUPPORTED for sizes or ratios outside the set above and
- * CUBE2_EINVAL for non-positive softenings or b_pp >= b_fine. */
+ * Returns CUBE2_EUNSUPPORTED for sizes or ratios outside the set above, or
+ * when no grid of K <= 64 equal intervals of [0, b_fine) has b_pp/2, b_pp
+ * and b_fine/2 on its edges (the exact pair-law pieces of eq. 2 need that),
+ * and CUBE2_EINVAL for non-positive softenings or b_pp >= b_fine. */
 int cube2_create(const cube2_config *cfg, cube2_ctx **out);
 
 /* Free a context (host memory only; device buffers belong to the caller). */
@@ -120,6 +122,15 @@ int cube2_init_tables(cube2_ctx *ctx, void *tables, size_t table_bytes, cube2_st
 /* Copy the level's Green's table (FP32, (n/2+1)^3, [mz][my][mx]) to `out`
  * (device). */
 int cube2_green_table(const cube2_ctx *ctx, int level, float *out, cube2_stream_t stream);
+
+/* The FP32 pair law of the PP force (eqs. 2 and 4d: g = [R(r, b_pp) -
+ * R(r, b_fine)] / r, so that a pair contributes g * D) exactly as the FP32
+ * forward PP kernel evaluates it -- the same table, indexed by s = |D|^2,
+ * and the same FP32 operations -- on the host, for inspecting its accuracy.
+ * d (host, 3*n floats: d[k*n+i] is component k of separation i, fine
+ * cells, each |component| < 4) in, g (host, n floats) out.  No device
+ * work; CUBE2_EINVAL for a NULL pointer, n < 0 or a component of 4 or more. */
+int cube2_pair_law_f32(const cube2_ctx *ctx, const float *d, float *g, int64_t n);
 
 /* Quantise FP32 box-unit positions x (device, x[d*n+i] in [0,1)) to the
  * IOS form (section 2.3): q = floor(x * n_fine * 2^15) mod (n_fine * 2^15),

@@ -79,6 +79,7 @@ def _load():
         "cube2_potential_f64": [P, I, P, P, P, S, P],
         "cube2_pm_force_f64": [P, P, P, I64, P, I, P, S, P],
         "cube2_pp_force_f64": [P, P, P, I64, P, I, P, S, P],
+        "cube2_pair_law_f32": [P, P, P, I64],
         "cube2_strerror": [I],
     }
     for name, args in sigs.items():
@@ -253,6 +254,18 @@ def cube2_pp_force_f64(ctx, pos, cell_start, acc, work, accumulate=False, stream
     _check(_lib.cube2_pp_force_f64(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], _ptr(acc),
                                    int(bool(accumulate)), _ptr(work), work.numel(),
                                    _stream(stream)), "cube2_pp_force_f64")
+
+
+def cube2_pair_law_f32(ctx, d):
+    """g for the separations d (numpy float32 (3, n), fine cells), evaluated
+    on the host exactly as the FP32 forward PP kernel does."""
+    import numpy as np
+    d = np.ascontiguousarray(d, dtype=np.float32)
+    n = d.shape[1]
+    g = np.empty(n, dtype=np.float32)
+    _check(_lib.cube2_pair_law_f32(ctx, d.ctypes.data_as(ctypes.c_void_p),
+                                   g.ctypes.data_as(ctypes.c_void_p), n), "cube2_pair_law_f32")
+    return g
 
 
 def cube2_strerror(code: int) -> str:

@@ -30,6 +30,8 @@ size_t table_layout(cube2_ctx *c) {
     }
     c->pp_off = off;
     off = align_up(off + (size_t)(kPairKMax + 1) * kPairRow * sizeof(float), 256);
+    c->pp_soff = off;
+    off = align_up(off + (size_t)kSRows * 4 * sizeof(float), 256);
     if (c->fp64) {
         for (int l = 0; l < c->n_levels; ++l) {
             Level &L = c->lv[l];
@@ -140,7 +142,10 @@ int cube2_create(const cube2_config *cfg, cube2_ctx **out) {
         C.b_prev = -1.0;
     }
     ctx->table_bytes = table_layout(ctx);
-    build_pair_table(ctx);
+    if (build_pair_table(ctx)) {
+        delete ctx;
+        return CUBE2_EUNSUPPORTED;
+    }
     *out = ctx;
     return CUBE2_OK;
 }
@@ -169,6 +174,8 @@ int cube2_init_tables(cube2_ctx *ctx, void *tables, size_t table_bytes, cube2_st
     CUBE2_CHECK_HIP(hipMemsetAsync(ctx->tables, 0, 256, s));
     CUBE2_CHECK_HIP(hipMemcpyAsync(ctx->tables + ctx->pp_off, ctx->pp_rows.data(),
                                    ctx->pp_rows.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    CUBE2_CHECK_HIP(hipMemcpyAsync(ctx->tables + ctx->pp_soff, ctx->pp_srows.data(),
+                                   ctx->pp_srows.size() * sizeof(float), hipMemcpyHostToDevice, s));
     if (ctx->fp64)
         CUBE2_CHECK_HIP(hipMemcpyAsync(ctx->tables + ctx->pp64_off, ctx->pp_rows64.data(),
                                        ctx->pp_rows64.size() * sizeof(double),

@@ -43,14 +43,24 @@ namespace cube2 {
 // Pair-law table of the PP kernels (built on the host, see pp.hip).
 constexpr int kPairKMax = 64;      // grid intervals of [0, b_f)
 constexpr int kPairRow = 12;       // floats per interval: 9 coefficients, y map, pad
+// FP32 forward pair law, indexed by s = r^2: one row of 4 cubic coefficients
+// per 1/16 of an octave, for s in [2^-31, 2^6).  The row of s is its float
+// bit pattern shifted right by 19 (exponent and top 4 mantissa bits) minus
+// kSRow0.
+constexpr int kSMantBits = 4;
+constexpr int kSRow0 = (127 - 31) << kSMantBits;
+constexpr int kSRows = (6 + 31) << kSMantBits;  // 592
 }  // namespace cube2
 
 struct cube2_ctx {
     cube2_config cfg;
     int pp_K = 0;                      // intervals of the pair-law grid
     float pp_kinv = 0.f;               // K / b_f
+    float pp_bf2 = 0.f;                // b_f^2 (FP32 forward pair law)
     std::vector<float> pp_rows;        // (K+1) * kPairRow floats (host copy)
     size_t pp_off = 0;                 // byte offset of the pair-law table in `tables`
+    std::vector<float> pp_srows;       // kSRows * 4 floats: the FP32 forward pair law by s = r^2
+    size_t pp_soff = 0;                // byte offset of pp_srows in `tables`
     std::vector<double> pp_rows64;     // the same rows in FP64
     size_t pp64_off = 0;               // FP64 rows (CUBE2_FP64_FORM only)
     bool fp64 = false;                 // CUBE2_FP64_FORM
@@ -287,7 +297,7 @@ inline unsigned persistent_grid(K kernel, int block, int ntiles) {
 }
 int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, float *acc,
               int accumulate, unsigned char *work, const WorkLayout &L, hipStream_t s);
-void build_pair_table(cube2_ctx *ctx);
+int build_pair_table(cube2_ctx *ctx);
 int launch_kick_drift(cube2_ctx *ctx, const uint16_t *pos_in, const uint32_t *cs_in,
                       const float *vel_in, const float *acc, int64_t n, double kick,
                       double drift, uint16_t *pos_out, uint32_t *cs_out, float *vel_out,

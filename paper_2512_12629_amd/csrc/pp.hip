@@ -17,6 +17,7 @@
 // Kahan compensation.  Boxes too large for LDS read the same data from HBM.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "common.hpp"
 
@@ -51,14 +52,36 @@ template <bool ADJ> struct PPGeo {
 // on the intervals where 1/r^2 - R(r, b_f) vanishes like (1 - r/b_f)^5 at the
 // cutoff, which use the exact factorisation r^3 g = s^5 Q(1 - s),
 // s = 1 - r/b_f, Q(t) = 32/35 + 32/7 t + 704/35 t^2 + 64/5 t^3.  The row of
-// r >= b_f is zero.  The interval is r K / b_f truncated: one multiply and
-// no compare chain; each lane reads its row (12 floats) from LDS.
+// r >= b_f is zero.  This exact table serves the adjoint (which needs dg/dr)
+// and, in FP64, the plain FP64 form.
+//
+// The FP32 forward kernel evaluates g as a function of s = r^2 instead, which
+// needs neither a square root nor r^-3.  Since g vanishes like (b_f - r)^5 at
+// the cutoff, and sparse particles often have all their neighbours close to
+// it, the table holds h = g / (b_f^2 - s)^5, smooth and nonzero up to and
+// beyond the cutoff (there the factorised form gives h = Q(1 - r/b_f) /
+// (r^3 (b_f (b_f + r))^5), continued analytically past b_f), and the kernel
+// forms g = h max(b_f^2 - s, 0)^5: exact zero beyond the cutoff and the same
+// relative accuracy near it as elsewhere.  s is cut at its float exponent and
+// top 4 mantissa bits (1/16 of an octave, s in [2^-31, 64)); on each piece h
+// is the cubic through its values at the 4 Chebyshev nodes (fitted in FP64
+// on the host from eq. (2) evaluated in extended precision).  For exact s the
+// table's g is within 8e-7 of the true g, relative; FP32 rounding of s adds
+// its own part near the cutoff, as rounding of r does in any evaluation.  The
+// row index is the bit pattern of s shifted right, the local variable the
+// remaining 19 mantissa bits read as a float in [0, 1/16).  Every pair
+// separation in the staged box is below 4 fine cells per axis, so s < 48 and
+// the row exists; the 2^-31 added to s (below the smallest nonzero
+// separation squared, 2^-30) keeps a coincident pair on row 0, where g is
+// finite and g D = 0.
 
 namespace {
 
-// The pair-law table in LDS, declared at namespace scope so that every access
-// is a 32-bit LDS address (each kernel that uses it gets its own copy).
+// The pair-law tables in LDS, declared at namespace scope so that every
+// access is a 32-bit LDS address (each kernel gets its own copy of those it
+// uses): by r (the adjoint) and by s = r^2 (the FP32 forward).
 __shared__ float4 pair_rows[3 * (kPairKMax + 1)];
+__shared__ float4 pair_srows[kSRows];
 
 __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
     const float y = v - c;
@@ -67,26 +90,21 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
     s = t;
 }
 
-// g(r) * D accumulated into (fx, fy, fz); rows (LDS) hold the pair-law table.
-__device__ __forceinline__ void pair_accumulate(float dx, float dy, float dz, float kinv, int K,
-                                                float &fx, float &fy, float &fz) {
-    // coincident particles (D = 0, r2 = 0) are clamped to r2 = 1e-12, below the
-    // smallest nonzero separation (2^-15 fine cells), so g stays finite and g D = 0
-    const float r2 = fmaxf(dx * dx + dy * dy + dz * dz, 1e-12f);
-    const float rinv = __builtin_amdgcn_rsqf(r2);
-    const float r = r2 * rinv;
-    const float f = r * kinv;
-    // idx <= K <= 64: the mask tells the compiler the row offset fits a
-    // 24-bit multiply (a full-rate v_mad_u32_u24 instead of a 64-bit one)
-    const int idx = min((int)f, K) & 127;
-    const float4 c0 = pair_rows[3 * idx], c1 = pair_rows[3 * idx + 1], c2 = pair_rows[3 * idx + 2];
-    const float y = c2.y + c2.z * __builtin_amdgcn_fractf(f);
-    const float U =
-        c0.x + y * (c0.y + y * (c0.z + y * (c0.w + y * (c1.x + y * (c1.y + y * (c1.z + y * (c1.w + y * c2.x)))))));
-    const float g = U * (rinv * rinv * rinv);
-    fx += g * dx;
-    fy += g * dy;
-    fz += g * dz;
+// g(r) * D accumulated into (fx, fy, fz) from the s-indexed table (LDS);
+// bf2 = b_f^2 in FP32.
+__device__ __forceinline__ void pair_accumulate(float dx, float dy, float dz, float bf2, float &fx,
+                                                float &fy, float &fz) {
+    const float s = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, 0x1p-31f)));
+    const uint32_t b = __float_as_uint(s);
+    const float4 c = pair_srows[(b >> (23 - kSMantBits)) - kSRow0];
+    const float z = __uint_as_float((b & ((1u << (23 - kSMantBits)) - 1u)) | 0x3F800000u) - 1.0f;
+    const float h = fmaf(fmaf(fmaf(c.w, z, c.z), z, c.y), z, c.x);
+    const float w = fmaxf(bf2 - s, 0.0f);
+    const float w2 = w * w;
+    const float g = (h * w) * (w2 * w2);
+    fx = fmaf(g, dx, fx);
+    fy = fmaf(g, dy, fy);
+    fz = fmaf(g, dz, fz);
 }
 
 // Adjoint of one pair for the cotangents: out += J(D) u with u = abar_j -
@@ -132,7 +150,7 @@ template <bool ADJ>
 __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *__restrict__ pos,
                                                      const uint32_t *__restrict__ cs, int n,
                                                      int nt, const float4 *__restrict__ table,
-                                                     int K, float kinv, float gm,
+                                                     int K, float kinv, float bf2, float gm,
                                                      const float *__restrict__ abar,
                                                      float *__restrict__ acc, int accumulate,
                                                      const uint32_t *__restrict__ order,
@@ -152,7 +170,11 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
     const int tid = threadIdx.x;
     const int n_ios = nt * kTileIos;
     const float inv = 1.0f / 32768.0f;
-    for (int i = tid; i < 3 * (K + 1); i += kPPBlock) pair_rows[i] = table[i];
+    if (ADJ) {
+        for (int i = tid; i < 3 * (K + 1); i += kPPBlock) pair_rows[i] = table[i];
+    } else {
+        for (int i = tid; i < kSRows; i += kPPBlock) pair_srows[i] = table[i];
+    }
 
     // Persistent workgroups: each takes the next tile of the heaviest-first
     // order (claim_slot) until all are taken (the exit test is
@@ -362,12 +384,12 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                         } else {
                             for (; v + 1 < v1; v += 2) {
                                 const float4 qa = xs[v], qb = xs[v + 1];
-                                pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, kinv, K, fx, fy, fz);
-                                pair_accumulate(qb.x - xi, qb.y - yi, qb.z - zi, kinv, K, fx, fy, fz);
+                                pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, bf2, fx, fy, fz);
+                                pair_accumulate(qb.x - xi, qb.y - yi, qb.z - zi, bf2, fx, fy, fz);
                             }
                             if (v < v1) {
                                 const float4 qa = xs[v];
-                                pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, kinv, K, fx, fy, fz);
+                                pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, bf2, fx, fy, fz);
                             }
                         }
                         kahan_add(sx, cx, fx);
@@ -392,7 +414,7 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                                              abar[(int64_t)n + pj] - aiy, abar[2 * (int64_t)n + pj] - aiz,
                                              kinv, K, fx, fy, fz);
                             else
-                                pair_accumulate(xj - xi, yj - yi, zj - zi, kinv, K, fx, fy, fz);
+                                pair_accumulate(xj - xi, yj - yi, zj - zi, bf2, fx, fy, fz);
                         }
                         kahan_add(sx, cx, fx);
                         kahan_add(sy, cy, fy);
@@ -429,13 +451,86 @@ void compose(const double P[9], double alpha, double beta, double Q[9]) {
 
 }  // namespace
 
-// The pair-law table (see the comment above pair_accumulate), in FP64.
-void build_pair_table(cube2_ctx *ctx) {
+namespace {
+
+// h = g / (b_f^2 - r^2)^5 for the pair law g(r) of eqs. (2) and (4d), in
+// extended precision: where 1/r^2 - R(r, b_f) would cancel (r >= b_pp and
+// r >= b_f/2) through its factorised form (which also continues h past the
+// cutoff), elsewhere from the branches of R(r, b).
+long double pair_h_direct(double b_pp, double b_f, double rd) {
+    using X = long double;
+    const X r = rd, bf = b_f;
+    auto r_over_r = [&](X b) -> X {  // R(r, b) / r
+        const X t = r / b;
+        if (t >= 1) return 1 / (r * r * r);
+        if (2 * t < 1)
+            return (X(64) / 5 + t * t * (X(-256) / 5 + t * (32 + t * (X(1536) / 35 + t * (X(-192) / 5))))) /
+                   (b * b * b);
+        const X p = X(3) / 35 / (t * t) - X(32) / 5 +
+                    t * (X(256) / 5 + t * (-96 + t * (X(256) / 5 + t * (32 + t * (X(-1536) / 35 + t * (X(64) / 5))))));
+        return p / (b * b * r);
+    };
+    if (r >= b_pp && 2 * r >= bf) {
+        // r^3 g = q^5 Q(q), q = 1 - r/b_f, and b_f^2 - r^2 = q b_f (b_f + r)
+        const X q = 1 - r / bf;
+        const X Q = X(1344) / 35 + q * (X(-2912) / 35 + q * (X(2048) / 35 + q * (X(-64) / 5)));
+        const X u = bf * (bf + r);
+        return Q / (r * r * r * u * u * u * u * u);
+    }
+    const X w = bf * bf - r * r;
+    return (r_over_r(b_pp) - r_over_r(bf)) / (w * w * w * w * w);
+}
+
+// The FP32 forward table by s = r^2 (see the comment above pair_accumulate):
+// per row the cubic in z in [0, 1/16) through h at the 4 Chebyshev nodes,
+// solved in FP64 in the variable y = 16 z and rescaled.  Built from the
+// branches of eq. (2) directly, so it does not depend on the r grid.
+void build_pair_srows(cube2_ctx *ctx) {
+    constexpr int D = 4;
+    const double pi = 3.14159265358979323846;
+    double yn[D];
+    for (int j = 0; j < D; ++j) yn[j] = 0.5 + 0.5 * std::cos(pi * (j + 0.5) / D);
+    ctx->pp_srows.assign((size_t)kSRows * 4, 0.0f);
+    for (int t = 0; t < kSRows; ++t) {
+        const int e = ((t + kSRow0) >> kSMantBits) - 127, i = (t + kSRow0) & ((1 << kSMantBits) - 1);
+        const double scale = std::ldexp(1.0, e), inv16 = 1.0 / (1 << kSMantBits);
+        const double bf = ctx->cfg.b_fine;
+        if (scale * (1.0 + i * inv16) >= bf * bf) continue;  // beyond the cutoff: h = 0
+        double A[D][D + 1];
+        for (int j = 0; j < D; ++j) {
+            const double sv = scale * (1.0 + (i + yn[j]) * inv16);
+            double p = 1.0;
+            for (int k = 0; k < D; ++k, p *= yn[j]) A[j][k] = p;
+            A[j][D] = (double)pair_h_direct(ctx->cfg.b_pp, bf, std::sqrt(sv));
+        }
+        for (int c = 0; c < D; ++c) {  // Gaussian elimination, partial pivoting
+            int pv = c;
+            for (int r = c + 1; r < D; ++r)
+                if (std::fabs(A[r][c]) > std::fabs(A[pv][c])) pv = r;
+            for (int k = 0; k <= D; ++k) std::swap(A[c][k], A[pv][k]);
+            for (int r = 0; r < D; ++r) {
+                if (r == c) continue;
+                const double f = A[r][c] / A[c][c];
+                for (int k = c; k <= D; ++k) A[r][k] -= f * A[c][k];
+            }
+        }
+        double p = 1.0;
+        for (int k = 0; k < D; ++k, p *= (1 << kSMantBits))
+            ctx->pp_srows[(size_t)t * 4 + k] = (float)(A[k][D] / A[k][k] * p);
+    }
+}
+
+}  // namespace
+
+// The pair-law tables (see the comment above pair_accumulate).  Returns
+// nonzero when no K <= kPairKMax puts b_pp/2, b_pp and b_f/2 on interval
+// edges (the pieces would then straddle a breakpoint of eq. 2).
+int build_pair_table(cube2_ctx *ctx) {
     static const double a[6] = {64.0 / 5, 0.0, -256.0 / 5, 32.0, 1536.0 / 35, -192.0 / 5};
     static const double c[6] = {256.0 / 5, -96.0, 256.0 / 5, 32.0, -1536.0 / 35, 64.0 / 5};
     const double bpp = ctx->cfg.b_pp, bf = ctx->cfg.b_fine;
     // smallest K with b_pp/2, b_pp and b_f/2 on interval edges
-    int K = kPairKMax;
+    int K = 0;
     for (int k = 1; k <= kPairKMax; ++k) {
         const double w = bf / k;
         bool ok = true;
@@ -445,9 +540,11 @@ void build_pair_table(cube2_ctx *ctx) {
         }
         if (ok) { K = k; break; }
     }
+    if (K == 0) return 1;
     const double w = bf / K;
     ctx->pp_K = K;
     ctx->pp_kinv = (float)(K / bf);
+    ctx->pp_bf2 = (float)(bf * bf);
     ctx->pp_rows.assign((size_t)(K + 1) * kPairRow, 0.0f);
     ctx->pp_rows64.assign((size_t)(K + 1) * kPairRow, 0.0);
     for (int k = 0; k < K; ++k) {
@@ -490,6 +587,8 @@ void build_pair_table(cube2_ctx *ctx) {
         row[9] = (float)(row64[9] = ya);
         row[10] = (float)(row64[10] = yb);
     }
+    build_pair_srows(ctx);
+    return 0;
 }
 
 namespace {
@@ -498,7 +597,8 @@ template <bool ADJ>
 int launch_pp_kernel(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                      const float *abar, float *out, int accumulate, unsigned char *work,
                      const WorkLayout &L, hipStream_t s) {
-    const float4 *table = reinterpret_cast<const float4 *>(ctx->tables + ctx->pp_off);
+    const float4 *table =
+        reinterpret_cast<const float4 *>(ctx->tables + (ADJ ? ctx->pp_off : ctx->pp_soff));
     const int nt = ctx->nt;
     const int ntiles = nt * nt * nt;
     int r = launch_order_tiles(ctx, cs, work, L, s);
@@ -506,7 +606,7 @@ int launch_pp_kernel(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, in
     const uint32_t *order = tile_order_ptr(work, L);
     uint32_t *queue = tile_queue_ptr(ctx, work, L);
     pp_kernel<ADJ><<<persistent_grid(pp_kernel<ADJ>, PPGeo<ADJ>::BLOCK, ntiles), PPGeo<ADJ>::BLOCK, 0, s>>>(
-        pos, cs, (int)n, nt, table, ctx->pp_K, ctx->pp_kinv,
+        pos, cs, (int)n, nt, table, ctx->pp_K, ctx->pp_kinv, ctx->pp_bf2,
         (float)(ctx->cfg.g_newton * ctx->cfg.m_p), abar, out, accumulate, order, queue, ntiles);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
@@ -526,3 +626,27 @@ int launch_pp_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, 
 }
 
 }  // namespace cube2
+
+extern "C" int cube2_pair_law_f32(const cube2_ctx *ctx, const float *d, float *g, int64_t n) {
+    using namespace cube2;
+    if (!ctx || n < 0 || (n > 0 && (!d || !g))) return CUBE2_EINVAL;
+    for (int64_t i = 0; i < n; ++i) {
+        const float dx = d[i], dy = d[n + i], dz = d[2 * n + i];
+        if (!(std::fabs(dx) < 4.0f && std::fabs(dy) < 4.0f && std::fabs(dz) < 4.0f))
+            return CUBE2_EINVAL;
+        // the operations of pair_accumulate, in the same order
+        const float s = std::fmaf(dz, dz, std::fmaf(dy, dy, std::fmaf(dx, dx, 0x1p-31f)));
+        uint32_t b;
+        std::memcpy(&b, &s, 4);
+        const float *c = &ctx->pp_srows[(size_t)((b >> (23 - kSMantBits)) - kSRow0) * 4];
+        const uint32_t zb = (b & ((1u << (23 - kSMantBits)) - 1u)) | 0x3F800000u;
+        float z;
+        std::memcpy(&z, &zb, 4);
+        z -= 1.0f;
+        const float h = std::fmaf(std::fmaf(std::fmaf(c[3], z, c[2]), z, c[1]), z, c[0]);
+        const float w = std::fmax(ctx->pp_bf2 - s, 0.0f);
+        const float w2 = w * w;
+        g[i] = (h * w) * (w2 * w2);
+    }
+    return CUBE2_OK;
+}

@@ -188,6 +188,35 @@ def test_pp_force_against_exact(name):
     assert med < MED and p99 < P99, (med, p99)
 
 
+def test_pp_pair_law_bit_exact_two_particles():
+    """Two particles: the PP kernel's force on each is g(D) D with g the FP32
+    pair law that cube2_pair_law_f32 evaluates on the host with the same
+    operations, so the device result is bit-exact against g * D rounded once
+    (G m = 1; the Kahan sum of one term is that term).  Separations span the
+    pair law's pieces, in both directions and across cell and tile edges."""
+    import paper_2512_12629_amd as m
+    n_f = 16
+    c = m.Cube2(m.Config(n_fine=n_f), n_max=2)
+    rng = np.random.default_rng(29)
+    L = n_f << 15
+    for k in range(24):
+        r = float(np.exp(rng.uniform(np.log(2.0 ** -13), np.log(2.2))))
+        u = rng.standard_normal(3)
+        u /= np.linalg.norm(u)
+        qi = rng.integers(0, L, 3)
+        qj = (qi + np.rint(u * r * 2 ** 15).astype(np.int64)) % L
+        x = (np.stack([qi, qj], axis=1).astype(np.float64) + 0.5) / L
+        pos, cs, perm = c.pack(torch.from_numpy(x.astype(np.float32)).cuda())
+        q = np.floor(x.astype(np.float32).astype(np.float64) * L).astype(np.int64)
+        d = (q[:, 1] - q[:, 0] + L // 2) % L - L // 2           # j - i, minimum image
+        dj = (d * 2.0 ** -15).astype(np.float32).reshape(3, 1)
+        g = m.cube2_pair_law_f32(c.ctx, dj)[0]
+        want = np.stack([np.float32(g) * dj[:, 0], -(np.float32(g) * dj[:, 0])], axis=1)
+        acc = np.empty((3, 2), np.float32)
+        acc[:, _np(perm).astype(np.int64)] = _np(c.pp_force(pos, cs))
+        assert np.array_equal(acc, want), (k, r, acc, want)
+
+
 def test_total_force_against_oracle(case):
     c, p = case["c"], case["p"]
     xf = _sorted_fine(case)

@@ -61,6 +61,9 @@ def test_create_validates_configuration(L):
     assert _create(L, _cfg(b_fine=3.0))[0] == -2        # PP beyond one IOS cell
     assert _create(L, _cfg(coarse_ratio=4, b_coarse=1.0))[0] == -1
     assert _create(L, _cfg(alias_nmax=9))[0] == -2
+    # b_pp/2 = 0.03 is on no grid of K <= 64 equal intervals of [0, 2)
+    assert _create(L, _cfg(b_pp=0.06))[0] == -2
+    assert _create(L, _cfg(b_pp=0.1))[0] == 0           # K = 40
 
 
 def test_sizes_and_state_errors(L):
