@@ -132,6 +132,12 @@ int cube2_green_table(const cube2_ctx *ctx, int level, float *out, cube2_stream_
  * work; CUBE2_EINVAL for a NULL pointer, n < 0 or a component of 4 or more. */
 int cube2_pair_law_f32(const cube2_ctx *ctx, const float *d, float *g, int64_t n);
 
+/* The FP32 pair law and its derivative g_s = dg/ds (s = |D|^2) exactly as
+ * the FP32 PP adjoint kernel evaluates them (its own table, the same FP32
+ * operations), on the host; the pair Jacobian is d(g D)/dD = g I +
+ * 2 g_s D D^T.  d as for cube2_pair_law_f32; g, gs (host, n floats) out. */
+int cube2_pair_jacobian_f32(const cube2_ctx *ctx, const float *d, float *g, float *gs, int64_t n);
+
 /* Quantise FP32 box-unit positions x (device, x[d*n+i] in [0,1)) to the
  * IOS form (section 2.3): q = floor(x * n_fine * 2^15) mod (n_fine * 2^15),
  * then sort stably by IOS cell.  Outputs (device): pos (3*n uint16 in-cell

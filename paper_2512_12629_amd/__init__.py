@@ -80,6 +80,7 @@ def _load():
         "cube2_pm_force_f64": [P, P, P, I64, P, I, P, S, P],
         "cube2_pp_force_f64": [P, P, P, I64, P, I, P, S, P],
         "cube2_pair_law_f32": [P, P, P, I64],
+        "cube2_pair_jacobian_f32": [P, P, P, P, I64],
         "cube2_strerror": [I],
     }
     for name, args in sigs.items():
@@ -266,6 +267,21 @@ def cube2_pair_law_f32(ctx, d):
     _check(_lib.cube2_pair_law_f32(ctx, d.ctypes.data_as(ctypes.c_void_p),
                                    g.ctypes.data_as(ctypes.c_void_p), n), "cube2_pair_law_f32")
     return g
+
+
+def cube2_pair_jacobian_f32(ctx, d):
+    """(g, dg/ds) for the separations d (numpy float32 (3, n)), evaluated on
+    the host exactly as the FP32 PP adjoint kernel does."""
+    import numpy as np
+    d = np.ascontiguousarray(d, dtype=np.float32)
+    n = d.shape[1]
+    g = np.empty(n, dtype=np.float32)
+    gs = np.empty(n, dtype=np.float32)
+    _check(_lib.cube2_pair_jacobian_f32(ctx, d.ctypes.data_as(ctypes.c_void_p),
+                                        g.ctypes.data_as(ctypes.c_void_p),
+                                        gs.ctypes.data_as(ctypes.c_void_p), n),
+           "cube2_pair_jacobian_f32")
+    return g, gs
 
 
 def cube2_strerror(code: int) -> str:

@@ -28,8 +28,8 @@ size_t table_layout(cube2_ctx *c) {
         L.g_off = off;
         off = align_up(off + h * h * h * sizeof(float), 256);
     }
-    c->pp_off = off;
-    off = align_up(off + (size_t)(kPairKMax + 1) * kPairRow * sizeof(float), 256);
+    c->pp_aoff = off;
+    off = align_up(off + (size_t)kARows * kARowFloats * sizeof(float), 256);
     c->pp_soff = off;
     off = align_up(off + (size_t)kSRows * 4 * sizeof(float), 256);
     if (c->fp64) {
@@ -172,8 +172,8 @@ int cube2_init_tables(cube2_ctx *ctx, void *tables, size_t table_bytes, cube2_st
     ctx->tables = static_cast<unsigned char *>(tables);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     CUBE2_CHECK_HIP(hipMemsetAsync(ctx->tables, 0, 256, s));
-    CUBE2_CHECK_HIP(hipMemcpyAsync(ctx->tables + ctx->pp_off, ctx->pp_rows.data(),
-                                   ctx->pp_rows.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    CUBE2_CHECK_HIP(hipMemcpyAsync(ctx->tables + ctx->pp_aoff, ctx->pp_arows.data(),
+                                   ctx->pp_arows.size() * sizeof(float), hipMemcpyHostToDevice, s));
     CUBE2_CHECK_HIP(hipMemcpyAsync(ctx->tables + ctx->pp_soff, ctx->pp_srows.data(),
                                    ctx->pp_srows.size() * sizeof(float), hipMemcpyHostToDevice, s));
     if (ctx->fp64)

@@ -50,6 +50,12 @@ constexpr int kPairRow = 12;       // floats per interval: 9 coefficients, y map
 constexpr int kSMantBits = 4;
 constexpr int kSRow0 = (127 - 31) << kSMantBits;
 constexpr int kSRows = (6 + 31) << kSMantBits;  // 592
+// FP32 adjoint pair law (g and dg/ds), indexed the same way with 1/8 octave
+// pieces: one row of 6 quintic coefficients, padded to 8 floats.
+constexpr int kAMantBits = 3;
+constexpr int kARow0 = (127 - 31) << kAMantBits;
+constexpr int kARows = (6 + 31) << kAMantBits;  // 296
+constexpr int kARowFloats = 8;
 }  // namespace cube2
 
 struct cube2_ctx {
@@ -57,8 +63,8 @@ struct cube2_ctx {
     int pp_K = 0;                      // intervals of the pair-law grid
     float pp_kinv = 0.f;               // K / b_f
     float pp_bf2 = 0.f;                // b_f^2 (FP32 forward pair law)
-    std::vector<float> pp_rows;        // (K+1) * kPairRow floats (host copy)
-    size_t pp_off = 0;                 // byte offset of the pair-law table in `tables`
+    std::vector<float> pp_arows;       // kARows * kARowFloats: the FP32 adjoint pair law by s
+    size_t pp_aoff = 0;                // byte offset of pp_arows in `tables`
     std::vector<float> pp_srows;       // kSRows * 4 floats: the FP32 forward pair law by s = r^2
     size_t pp_soff = 0;                // byte offset of pp_srows in `tables`
     std::vector<double> pp_rows64;     // the same rows in FP64

@@ -52,8 +52,7 @@ template <bool ADJ> struct PPGeo {
 // on the intervals where 1/r^2 - R(r, b_f) vanishes like (1 - r/b_f)^5 at the
 // cutoff, which use the exact factorisation r^3 g = s^5 Q(1 - s),
 // s = 1 - r/b_f, Q(t) = 32/35 + 32/7 t + 704/35 t^2 + 64/5 t^3.  The row of
-// r >= b_f is zero.  This exact table serves the adjoint (which needs dg/dr)
-// and, in FP64, the plain FP64 form.
+// r >= b_f is zero.  This exact table, in FP64, serves the plain FP64 form.
 //
 // The FP32 forward kernel evaluates g as a function of s = r^2 instead, which
 // needs neither a square root nor r^-3.  Since g vanishes like (b_f - r)^5 at
@@ -78,9 +77,9 @@ template <bool ADJ> struct PPGeo {
 namespace {
 
 // The pair-law tables in LDS, declared at namespace scope so that every
-// access is a 32-bit LDS address (each kernel gets its own copy of those it
-// uses): by r (the adjoint) and by s = r^2 (the FP32 forward).
-__shared__ float4 pair_rows[3 * (kPairKMax + 1)];
+// access is a 32-bit LDS address (each kernel gets its own copy of the one it
+// uses): the adjoint's and the forward's, both indexed by s = r^2.
+__shared__ float4 pair_arows[kARows * kARowFloats / 4];
 __shared__ float4 pair_srows[kSRows];
 
 __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
@@ -108,31 +107,36 @@ __device__ __forceinline__ void pair_accumulate(float dx, float dy, float dz, fl
 }
 
 // Adjoint of one pair for the cotangents: out += J(D) u with u = abar_j -
-// abar_i and J = g I + g' D D^T / r.  g' = r^-3 (y_b K/b_f dU/dy - 3 U / r)
-// with U and dU/dy from the same table row (Horner with derivative).
+// abar_i and J = d(g D)/dD = g I + 2 g_s D D^T, g_s = dg/ds.  The adjoint
+// table holds h = g / (b_f^2 - s)^5 as a quintic per 1/8 octave of s, so
+// that its derivative is accurate too; with w = max(b_f^2 - s, 0):
+// g = h w^5 and g_s = w^4 (h_s w - 5 h), h_s = (dh/dz) 2^-e for s in
+// [2^e, 2^(e+1)).
 __device__ __forceinline__ void pair_adjoint(float dx, float dy, float dz, float ux, float uy,
-                                             float uz, float kinv, int K, float &ox, float &oy,
+                                             float uz, float bf2, float &ox, float &oy,
                                              float &oz) {
-    const float r2 = fmaxf(dx * dx + dy * dy + dz * dz, 1e-12f);
-    const float rinv = __builtin_amdgcn_rsqf(r2);
-    const float r = r2 * rinv;
-    const float f = r * kinv;
-    // idx <= K <= 64: the mask tells the compiler the row offset fits a
-    // 24-bit multiply (a full-rate v_mad_u32_u24 instead of a 64-bit one)
-    const int idx = min((int)f, K) & 127;
-    const float4 c0 = pair_rows[3 * idx], c1 = pair_rows[3 * idx + 1], c2 = pair_rows[3 * idx + 2];
-    const float y = c2.y + c2.z * __builtin_amdgcn_fractf(f);
-    const float cf[9] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w, c2.x};
-    float U = cf[8], dU = 0.0f;
-#pragma unroll
-    for (int j = 7; j >= 0; --j) {
-        dU = dU * y + U;
-        U = U * y + cf[j];
-    }
-    const float ri3 = rinv * rinv * rinv;
-    const float g = U * ri3;
-    const float gp = ri3 * (c2.z * kinv * dU - 3.0f * U * rinv);
-    const float du = (dx * ux + dy * uy + dz * uz) * gp * rinv;
+    const float s = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, 0x1p-31f)));
+    const uint32_t b = __float_as_uint(s);
+    const int row = (int)(b >> (23 - kAMantBits)) - kARow0;
+    const float4 c0 = pair_arows[2 * row], c1 = pair_arows[2 * row + 1];
+    const float z = __uint_as_float((b & ((1u << (23 - kAMantBits)) - 1u)) | 0x3F800000u) - 1.0f;
+    const float inv2e = __uint_as_float(0x7F000000u - (b & 0x7F800000u));  // 2^-e
+    float h = fmaf(c1.y, z, c1.x);
+    float hz = c1.y;
+    hz = fmaf(hz, z, h);
+    h = fmaf(h, z, c0.w);
+    hz = fmaf(hz, z, h);
+    h = fmaf(h, z, c0.z);
+    hz = fmaf(hz, z, h);
+    h = fmaf(h, z, c0.y);
+    hz = fmaf(hz, z, h);
+    h = fmaf(h, z, c0.x);
+    const float w = fmaxf(bf2 - s, 0.0f);
+    const float w2 = w * w;
+    const float w4 = w2 * w2;
+    const float g = (h * w) * w4;
+    const float gs2 = 2.0f * w4 * fmaf(hz * inv2e, w, -5.0f * h);  // 2 g_s
+    const float du = (dx * ux + dy * uy + dz * uz) * gs2;
     ox += g * ux + du * dx;
     oy += g * uy + du * dy;
     oz += g * uz + du * dz;
@@ -150,7 +154,7 @@ template <bool ADJ>
 __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *__restrict__ pos,
                                                      const uint32_t *__restrict__ cs, int n,
                                                      int nt, const float4 *__restrict__ table,
-                                                     int K, float kinv, float bf2, float gm,
+                                                     float bf2, float gm,
                                                      const float *__restrict__ abar,
                                                      float *__restrict__ acc, int accumulate,
                                                      const uint32_t *__restrict__ order,
@@ -171,7 +175,7 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
     const int n_ios = nt * kTileIos;
     const float inv = 1.0f / 32768.0f;
     if (ADJ) {
-        for (int i = tid; i < 3 * (K + 1); i += kPPBlock) pair_rows[i] = table[i];
+        for (int i = tid; i < kARows * kARowFloats / 4; i += kPPBlock) pair_arows[i] = table[i];
     } else {
         for (int i = tid; i < kSRows; i += kPPBlock) pair_srows[i] = table[i];
     }
@@ -379,7 +383,7 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                             for (; v < v1; ++v) {
                                 const float4 qa = xs[v], aa = as_[v];
                                 pair_adjoint(qa.x - xi, qa.y - yi, qa.z - zi, aa.x - aix, aa.y - aiy,
-                                             aa.z - aiz, kinv, K, fx, fy, fz);
+                                             aa.z - aiz, bf2, fx, fy, fz);
                             }
                         } else {
                             for (; v + 1 < v1; v += 2) {
@@ -412,7 +416,7 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                             if (ADJ)
                                 pair_adjoint(xj - xi, yj - yi, zj - zi, abar[pj] - aix,
                                              abar[(int64_t)n + pj] - aiy, abar[2 * (int64_t)n + pj] - aiz,
-                                             kinv, K, fx, fy, fz);
+                                             bf2, fx, fy, fz);
                             else
                                 pair_accumulate(xj - xi, yj - yi, zj - zi, bf2, fx, fy, fz);
                         }
@@ -481,29 +485,31 @@ long double pair_h_direct(double b_pp, double b_f, double rd) {
     return (r_over_r(b_pp) - r_over_r(bf)) / (w * w * w * w * w);
 }
 
-// The FP32 forward table by s = r^2 (see the comment above pair_accumulate):
-// per row the cubic in z in [0, 1/16) through h at the 4 Chebyshev nodes,
-// solved in FP64 in the variable y = 16 z and rescaled.  Built from the
-// branches of eq. (2) directly, so it does not depend on the r grid.
-void build_pair_srows(cube2_ctx *ctx) {
-    constexpr int D = 4;
-    const double pi = 3.14159265358979323846;
-    double yn[D];
+// A table of h = g / (b_f^2 - s)^5 by s = r^2 (see the comments above
+// pair_accumulate and pair_adjoint): row t covers s in [2^e (1 + i/2^mb),
+// 2^e (1 + (i+1)/2^mb)) with (e + 127) 2^mb + i = t + row0, and holds the
+// polynomial of degree D-1 in z in [0, 2^-mb) through h at the D Chebyshev
+// nodes, solved in FP64 in the variable y = 2^mb z and rescaled.  Built from
+// eq. (2) directly (extended precision), independent of the r grid; rows
+// beyond the cutoff are zero.
+void fit_h_rows(const cube2_ctx *ctx, int mb, int D, int row0, int nrows, int row_floats,
+                std::vector<float> &out) {
+    const double pi = 3.14159265358979323846, bf = ctx->cfg.b_fine;
+    std::vector<double> yn(D);
     for (int j = 0; j < D; ++j) yn[j] = 0.5 + 0.5 * std::cos(pi * (j + 0.5) / D);
-    ctx->pp_srows.assign((size_t)kSRows * 4, 0.0f);
-    for (int t = 0; t < kSRows; ++t) {
-        const int e = ((t + kSRow0) >> kSMantBits) - 127, i = (t + kSRow0) & ((1 << kSMantBits) - 1);
-        const double scale = std::ldexp(1.0, e), inv16 = 1.0 / (1 << kSMantBits);
-        const double bf = ctx->cfg.b_fine;
-        if (scale * (1.0 + i * inv16) >= bf * bf) continue;  // beyond the cutoff: h = 0
-        double A[D][D + 1];
+    out.assign((size_t)nrows * row_floats, 0.0f);
+    for (int t = 0; t < nrows; ++t) {
+        const int e = ((t + row0) >> mb) - 127, i = (t + row0) & ((1 << mb) - 1);
+        const double scale = std::ldexp(1.0, e), inv = 1.0 / (1 << mb);
+        if (scale * (1.0 + i * inv) >= bf * bf) continue;  // beyond the cutoff: h = 0
+        double A[8][9];
         for (int j = 0; j < D; ++j) {
-            const double sv = scale * (1.0 + (i + yn[j]) * inv16);
+            const double sv = scale * (1.0 + (i + yn[j]) * inv);
             double p = 1.0;
             for (int k = 0; k < D; ++k, p *= yn[j]) A[j][k] = p;
             A[j][D] = (double)pair_h_direct(ctx->cfg.b_pp, bf, std::sqrt(sv));
         }
-        for (int c = 0; c < D; ++c) {  // Gaussian elimination, partial pivoting
+        for (int c = 0; c < D; ++c) {  // Gauss-Jordan, partial pivoting
             int pv = c;
             for (int r = c + 1; r < D; ++r)
                 if (std::fabs(A[r][c]) > std::fabs(A[pv][c])) pv = r;
@@ -515,8 +521,8 @@ void build_pair_srows(cube2_ctx *ctx) {
             }
         }
         double p = 1.0;
-        for (int k = 0; k < D; ++k, p *= (1 << kSMantBits))
-            ctx->pp_srows[(size_t)t * 4 + k] = (float)(A[k][D] / A[k][k] * p);
+        for (int k = 0; k < D; ++k, p *= (1 << mb))
+            out[(size_t)t * row_floats + k] = (float)(A[k][D] / A[k][k] * p);
     }
 }
 
@@ -545,7 +551,6 @@ int build_pair_table(cube2_ctx *ctx) {
     ctx->pp_K = K;
     ctx->pp_kinv = (float)(K / bf);
     ctx->pp_bf2 = (float)(bf * bf);
-    ctx->pp_rows.assign((size_t)(K + 1) * kPairRow, 0.0f);
     ctx->pp_rows64.assign((size_t)(K + 1) * kPairRow, 0.0);
     for (int k = 0; k < K; ++k) {
         const double mid = (k + 0.5) * w, rl = k * w, rr = (k + 1) * w;
@@ -581,13 +586,13 @@ int build_pair_table(cube2_ctx *ctx) {
             ya = 0.0;
             yb = 1.0;
         }
-        float *row = &ctx->pp_rows[(size_t)k * kPairRow];
         double *row64 = &ctx->pp_rows64[(size_t)k * kPairRow];
-        for (int j = 0; j < 9; ++j) row[j] = (float)(row64[j] = Q[j]);
-        row[9] = (float)(row64[9] = ya);
-        row[10] = (float)(row64[10] = yb);
+        for (int j = 0; j < 9; ++j) row64[j] = Q[j];
+        row64[9] = ya;
+        row64[10] = yb;
     }
-    build_pair_srows(ctx);
+    fit_h_rows(ctx, kSMantBits, 4, kSRow0, kSRows, 4, ctx->pp_srows);
+    fit_h_rows(ctx, kAMantBits, 6, kARow0, kARows, kARowFloats, ctx->pp_arows);
     return 0;
 }
 
@@ -598,7 +603,7 @@ int launch_pp_kernel(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, in
                      const float *abar, float *out, int accumulate, unsigned char *work,
                      const WorkLayout &L, hipStream_t s) {
     const float4 *table =
-        reinterpret_cast<const float4 *>(ctx->tables + (ADJ ? ctx->pp_off : ctx->pp_soff));
+        reinterpret_cast<const float4 *>(ctx->tables + (ADJ ? ctx->pp_aoff : ctx->pp_soff));
     const int nt = ctx->nt;
     const int ntiles = nt * nt * nt;
     int r = launch_order_tiles(ctx, cs, work, L, s);
@@ -606,7 +611,7 @@ int launch_pp_kernel(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, in
     const uint32_t *order = tile_order_ptr(work, L);
     uint32_t *queue = tile_queue_ptr(ctx, work, L);
     pp_kernel<ADJ><<<persistent_grid(pp_kernel<ADJ>, PPGeo<ADJ>::BLOCK, ntiles), PPGeo<ADJ>::BLOCK, 0, s>>>(
-        pos, cs, (int)n, nt, table, ctx->pp_K, ctx->pp_kinv, ctx->pp_bf2,
+        pos, cs, (int)n, nt, table, ctx->pp_bf2,
         (float)(ctx->cfg.g_newton * ctx->cfg.m_p), abar, out, accumulate, order, queue, ntiles);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
@@ -647,6 +652,40 @@ extern "C" int cube2_pair_law_f32(const cube2_ctx *ctx, const float *d, float *g
         const float w = std::fmax(ctx->pp_bf2 - s, 0.0f);
         const float w2 = w * w;
         g[i] = (h * w) * (w2 * w2);
+    }
+    return CUBE2_OK;
+}
+
+extern "C" int cube2_pair_jacobian_f32(const cube2_ctx *ctx, const float *d, float *g, float *gs,
+                                       int64_t n) {
+    using namespace cube2;
+    if (!ctx || n < 0 || (n > 0 && (!d || !g || !gs))) return CUBE2_EINVAL;
+    for (int64_t i = 0; i < n; ++i) {
+        const float dx = d[i], dy = d[n + i], dz = d[2 * n + i];
+        if (!(std::fabs(dx) < 4.0f && std::fabs(dy) < 4.0f && std::fabs(dz) < 4.0f))
+            return CUBE2_EINVAL;
+        // the operations of pair_adjoint, in the same order
+        const float s = std::fmaf(dz, dz, std::fmaf(dy, dy, std::fmaf(dx, dx, 0x1p-31f)));
+        uint32_t b;
+        std::memcpy(&b, &s, 4);
+        const float *c = &ctx->pp_arows[(size_t)((int)(b >> (23 - kAMantBits)) - kARow0) * kARowFloats];
+        const uint32_t zb = (b & ((1u << (23 - kAMantBits)) - 1u)) | 0x3F800000u;
+        const uint32_t eb = 0x7F000000u - (b & 0x7F800000u);
+        float z, inv2e;
+        std::memcpy(&z, &zb, 4);
+        std::memcpy(&inv2e, &eb, 4);
+        z -= 1.0f;
+        float h = std::fmaf(c[5], z, c[4]);
+        float hz = c[5];
+        for (int k = 3; k >= 0; --k) {
+            hz = std::fmaf(hz, z, h);
+            h = std::fmaf(h, z, c[k]);
+        }
+        const float w = std::fmax(ctx->pp_bf2 - s, 0.0f);
+        const float w2 = w * w;
+        const float w4 = w2 * w2;
+        g[i] = (h * w) * w4;
+        gs[i] = 0.5f * (2.0f * w4 * std::fmaf(hz * inv2e, w, -5.0f * h));
     }
     return CUBE2_OK;
 }

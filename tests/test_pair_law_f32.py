@@ -103,3 +103,39 @@ def test_pair_law_f32_coincident_and_range():
             m.cube2_pair_law_f32(h, np.full((3, 1), 4.0, np.float32))
     finally:
         m.cube2_destroy(h)
+
+
+@pytest.mark.parametrize("b_f,b_pp", CONFIGS)
+def test_pair_jacobian_f32_against_oracle(b_f, b_pp):
+    """The adjoint kernel's (g, g_s = dg/ds) against the extended-precision
+    oracle (g_s = (dg/dr) / 2r): g as above; the term 2 g_s D D^T of the pair
+    Jacobian g I + 2 g_s D D^T within (3e-5 + 5e-7/q) of the Jacobian's size
+    |g| + 2 |g_s| s (its table is a quintic per 1/8 octave, whose derivative
+    is good to a few 1e-6; g_s vanishes like q^4 at the cutoff)."""
+    m, h = _ctx(b_f, b_pp)
+    try:
+        rng = np.random.default_rng(13)
+        edges = [b_pp / 2, b_pp, b_f / 2]
+        r = np.concatenate([np.exp(rng.uniform(np.log(3e-5), np.log(b_f), 6000)),
+                            b_f * (1 - 10 ** rng.uniform(-3, -1, 1500)),
+                            b_f * (1 + rng.uniform(0, 0.02, 500))] +
+                           [e * (1 + rng.uniform(-0.02, 0.02, 1500)) for e in edges])
+        u = rng.standard_normal((3, r.size))
+        u /= np.linalg.norm(u, axis=0)
+        d = (u * r).astype(np.float32)
+        g, gs = m.cube2_pair_jacobian_f32(h, d)
+        dd = d.astype(np.float64)
+        rr = np.sqrt((dd * dd).sum(axis=0))
+        q = 1.0 - rr / b_f
+        gref = np.array([oracle.pp_g(x, b_pp, b_f) for x in rr])
+        gsref = np.array([oracle.pp_dg(x, b_pp, b_f) for x in rr]) / (2 * rr)
+        inside = q >= 1e-3
+        eg = np.abs(g - gref)[inside] / ((2e-6 + 1e-6 / q[inside]) * np.abs(gref[inside]))
+        s2 = 2 * rr[inside] ** 2
+        jac = np.abs(gref[inside]) + np.abs(gsref[inside]) * s2
+        es = np.abs(gs - gsref)[inside] * s2 / ((3e-5 + 5e-7 / q[inside]) * jac)
+        assert eg.max() <= 1.0, (eg.max(), rr[inside][np.argmax(eg)])
+        assert es.max() <= 1.0, (es.max(), rr[inside][np.argmax(es)])
+        assert np.all(g[q <= 0] == 0.0) and np.all(gs[q <= 0] == 0.0)
+    finally:
+        m.cube2_destroy(h)
