@@ -44,17 +44,16 @@ WORKLOADS = {
 
 # Algorithmic FP32 flops (FMA = 2) of one in-cutoff PP pair, counted from
 # the arithmetic of the compiled inner loop: 3 differences, s = r^2 with its
-# clamp (3 FMA, 6), the local variable (1), b_f^2 - s (1), 3 Horner FMA (6),
-# the (b_f^2 - s)^5 factor and g (4), 3 accumulating FMA (6).  The table
-# index (shift, mask) and the clamp at zero are integer/compare operations
-# and are not counted.
-PP_FLOPS_PER_PAIR = 27
+# offset (3 FMA, 6), the local variable (1), w = 1 - s/b_f^2 (1 FMA, 2),
+# 3 Horner FMA (6), w^2, w^4, h w and g (4), 3 accumulating FMA (6).  The
+# table index (shift, mask, or) is integer work and is not counted.
+PP_FLOPS_PER_PAIR = 28
 
 
 # VALU instructions per candidate pair of the compiled forward PP inner loop
-# (gfx950 ISA: 49 per iteration of the two-pair unrolled loop), and the
+# (gfx950 ISA: 47 per iteration of the two-pair unrolled loop), and the
 # unpacked FP32 VALU issue rate (lane-ops per second).
-PP_VALU_PER_PAIR = 24.5
+PP_VALU_PER_PAIR = 23.5
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 

@@ -62,7 +62,7 @@ struct cube2_ctx {
     cube2_config cfg;
     int pp_K = 0;                      // intervals of the pair-law grid
     float pp_kinv = 0.f;               // K / b_f
-    float pp_bf2 = 0.f;                // b_f^2 (FP32 forward pair law)
+    float pp_negc = 0.f;               // -1/b_f^2, rounded away from zero (FP32 pair law)
     std::vector<float> pp_arows;       // kARows * kARowFloats: the FP32 adjoint pair law by s
     size_t pp_aoff = 0;                // byte offset of pp_arows in `tables`
     std::vector<float> pp_srows;       // kSRows * 4 floats: the FP32 forward pair law by s = r^2

@@ -59,9 +59,10 @@ template <bool ADJ> struct PPGeo {
 // the cutoff, and sparse particles often have all their neighbours close to
 // it, the table holds h = g / (b_f^2 - s)^5, smooth and nonzero up to and
 // beyond the cutoff (there the factorised form gives h = Q(1 - r/b_f) /
-// (r^3 (b_f (b_f + r))^5), continued analytically past b_f), and the kernel
-// forms g = h max(b_f^2 - s, 0)^5: exact zero beyond the cutoff and the same
-// relative accuracy near it as elsewhere.  s is cut at its float exponent and
+// (r^3 (b_f (b_f + r))^5), continued analytically past b_f), scaled by
+// b_f^10, and the kernel forms g = (h b_f^10) w^5 with w = 1 - s/b_f^2
+// clamped to [0, 1]: exact zero beyond the cutoff and the same relative
+// accuracy near it as elsewhere.  s is cut at its float exponent and
 // top 4 mantissa bits (1/16 of an octave, s in [2^-31, 64)); on each piece h
 // is the cubic through its values at the 4 Chebyshev nodes (fitted in FP64
 // on the host from eq. (2) evaluated in extended precision).  For exact s the
@@ -89,16 +90,20 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
     s = t;
 }
 
-// g(r) * D accumulated into (fx, fy, fz) from the s-indexed table (LDS);
-// bf2 = b_f^2 in FP32.
-__device__ __forceinline__ void pair_accumulate(float dx, float dy, float dz, float bf2, float &fx,
+// g(r) * D accumulated into (fx, fy, fz) from the s-indexed table (LDS).
+// The table holds h b_f^10, and w = 1 - s/b_f^2 is formed as one FMA with
+// the result clamped to [0, 1] (negc = -1/b_f^2 rounded away from zero, so
+// that w = 0 for every s >= b_f^2).
+__device__ __forceinline__ float unit_clamp(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
+
+__device__ __forceinline__ void pair_accumulate(float dx, float dy, float dz, float negc, float &fx,
                                                 float &fy, float &fz) {
     const float s = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, 0x1p-31f)));
     const uint32_t b = __float_as_uint(s);
     const float4 c = pair_srows[(b >> (23 - kSMantBits)) - kSRow0];
     const float z = __uint_as_float((b & ((1u << (23 - kSMantBits)) - 1u)) | 0x3F800000u) - 1.0f;
     const float h = fmaf(fmaf(fmaf(c.w, z, c.z), z, c.y), z, c.x);
-    const float w = fmaxf(bf2 - s, 0.0f);
+    const float w = unit_clamp(fmaf(s, negc, 1.0f));
     const float w2 = w * w;
     const float g = (h * w) * (w2 * w2);
     fx = fmaf(g, dx, fx);
@@ -108,12 +113,12 @@ __device__ __forceinline__ void pair_accumulate(float dx, float dy, float dz, fl
 
 // Adjoint of one pair for the cotangents: out += J(D) u with u = abar_j -
 // abar_i and J = d(g D)/dD = g I + 2 g_s D D^T, g_s = dg/ds.  The adjoint
-// table holds h = g / (b_f^2 - s)^5 as a quintic per 1/8 octave of s, so
-// that its derivative is accurate too; with w = max(b_f^2 - s, 0):
-// g = h w^5 and g_s = w^4 (h_s w - 5 h), h_s = (dh/dz) 2^-e for s in
-// [2^e, 2^(e+1)).
+// table holds H = h b_f^10 = g / (1 - s/b_f^2)^5 as a quintic per 1/8 octave
+// of s, so that its derivative is accurate too; with w = 1 - s/b_f^2 clamped
+// to [0, 1] as in pair_accumulate: g = H w^5 and g_s = w^4 (H_s w - 5 H /
+// b_f^2), H_s = (dH/dz) 2^-e for s in [2^e, 2^(e+1)).
 __device__ __forceinline__ void pair_adjoint(float dx, float dy, float dz, float ux, float uy,
-                                             float uz, float bf2, float &ox, float &oy,
+                                             float uz, float negc, float &ox, float &oy,
                                              float &oz) {
     const float s = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, 0x1p-31f)));
     const uint32_t b = __float_as_uint(s);
@@ -131,11 +136,11 @@ __device__ __forceinline__ void pair_adjoint(float dx, float dy, float dz, float
     h = fmaf(h, z, c0.y);
     hz = fmaf(hz, z, h);
     h = fmaf(h, z, c0.x);
-    const float w = fmaxf(bf2 - s, 0.0f);
+    const float w = unit_clamp(fmaf(s, negc, 1.0f));
     const float w2 = w * w;
     const float w4 = w2 * w2;
     const float g = (h * w) * w4;
-    const float gs2 = 2.0f * w4 * fmaf(hz * inv2e, w, -5.0f * h);  // 2 g_s
+    const float gs2 = 2.0f * w4 * fmaf(hz * inv2e, w, (5.0f * negc) * h);  // 2 g_s
     const float du = (dx * ux + dy * uy + dz * uz) * gs2;
     ox += g * ux + du * dx;
     oy += g * uy + du * dy;
@@ -154,7 +159,7 @@ template <bool ADJ>
 __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *__restrict__ pos,
                                                      const uint32_t *__restrict__ cs, int n,
                                                      int nt, const float4 *__restrict__ table,
-                                                     float bf2, float gm,
+                                                     float negc, float gm,
                                                      const float *__restrict__ abar,
                                                      float *__restrict__ acc, int accumulate,
                                                      const uint32_t *__restrict__ order,
@@ -383,17 +388,17 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                             for (; v < v1; ++v) {
                                 const float4 qa = xs[v], aa = as_[v];
                                 pair_adjoint(qa.x - xi, qa.y - yi, qa.z - zi, aa.x - aix, aa.y - aiy,
-                                             aa.z - aiz, bf2, fx, fy, fz);
+                                             aa.z - aiz, negc, fx, fy, fz);
                             }
                         } else {
                             for (; v + 1 < v1; v += 2) {
                                 const float4 qa = xs[v], qb = xs[v + 1];
-                                pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, bf2, fx, fy, fz);
-                                pair_accumulate(qb.x - xi, qb.y - yi, qb.z - zi, bf2, fx, fy, fz);
+                                pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, negc, fx, fy, fz);
+                                pair_accumulate(qb.x - xi, qb.y - yi, qb.z - zi, negc, fx, fy, fz);
                             }
                             if (v < v1) {
                                 const float4 qa = xs[v];
-                                pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, bf2, fx, fy, fz);
+                                pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, negc, fx, fy, fz);
                             }
                         }
                         kahan_add(sx, cx, fx);
@@ -416,9 +421,9 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                             if (ADJ)
                                 pair_adjoint(xj - xi, yj - yi, zj - zi, abar[pj] - aix,
                                              abar[(int64_t)n + pj] - aiy, abar[2 * (int64_t)n + pj] - aiz,
-                                             bf2, fx, fy, fz);
+                                             negc, fx, fy, fz);
                             else
-                                pair_accumulate(xj - xi, yj - yi, zj - zi, bf2, fx, fy, fz);
+                                pair_accumulate(xj - xi, yj - yi, zj - zi, negc, fx, fy, fz);
                         }
                         kahan_add(sx, cx, fx);
                         kahan_add(sy, cy, fy);
@@ -485,7 +490,7 @@ long double pair_h_direct(double b_pp, double b_f, double rd) {
     return (r_over_r(b_pp) - r_over_r(bf)) / (w * w * w * w * w);
 }
 
-// A table of h = g / (b_f^2 - s)^5 by s = r^2 (see the comments above
+// A table of H = h b_f^10 = g / (1 - s/b_f^2)^5 by s = r^2 (see the comments above
 // pair_accumulate and pair_adjoint): row t covers s in [2^e (1 + i/2^mb),
 // 2^e (1 + (i+1)/2^mb)) with (e + 127) 2^mb + i = t + row0, and holds the
 // polynomial of degree D-1 in z in [0, 2^-mb) through h at the D Chebyshev
@@ -495,6 +500,7 @@ long double pair_h_direct(double b_pp, double b_f, double rd) {
 void fit_h_rows(const cube2_ctx *ctx, int mb, int D, int row0, int nrows, int row_floats,
                 std::vector<float> &out) {
     const double pi = 3.14159265358979323846, bf = ctx->cfg.b_fine;
+    const long double bf10 = std::pow((long double)bf, 10);  // rows hold H = h b_f^10
     std::vector<double> yn(D);
     for (int j = 0; j < D; ++j) yn[j] = 0.5 + 0.5 * std::cos(pi * (j + 0.5) / D);
     out.assign((size_t)nrows * row_floats, 0.0f);
@@ -507,7 +513,7 @@ void fit_h_rows(const cube2_ctx *ctx, int mb, int D, int row0, int nrows, int ro
             const double sv = scale * (1.0 + (i + yn[j]) * inv);
             double p = 1.0;
             for (int k = 0; k < D; ++k, p *= yn[j]) A[j][k] = p;
-            A[j][D] = (double)pair_h_direct(ctx->cfg.b_pp, bf, std::sqrt(sv));
+            A[j][D] = (double)(pair_h_direct(ctx->cfg.b_pp, bf, std::sqrt(sv)) * bf10);
         }
         for (int c = 0; c < D; ++c) {  // Gauss-Jordan, partial pivoting
             int pv = c;
@@ -550,7 +556,10 @@ int build_pair_table(cube2_ctx *ctx) {
     const double w = bf / K;
     ctx->pp_K = K;
     ctx->pp_kinv = (float)(K / bf);
-    ctx->pp_bf2 = (float)(bf * bf);
+    // -1/b_f^2 rounded away from zero: s * (-negc) >= 1 whenever s >= b_f^2
+    float cinv = (float)(1.0 / (bf * bf));
+    if ((double)cinv < 1.0 / (bf * bf)) cinv = std::nextafter(cinv, 2.0f * cinv);
+    ctx->pp_negc = -cinv;
     ctx->pp_rows64.assign((size_t)(K + 1) * kPairRow, 0.0);
     for (int k = 0; k < K; ++k) {
         const double mid = (k + 0.5) * w, rl = k * w, rr = (k + 1) * w;
@@ -611,7 +620,7 @@ int launch_pp_kernel(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, in
     const uint32_t *order = tile_order_ptr(work, L);
     uint32_t *queue = tile_queue_ptr(ctx, work, L);
     pp_kernel<ADJ><<<persistent_grid(pp_kernel<ADJ>, PPGeo<ADJ>::BLOCK, ntiles), PPGeo<ADJ>::BLOCK, 0, s>>>(
-        pos, cs, (int)n, nt, table, ctx->pp_bf2,
+        pos, cs, (int)n, nt, table, ctx->pp_negc,
         (float)(ctx->cfg.g_newton * ctx->cfg.m_p), abar, out, accumulate, order, queue, ntiles);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
@@ -649,7 +658,7 @@ extern "C" int cube2_pair_law_f32(const cube2_ctx *ctx, const float *d, float *g
         std::memcpy(&z, &zb, 4);
         z -= 1.0f;
         const float h = std::fmaf(std::fmaf(std::fmaf(c[3], z, c[2]), z, c[1]), z, c[0]);
-        const float w = std::fmax(ctx->pp_bf2 - s, 0.0f);
+        const float w = std::fmin(std::fmax(std::fmaf(s, ctx->pp_negc, 1.0f), 0.0f), 1.0f);
         const float w2 = w * w;
         g[i] = (h * w) * (w2 * w2);
     }
@@ -681,11 +690,11 @@ extern "C" int cube2_pair_jacobian_f32(const cube2_ctx *ctx, const float *d, flo
             hz = std::fmaf(hz, z, h);
             h = std::fmaf(h, z, c[k]);
         }
-        const float w = std::fmax(ctx->pp_bf2 - s, 0.0f);
+        const float w = std::fmin(std::fmax(std::fmaf(s, ctx->pp_negc, 1.0f), 0.0f), 1.0f);
         const float w2 = w * w;
         const float w4 = w2 * w2;
         g[i] = (h * w) * w4;
-        gs[i] = 0.5f * (2.0f * w4 * std::fmaf(hz * inv2e, w, -5.0f * h));
+        gs[i] = 0.5f * (2.0f * w4 * std::fmaf(hz * inv2e, w, (5.0f * ctx->pp_negc) * h));
     }
     return CUBE2_OK;
 }
