@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
     for (int i = tid; i < 3 * kCN * kCN * kCN; i += kBlock) (&A[0][0])[i] = 0ull;
     const float S = fixed_scale(amax_bits, c), invS = 1.0f / S;
     const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
-    for (int i = tid; i <= kTileCells; i += kBlock) cst[i] = cs[key0 + i];
+    stage_cell_starts<kBlock>(cst, cs, key0);
     __syncthreads();
     const float inv = 1.0f / 32768.0f;
     // Wave-uniform loop over the tile's particles.  An IOS cell lies in one
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(kBlock) void xbar_gather_kernel(
     tile_of_block(blockIdx.x, nt, tx, ty, tz);
     const int tid = threadIdx.x;
     const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
-    for (int i = tid; i <= kTileCells; i += kBlock) cst[i] = cs[key0 + i];
+    stage_cell_starts<kBlock>(cst, cs, key0);
     const int a0x = tx * kTileFine, a0y = ty * kTileFine, a0z = tz * kTileFine;
     if (WITH_E) stage_block<kFS, kBlock>(pf, phi_f, n_f, a0x - 2, a0y - 2, a0z - 2);
     if (rb_f) {

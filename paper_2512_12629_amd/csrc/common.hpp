@@ -210,6 +210,26 @@ __device__ __forceinline__ int first_lane(unsigned long long mask) {
     return __ffsll((long long)mask) - 1;
 }
 
+// The kTileCells + 1 particle starts of one tile (cs[key0 .. key0 + 512])
+// into LDS, every load of a thread issued before its LDS stores.
+template <int BLOCK>
+__device__ __forceinline__ void stage_cell_starts(uint32_t *__restrict__ dst,
+                                                  const uint32_t *__restrict__ cs, uint32_t key0) {
+    constexpr int PER = (kTileCells + 1 + BLOCK - 1) / BLOCK;
+    uint32_t v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = (int)threadIdx.x + k * BLOCK;
+        if (i <= kTileCells) v[k] = cs[key0 + i];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = (int)threadIdx.x + k * BLOCK;
+        if (i <= kTileCells) dst[i] = v[k];
+    }
+}
+
+
 // Copy the periodic S^3 block of an n^3 mesh starting at node (x0, y0, z0)
 // (wrapped) into LDS, x fastest.  The loads of one thread are issued as a
 // batch (all in flight before the LDS stores), so a block pays one memory

@@ -330,10 +330,24 @@ __global__ __launch_bounds__(256) void c2r_x(const typename Cx<T>::c *__restrict
     const bool live = row < nrows;
     const C *src = in + (live ? row : 0) * pitch;
     C *x = sh + rl * XL;
-    for (int k = tl; k <= M; k += TR) {
-        C v = src[k];
-        if (k == 0 || k == M) v.y = T(0);  // DC and Nyquist are real
-        x[k] = v;
+    {
+        // all loads of the row issued before the LDS stores
+        constexpr int KL = (M + 1 + TR - 1) / TR;
+        C vin[KL];
+#pragma unroll
+        for (int i = 0; i < KL; ++i) {
+            const int k = tl + i * TR;
+            if (k <= M) vin[i] = src[k];
+        }
+#pragma unroll
+        for (int i = 0; i < KL; ++i) {
+            const int k = tl + i * TR;
+            if (k <= M) {
+                C v = vin[i];
+                if (k == 0 || k == M) v.y = T(0);  // DC and Nyquist are real
+                x[k] = v;
+            }
+        }
     }
     __syncthreads();
     C v[M1];

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(
     tile_of_block(blockIdx.x, nt, tx, ty, tz);
     const int tid = threadIdx.x;
     const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
-    for (int i = tid; i <= kTileCells; i += kBlock) cst[i] = cs[key0 + i];
+    stage_cell_starts<kBlock>(cst, cs, key0);
     const int ax0 = tx * kTileFine, ay0 = ty * kTileFine, az0 = tz * kTileFine;
     stage_block<kFS, kBlock>(pf, phi_f, n_f, ax0 - 2, ay0 - 2, az0 - 2);
     const int CS = (kTileFine >> hshift) + 5;

@@ -24,7 +24,7 @@ __global__ __launch_bounds__(kBlock) void kick_drift_kernel(
     tile_of_block(blockIdx.x, nt, tx, ty, tz);
     const int tid = threadIdx.x;
     const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
-    for (int i = tid; i <= kTileCells; i += kBlock) cst[i] = cs[key0 + i];
+    stage_cell_starts<kBlock>(cst, cs, key0);
     __syncthreads();
     const int64_t span = (int64_t)n_f << kFracBits;
     const int cbase[3] = {tx * kTileIos, ty * kTileIos, tz * kTileIos};
