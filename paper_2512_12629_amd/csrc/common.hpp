@@ -218,9 +218,9 @@ __device__ __forceinline__ void stage_cell_starts(uint32_t *__restrict__ dst,
     constexpr int PER = (kTileCells + 1 + BLOCK - 1) / BLOCK;
     uint32_t v[PER];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
+    for (int k = 0; k < PER; ++k) {  // unconditional loads (clamped index)
         const int i = (int)threadIdx.x + k * BLOCK;
-        if (i <= kTileCells) v[k] = cs[key0 + i];
+        v[k] = cs[key0 + (i <= kTileCells ? i : kTileCells)];
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -231,33 +231,47 @@ __device__ __forceinline__ void stage_cell_starts(uint32_t *__restrict__ dst,
 
 
 // Copy the periodic S^3 block of an n^3 mesh starting at node (x0, y0, z0)
-// (wrapped) into LDS, x fastest.  The loads of one thread are issued as a
-// batch (all in flight before the LDS stores), so a block pays one memory
-// latency per batch instead of one per element.
-template <int S, int BLOCK, typename T>
+// (wrapped) into LDS, x fastest.  Each wave copies 64/S whole x-rows per pass
+// (lane -> (row, x) fixed for the whole copy, so a row is one contiguous
+// read), the row's (y, z) is advanced incrementally, and the loads of one
+// thread are issued in batches (all in flight before the LDS stores).
+template <int S, int BLOCK, typename T, int MAXB = 20>
 __device__ __forceinline__ void stage_block(T *__restrict__ dst, const T *__restrict__ mesh, int n,
                                             int x0, int y0, int z0) {
-    constexpr int TOT = S * S * S;
-    constexpr int PER = (TOT + BLOCK - 1) / BLOCK;
-    constexpr int BATCH = PER < 12 ? PER : 12;
-    const int tid = threadIdx.x;
+    static_assert(S <= 64 && BLOCK % 64 == 0, "rows must fit a wave");
+    constexpr int RPW = 64 / S;          // rows per wave and pass
+    constexpr int RPP = RPW * (BLOCK / 64);
+    constexpr int ROWS = S * S;
+    constexpr int PASSES = (ROWS + RPP - 1) / RPP;
+    constexpr int BATCH = PASSES < MAXB ? PASSES : MAXB;
+    constexpr int DY = RPP % S, DZ = RPP / S;
+    const int lane = (int)(threadIdx.x & 63u), w = (int)(threadIdx.x >> 6);
+    const int rr = lane / S, lx = lane - rr * S;
+    const bool act = rr < RPW;
+    const int r0 = w * RPW + rr;
+    const int m = n - 1;
+    const int gx = (x0 + lx) & m;
+    int ly = r0 % S, lz = r0 / S;       // (y, z) of this thread's current row
 #pragma unroll
-    for (int k0 = 0; k0 < PER; k0 += BATCH) {
+    for (int p0 = 0; p0 < PASSES; p0 += BATCH) {
         T v[BATCH];
 #pragma unroll
         for (int k = 0; k < BATCH; ++k) {
-            const int i = tid + (k0 + k) * BLOCK;
-            v[k] = T(0);
-            if (k0 + k < PER && i < TOT) {
-                const int lx = i % S, ly = (i / S) % S, lz = i / (S * S);
-                v[k] = mesh[((int64_t)((z0 + lz) & (n - 1)) * n + ((y0 + ly) & (n - 1))) * n +
-                            ((x0 + lx) & (n - 1))];
+            // unconditional: the wrapped (y, z, x) is a node of the mesh for
+            // every lane, also those whose value is not stored
+            const uint32_t row = (uint32_t)((z0 + lz) & m) * (uint32_t)n + (uint32_t)((y0 + ly) & m);
+            v[k] = mesh[row * (uint32_t)n + (uint32_t)gx];
+            ly += DY;
+            lz += DZ;
+            if (ly >= S) {
+                ly -= S;
+                ++lz;
             }
         }
 #pragma unroll
         for (int k = 0; k < BATCH; ++k) {
-            const int i = tid + (k0 + k) * BLOCK;
-            if (k0 + k < PER && i < TOT) dst[i] = v[k];
+            const int r = r0 + (p0 + k) * RPP;
+            if (act && p0 + k < PASSES && r < ROWS) dst[r * S + lx] = v[k];
         }
     }
 }
