@@ -81,6 +81,9 @@ def lib():
             "orc_fd_force": (None, [i, p, p]),
             "orc_fd_force_adjoint": (None, [i, p, p]),
             "orc_interp": (None, [i64, p, i, d, i, p, p]),
+            "orc_deposit_tsc_fx": (None, [i64, p, i, d, p]),
+            "orc_deposit_tsc": (None, [i64, p, i, d, i, p]),
+            "orc_interp_tsc": (None, [i64, p, i, d, i, p, p]),
             "orc_interp_adjoint_mesh": (None, [i64, p, i, d, i, p, p]),
             "orc_interp_adjoint_pos": (None, [i64, p, i, d, i, p, p, p]),
             "orc_deposit_adjoint_pos": (None, [i64, p, i, d, i, p, p]),
@@ -126,6 +129,7 @@ class Params:
     m_p: float = 1.0
     G_N: float = 1.0
     alias_nmax: int = 2
+    assign: int = 2          # 2 = CIC, 3 = TSC (eq. 5)
 
     def levels(self):
         """[(H, n, b_alpha, b_prev)] in fine-cell units; b_prev=inf for PM1."""
@@ -247,23 +251,31 @@ def ios_order(q: np.ndarray, n_fine: int):
 # PM steps
 # ---------------------------------------------------------------------------
 
-def deposit_fx(xf: np.ndarray, n: int, H: float) -> np.ndarray:
-    """Exact integer CIC deposit (uint64), weights in units of 2^-45."""
+def deposit_fx(xf: np.ndarray, n: int, H: float, p: int = 2) -> np.ndarray:
+    """Exact integer deposit (uint64): CIC (p = 2) with weights in units of
+    2^-45, or TSC (p = 3, eq. 5) with 16-bit weights, units of 2^-48."""
     xf = np.ascontiguousarray(xf, dtype=np.float64)
     out = np.zeros((n, n, n), dtype=np.uint64)
-    lib().orc_deposit_fx(xf.shape[1], _p(xf), int(n), float(H), _p(out))
+    f = lib().orc_deposit_tsc_fx if p == 3 else lib().orc_deposit_fx
+    f(xf.shape[1], _p(xf), int(n), float(H), _p(out))
     return out
 
 
-def density_f32(acc: np.ndarray) -> np.ndarray:
-    """FP32 density: the integer accumulator rounded to nearest, times 2^-45."""
-    return (acc.astype(np.float32) * np.float32(2.0 ** -45)).astype(np.float32)
+def fx_scale(p: int = 2) -> float:
+    """Value of one unit of the integer deposit accumulator (a particle mass)."""
+    return 2.0 ** -48 if p == 3 else 2.0 ** -45
 
 
-def deposit(xf: np.ndarray, n: int, H: float, quant: bool = True) -> np.ndarray:
+def density_f32(acc: np.ndarray, p: int = 2) -> np.ndarray:
+    """FP32 density: the integer accumulator rounded to nearest, times its unit."""
+    return (acc.astype(np.float32) * np.float32(fx_scale(p))).astype(np.float32)
+
+
+def deposit(xf: np.ndarray, n: int, H: float, quant: bool = True, p: int = 2) -> np.ndarray:
     xf = np.ascontiguousarray(xf, dtype=np.float64)
     out = np.zeros((n, n, n))
-    lib().orc_deposit(xf.shape[1], _p(xf), int(n), float(H), int(quant), _p(out))
+    f = lib().orc_deposit_tsc if p == 3 else lib().orc_deposit
+    f(xf.shape[1], _p(xf), int(n), float(H), int(quant), _p(out))
     return out
 
 
@@ -289,12 +301,13 @@ def fd_force_adjoint(Eb: np.ndarray) -> np.ndarray:
     return out
 
 
-def interp(xf: np.ndarray, E: np.ndarray, H: float, quant: bool = True) -> np.ndarray:
+def interp(xf: np.ndarray, E: np.ndarray, H: float, quant: bool = True, p: int = 2) -> np.ndarray:
     xf = np.ascontiguousarray(xf, dtype=np.float64)
     E = np.ascontiguousarray(E, dtype=np.float64)
     n = E.shape[1]
     acc = np.zeros((3, xf.shape[1]))
-    lib().orc_interp(xf.shape[1], _p(xf), int(n), float(H), int(quant), _p(E), _p(acc))
+    f = lib().orc_interp_tsc if p == 3 else lib().orc_interp
+    f(xf.shape[1], _p(xf), int(n), float(H), int(quant), _p(E), _p(acc))
     return acc
 
 
@@ -309,14 +322,14 @@ class Oracle:
     def green(self, level: int) -> np.ndarray:
         if level not in self._G:
             H, n, b_a, b_prev = self.p.levels()[level]
-            self._G[level] = green_table(n, b_a / H, b_prev / H, self.p.alias_nmax, 2)
+            self._G[level] = green_table(n, b_a / H, b_prev / H, self.p.alias_nmax, self.p.assign)
         return self._G[level]
 
     # -- forward ------------------------------------------------------------
     def level_mesh(self, xf, level):
         """(rho, phi, E) of one level, unit particle mass."""
         H, n, _, _ = self.p.levels()[level]
-        rho = deposit(xf, n, H, self.quant)
+        rho = deposit(xf, n, H, self.quant, self.p.assign)
         phi = potential(rho, self.green(level))
         return rho, phi, fd_force(phi)
 
@@ -324,7 +337,7 @@ class Oracle:
         """Acceleration of one PM level in fine-cell units (G m included)."""
         H = self.p.levels()[level][0]
         _, _, E = self.level_mesh(xf, level)
-        return interp(xf, E, H, self.quant) * (self.p.G_N * self.p.m_p / H ** 2)
+        return interp(xf, E, H, self.quant, self.p.assign) * (self.p.G_N * self.p.m_p / H ** 2)
 
     def pm_accel(self, xf):
         return sum(self.pm_level_accel(xf, l) for l in range(len(self.p.levels())))
@@ -367,6 +380,7 @@ class Oracle:
           rhobar = K phibar                           (G real, even: K^T = K)
           xbar_i = c grad_x W . (abar_i . E) + grad_x W . rhobar
         """
+        assert self.p.assign == 2, "the oracle adjoints are written for CIC"
         H = self.p.levels()[level][0]
         n = self.p.levels()[level][1]
         c = self.p.G_N * self.p.m_p / H ** 2
@@ -407,6 +421,7 @@ class Oracle:
 
     def deposit_adjoint(self, xf, rhobar, level=None):
         """x-bar of the unit-mass density of the finest level for rhobar."""
+        assert self.p.assign == 2, "the oracle adjoints are written for CIC"
         if level is None:
             level = len(self.p.levels()) - 1
         H, n, _, _ = self.p.levels()[level]

@@ -239,6 +239,123 @@ void orc_deposit(int64_t N, const double *x, int n, double H, int quant, double 
     }
 }
 
+/* ------------------------------------------------------------------ */
+/* TSC assignment and interpolation (eq. 5)                            */
+/* ------------------------------------------------------------------ */
+
+/* eq. (5): W(x) = 3/4 - x^2 for |x| <= 1/2, (3/2 - |x|)^2 / 2 for
+ * 1/2 <= |x| <= 3/2, 0 beyond, x the distance to a node in level cells.
+ * A particle at y (level units) has nearest node n0 = floor(y + 1/2) and
+ * d = y - n0 in [-1/2, 1/2); nodes n0-1, n0, n0+1 get (1/2 - d)^2/2,
+ * 3/4 - d^2, (1/2 + d)^2/2.  With quant != 0 the in-cell fraction of y is
+ * first truncated to 15 bits (as for CIC), so d = m 2^-15 with integer m in
+ * [-2^14, 2^14). */
+static inline void tsc_coord(double x, double H, int quant, long *n0, long *m, double *d)
+{
+    double y = x / H;
+    double fl = floor(y);
+    double fr = y - fl;
+    if (quant) fr = floor(fr * 32768.0) / 32768.0;
+    if (fr < 0.5) {
+        *n0 = (long)fl;
+        *d = fr;
+    } else {
+        *n0 = (long)fl + 1;
+        *d = fr - 1.0;
+    }
+    *m = (long)floor(*d * 32768.0);
+}
+
+/* The fixed-point TSC weights (units 2^-16) for d = m 2^-15: the outer two
+ * are the eq. (5) values rounded to nearest (ties up), the centre one takes
+ * the remainder so that the three sum to exactly 2^16. */
+static inline void tsc_weights_fx(long m, uint64_t w[3])
+{
+    const uint64_t a = (uint64_t)(16384 - m), b = (uint64_t)(16384 + m);
+    w[0] = (a * a + 16384u) >> 15;
+    w[2] = (b * b + 16384u) >> 15;
+    w[1] = 65536u - w[0] - w[2];
+}
+
+static inline void tsc_weights(long m, double d, int quant, double w[3])
+{
+    if (quant) {
+        uint64_t wi[3];
+        tsc_weights_fx(m, wi);
+        for (int k = 0; k < 3; ++k) w[k] = (double)wi[k] / 65536.0;
+    } else {
+        w[0] = 0.5 * (0.5 - d) * (0.5 - d);
+        w[1] = 0.75 - d * d;
+        w[2] = 0.5 * (0.5 + d) * (0.5 + d);
+    }
+}
+
+/* Exact integer TSC deposit: acc[n0 + s - 1] += prod_d W_d(s_d), s_d in
+ * {0, 1, 2}, with the fixed-point weights above; density = acc * 2^-48. */
+void orc_deposit_tsc_fx(int64_t N, const double *x, int n, double H, uint64_t *acc)
+{
+    for (int64_t i = 0; i < N; ++i) {
+        long n0[3];
+        uint64_t w[3][3];
+        for (int d = 0; d < 3; ++d) {
+            long m;
+            double dd;
+            tsc_coord(x[d * N + i], H, 1, &n0[d], &m, &dd);
+            tsc_weights_fx(m, w[d]);
+        }
+        for (int sz = 0; sz < 3; ++sz)
+            for (int sy = 0; sy < 3; ++sy)
+                for (int sx = 0; sx < 3; ++sx)
+                    acc[midx(n0[0] + sx - 1, n0[1] + sy - 1, n0[2] + sz - 1, n)] +=
+                        w[0][sx] * w[1][sy] * w[2][sz];
+    }
+}
+
+/* Floating-point TSC deposit, unit mass per particle. */
+void orc_deposit_tsc(int64_t N, const double *x, int n, double H, int quant, double *rho)
+{
+    for (int64_t i = 0; i < N; ++i) {
+        long n0[3];
+        double w[3][3];
+        for (int d = 0; d < 3; ++d) {
+            long m;
+            double dd;
+            tsc_coord(x[d * N + i], H, quant, &n0[d], &m, &dd);
+            tsc_weights(m, dd, quant, w[d]);
+        }
+        for (int sz = 0; sz < 3; ++sz)
+            for (int sy = 0; sy < 3; ++sy)
+                for (int sx = 0; sx < 3; ++sx)
+                    rho[midx(n0[0] + sx - 1, n0[1] + sy - 1, n0[2] + sz - 1, n)] +=
+                        w[0][sx] * w[1][sy] * w[2][sz];
+    }
+}
+
+/* TSC interpolation with the deposit's weights: acc_i += sum_s W_s E(n0+s-1). */
+void orc_interp_tsc(int64_t N, const double *x, int n, double H, int quant,
+                    const double *E, double *acc)
+{
+    size_t n3 = (size_t)n * n * n;
+#pragma omp parallel for
+    for (int64_t i = 0; i < N; ++i) {
+        long n0[3];
+        double w[3][3];
+        for (int d = 0; d < 3; ++d) {
+            long m;
+            double dd;
+            tsc_coord(x[d * N + i], H, quant, &n0[d], &m, &dd);
+            tsc_weights(m, dd, quant, w[d]);
+        }
+        for (int sz = 0; sz < 3; ++sz)
+            for (int sy = 0; sy < 3; ++sy)
+                for (int sx = 0; sx < 3; ++sx) {
+                    double W = w[0][sx] * w[1][sy] * w[2][sz];
+                    size_t c = midx(n0[0] + sx - 1, n0[1] + sy - 1, n0[2] + sz - 1, n);
+                    for (int d = 0; d < 3; ++d) acc[d * N + i] += W * E[d * n3 + c];
+                }
+    }
+}
+
 /* eq. (7) with the physical sign: E_d(n) = -[(2/3)(phi(n+e_d) - phi(n-e_d))
  *                                     - (1/12)(phi(n+2e_d) - phi(n-2e_d))]. */
 void orc_fd_force(int n, const double *phi, double *E)
