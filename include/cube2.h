@@ -71,8 +71,15 @@ enum cube2_status_code {
 enum cube2_flags {
     CUBE2_PP_OFF = 1,         /* cube2_pp_force becomes a no-op (paper, sec. 4:
                                  PP may be disabled for fast runs) */
-    CUBE2_FP64_FORM = 2       /* also build the FP64 tables and size the work
+    CUBE2_FP64_FORM = 2,      /* also build the FP64 tables and size the work
                                  buffer for the *_f64 entry points */
+    CUBE2_ASSIGN_TSC = 4      /* TSC assignment (eq. 5) on every PM level instead
+                                 of CIC: 16-bit fixed-point weights, density =
+                                 accumulator * 2^-48, G with W = sinc^3 (eq. 9);
+                                 cube2_deposit_backward and
+                                 cube2_pm_force_backward return
+                                 CUBE2_EUNSUPPORTED (their adjoints are built for
+                                 CIC) */
 };
 
 /* Force parameters (section 2.1.1 and 2.2.2).  All lengths in fine cells. */
@@ -150,7 +157,11 @@ int cube2_pack(cube2_ctx *ctx, const float *x, int64_t n, uint16_t *pos, uint32_
  * acc(node) = sum_i prod_d w_d, w = (2^15 - f, f), f the 15-bit in-cell
  * fraction of the particle on that level, summed exactly in uint64; the
  * FP32 density (particle masses per level cell) is acc rounded to nearest
- * times 2^-45.  level 0 = fine (n_fine^3), 1 = coarse.  rho (device,
+ * times 2^-45.  With CUBE2_ASSIGN_TSC: TSC (eq. 5), three nodes per axis
+ * around the nearest node with the 16-bit weights round((2^14 -/+ m)^2 /
+ * 2^15) and 2^16 minus their sum (m the offset from the nearest node in
+ * units of 2^-15), density = acc * 2^-48; the overflow guard then trips at
+ * 2^17 particles in a tile's gathered box or 2^14 in a tile.  level 0 = fine (n_fine^3), 1 = coarse.  rho (device,
  * [z][y][x]) receives the FP32 density; rho_fx (device, optional, may be
  * NULL) receives the integer accumulator.  Bit-exact and order independent.
  * Sets CUBE2_EOVERFLOW in the status word if a tile holds 2^16 or more

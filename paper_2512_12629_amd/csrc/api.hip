@@ -125,6 +125,7 @@ int cube2_create(const cube2_config *cfg, cube2_ctx **out) {
     ctx->n_cells = (int64_t)ctx->n_ios * ctx->n_ios * ctx->n_ios;
     ctx->n_levels = c.coarse_ratio ? 2 : 1;
     ctx->fp64 = (c.flags & CUBE2_FP64_FORM) != 0;
+    ctx->tsc = (c.flags & CUBE2_ASSIGN_TSC) != 0;
     Level &F = ctx->lv[0];
     F.n = c.n_fine;
     F.H = 1;
@@ -326,6 +327,7 @@ int cube2_deposit_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *
                            int64_t n, int level, const float *rho_bar, float *x_bar,
                            int accumulate, void *work, size_t work_bytes, cube2_stream_t stream) {
     CHECK_READY();
+    if (ctx->tsc) return CUBE2_EUNSUPPORTED;  // adjoints are built for CIC
     if (n < 0 || n > INT32_MAX || !cell_start || !rho_bar || (n > 0 && (!pos || !x_bar)))
         return CUBE2_EINVAL;
     if (level < 0 || level >= ctx->n_levels) return CUBE2_EINVAL;
@@ -340,6 +342,7 @@ int cube2_pm_force_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t 
                             int64_t n, const float *acc_bar, float *x_bar, int accumulate,
                             void *work, size_t work_bytes, cube2_stream_t stream) {
     CHECK_READY();
+    if (ctx->tsc) return CUBE2_EUNSUPPORTED;  // adjoints are built for CIC
     if (n < 0 || n > INT32_MAX || !cell_start || (n > 0 && (!pos || !acc_bar || !x_bar)))
         return CUBE2_EINVAL;
     CHECK_WORK(n);
@@ -410,7 +413,7 @@ int cube2_pm_force_f64(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell
     for (int l = 0; l < ctx->n_levels; ++l) {
         uint64_t *m = l == 0 ? ff : fc;
         const int64_t nl = ctx->lv[l].n;
-        rcode = launch_fx_to_f64(m, nl * nl * nl, s);
+        rcode = launch_fx_to_f64(m, nl * nl * nl, ctx->tsc ? 0x1p-48 : 0x1p-45, s);
         if (rcode) return rcode;
         double *md = reinterpret_cast<double *>(m);
         rcode = launch_potential64(ctx, l, md, md, spec, s);

@@ -70,6 +70,7 @@ struct cube2_ctx {
     std::vector<double> pp_rows64;     // the same rows in FP64
     size_t pp64_off = 0;               // FP64 rows (CUBE2_FP64_FORM only)
     bool fp64 = false;                 // CUBE2_FP64_FORM
+    bool tsc = false;                  // CUBE2_ASSIGN_TSC: TSC instead of CIC on every PM level
     int n_f = 0, n_ios = 0, nt = 0;   // fine cells, IOS cells, tiles per side
     int64_t n_cells = 0;               // IOS cells
     int n_levels = 1;                  // 1 or 2; level 0 = fine, 1 = coarse
@@ -306,7 +307,7 @@ int launch_interp64(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int
                     hipStream_t s);
 int launch_pp64(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, double *acc,
                 int accumulate, hipStream_t s);
-int launch_fx_to_f64(uint64_t *buf, int64_t m, hipStream_t s);
+int launch_fx_to_f64(uint64_t *buf, int64_t m, double unit, hipStream_t s);
 int launch_interp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                   const float *phi_f, const float *phi_c, float *acc, int accumulate,
                   hipStream_t s);

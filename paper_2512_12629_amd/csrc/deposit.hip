@@ -18,15 +18,36 @@
 // Coarse level: only the tile's own particles are assigned; the tile's
 // coarse footprint (16/H + 1 nodes per axis) is accumulated in LDS and added
 // to a uint64 coarse mesh with global atomics, then converted to FP32.
+//
+// TSC (eq. 5, context flag CUBE2_ASSIGN_TSC): a particle with in-cell
+// fraction f has nearest node n0 = j + [f >= 1/2] and offset m = f - [f >=
+// 1/2] (units 2^-15, m in [-2^14, 2^14)); nodes n0-1, n0, n0+1 get the
+// 16-bit weights W- = round((2^14 - m)^2 / 2^15), W+ = round((2^14 + m)^2 /
+// 2^15) and W0 = 2^16 - W- - W+ (eq. 5 to 2^-16, summing exactly to one
+// particle).  Products are below 2^47, the density is the accumulator times
+// 2^-48.  A fine node then also receives particles of the next IOS cell up,
+// so the gathered box is 10^3 IOS cells; the coarse footprint has 16/H + 3
+// nodes per axis.
 #include "common.hpp"
 
 namespace cube2 {
 namespace {
 
-constexpr int kBox = kTileIos + 1;            // 9 IOS cells per axis
-constexpr int kSegs = kBox * kBox * kBox;     // 729
-constexpr int kSegPerThread = (kSegs + kBlock - 1) / kBlock;  // 3
-constexpr int kCoarseMax = kTileFine / 2 + 1; // 9 coarse nodes per axis (ratio 2)
+// Gathered box of IOS cells per axis: [c0-1, c0+8) for CIC, [c0-1, c0+9) for TSC.
+template <int P> struct DepGeo {
+    static constexpr int BOX = kTileIos + (P == 3 ? 2 : 1);
+    static constexpr int SEGS = BOX * BOX * BOX;              // 729 or 1000
+    static constexpr int SEG_PER_THREAD = (SEGS + kBlock - 1) / kBlock;
+    static constexpr int CMAX = kTileFine / 2 + (P == 3 ? 3 : 1);  // coarse nodes per axis (ratio 2)
+};
+
+// TSC weights of offset m (units 2^-15, m in [-2^14, 2^14)) in units of 2^-16.
+__device__ __forceinline__ void tsc_weights(int m, uint32_t (&w)[3]) {
+    const uint32_t a = (uint32_t)(16384 - m), b = (uint32_t)(16384 + m);
+    w[0] = (a * a + 16384u) >> 15;
+    w[2] = (b * b + 16384u) >> 15;
+    w[1] = 65536u - w[0] - w[2];
+}
 
 __global__ void fill_u64(unsigned long long *p, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -61,6 +82,80 @@ __device__ __forceinline__ void deposit_fine(const int (&b)[3], const uint32_t (
                 if ((unsigned)nx >= (unsigned)kTileFine) continue;
                 atomicAdd(&acc_f[(nz * kTileFine + ny) * kTileFine + nx],
                           (unsigned long long)wyz * w[0][sx]);
+            }
+        }
+}
+
+// Fine TSC weights of one particle of box segment b, added to the tile's
+// fine nodes that it reaches (nodes n0-1 .. n0+1 per axis).
+__device__ __forceinline__ void deposit_fine_tsc(const int (&b)[3], const uint32_t (&o)[3],
+                                                 unsigned long long *acc_f) {
+    int j[3];
+    uint32_t w[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int f = (int)(o[d] & 0x7FFFu);
+        const int hi = f >= 16384 ? 1 : 0;
+        j[d] = 2 * (b[d] - 1) + (int)(o[d] >> 15) + hi - 1;  // node n0 - 1, rel. to the tile
+        tsc_weights(f - (hi << 15), w[d]);
+    }
+#pragma unroll
+    for (int sz = 0; sz < 3; ++sz)
+#pragma unroll
+        for (int sy = 0; sy < 3; ++sy) {
+            const int nz = j[2] + sz, ny = j[1] + sy;
+            if ((unsigned)nz >= (unsigned)kTileFine || (unsigned)ny >= (unsigned)kTileFine)
+                continue;
+            const uint32_t wyz = w[1][sy] * w[2][sz];  // < 2^32
+#pragma unroll
+            for (int sx = 0; sx < 3; ++sx) {
+                const int nx = j[0] + sx;
+                if ((unsigned)nx >= (unsigned)kTileFine) continue;
+                atomicAdd(&acc_f[(nz * kTileFine + ny) * kTileFine + nx],
+                          (unsigned long long)wyz * w[0][sx]);
+            }
+        }
+}
+
+// Coarse TSC weights of the wave's own-tile particles, added to the tile's
+// coarse footprint (LDS index = coarse node - tile origin + 1), wave-summed
+// when every own lane shares its nearest node.
+__device__ __forceinline__ void deposit_coarse_wave_tsc(bool own, const int (&b)[3],
+                                                        const uint32_t (&o)[3], int hshift, int NC,
+                                                        unsigned long long *acc_c) {
+    const unsigned long long om = __ballot(own);
+    if (om == 0ull) return;
+    int j[3];
+    uint32_t w[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const uint32_t q = ((uint32_t)(b[d] - 1) << 16) + o[d];  // tile-relative
+        const uint32_t y = q >> hshift;                           // 2^-15 coarse cells
+        const int f = (int)(y & 0x7FFFu);
+        const int hi = f >= 16384 ? 1 : 0;
+        j[d] = (int)(y >> kFracBits) + hi;                        // n0, LDS index of n0 - 1
+        tsc_weights(f - (hi << 15), w[d]);
+        if (!own) w[d][0] = w[d][1] = w[d][2] = 0u;
+    }
+    const int key = own ? (j[2] * NC + j[1]) * NC + j[0] : -1;
+    const int lead = first_lane(om);
+    const int key0 = __shfl(key, lead, 64);
+    const bool uniform = __ballot(own && key != key0) == 0ull;
+#pragma unroll
+    for (int sz = 0; sz < 3; ++sz)
+#pragma unroll
+        for (int sy = 0; sy < 3; ++sy) {
+            const uint32_t wyz = w[1][sy] * w[2][sz];
+#pragma unroll
+            for (int sx = 0; sx < 3; ++sx) {
+                const unsigned long long v = (unsigned long long)wyz * w[0][sx];
+                const int off = (sz * NC + sy) * NC + sx;
+                if (uniform) {
+                    const unsigned long long t = wave_sum(v);
+                    if ((int)(threadIdx.x & 63) == lead) atomicAdd(&acc_c[key0 + off], t);
+                } else if (own) {
+                    atomicAdd(&acc_c[key + off], v);
+                }
             }
         }
 }
@@ -108,12 +203,14 @@ __device__ __forceinline__ void deposit_coarse_wave(bool own, const int (&b)[3],
         }
 }
 
-template <bool FINE, bool COARSE>
+template <bool FINE, bool COARSE, int P>
 __global__ __launch_bounds__(kBlock) void deposit_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs, int n, int n_f, int nt,
     float *__restrict__ rho_f, unsigned long long *__restrict__ rho_f_fx,
     unsigned long long *__restrict__ coarse_acc, int n_c, int hshift, uint32_t *status,
     const uint32_t *__restrict__ order, uint32_t *__restrict__ queue) {
+    constexpr int kBox = DepGeo<P>::BOX, kSegs = DepGeo<P>::SEGS;
+    constexpr int kSegPerThread = DepGeo<P>::SEG_PER_THREAD, kCoarseMax = DepGeo<P>::CMAX;
     __shared__ uint32_t seg_pre[kSegs + 1];
     __shared__ uint32_t seg_src[kSegs];
     __shared__ unsigned long long acc_f[FINE ? kTileFine * kTileFine * kTileFine : 1];
@@ -123,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
 
     const int tid = threadIdx.x;
     const int n_ios = nt * kTileIos;
-    const int NC = (kTileFine >> hshift) + 1;  // coarse nodes per axis touched by the tile
+    const int NC = (kTileFine >> hshift) + (P == 3 ? 3 : 1);  // coarse nodes per axis touched
     int round = 0, tx, ty, tz;
     while (claim_tile(order, queue, nt * nt * nt, nt, round, &tile_sh, tx, ty, tz)) {
         const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
@@ -133,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
         if (COARSE)
             for (int i = tid; i < NC * NC * NC; i += kBlock) acc_c[i] = 0ull;
 
-        // particle ranges of the 9^3 box of IOS cells [c0-1, c0+8)
+        // particle ranges of the box of IOS cells [c0-1, c0+kBox-1)
         uint32_t cnt[kSegPerThread], src[kSegPerThread], sum = 0;
 #pragma unroll
         for (int k = 0; k < kSegPerThread; ++k) {
@@ -166,10 +263,13 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
         if (tid == 0) {
             seg_pre[kSegs] = total;
             // Overflow guard: a fine node sums at most `total` weights of 2^45
-            // each; a coarse node sums the own particles of at most 8 tiles.
+            // (CIC) or 2^47 (TSC) each; a coarse node sums the own particles
+            // of at most 8 tiles.
             const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
             const uint32_t own = cs[key0 + kTileCells] - cs[key0];
-            if ((FINE && total >= (1u << 19)) || (COARSE && own >= (1u << 16))) atomicOr(status, 1u);
+            const uint32_t fine_max = P == 3 ? (1u << 17) : (1u << 19);
+            const uint32_t own_max = P == 3 ? (1u << 14) : (1u << 16);
+            if ((FINE && total >= fine_max) || (COARSE && own >= own_max)) atomicOr(status, 1u);
         }
         __syncthreads();
 
@@ -200,10 +300,15 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
                 const bool valid = sg[k] >= 0;
                 const int s = valid ? sg[k] : 0;
                 const int b[3] = {s % kBox, (s / kBox) % kBox, s / (kBox * kBox)};
-                if (FINE && valid) deposit_fine(b, o[k], acc_f);
-                if (COARSE)
-                    deposit_coarse_wave(valid && b[0] > 0 && b[1] > 0 && b[2] > 0, b, o[k], hshift, NC,
-                                        acc_c);
+                const bool own = valid && b[0] > 0 && b[1] > 0 && b[2] > 0 && b[0] <= kTileIos &&
+                                 b[1] <= kTileIos && b[2] <= kTileIos;
+                if (P == 3) {
+                    if (FINE && valid) deposit_fine_tsc(b, o[k], acc_f);
+                    if (COARSE) deposit_coarse_wave_tsc(own, b, o[k], hshift, NC, acc_c);
+                } else {
+                    if (FINE && valid) deposit_fine(b, o[k], acc_f);
+                    if (COARSE) deposit_coarse_wave(own, b, o[k], hshift, NC, acc_c);
+                }
             }
         }
         __syncthreads();
@@ -215,13 +320,14 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
                           lz = i / (kTileFine * kTileFine);
                 const int64_t g = ((int64_t)(a0z + lz) * n_f + (a0y + ly)) * n_f + (a0x + lx);
                 const unsigned long long v = acc_f[i];
-                rho_f[g] = (float)v * 0x1p-45f;
+                rho_f[g] = (float)v * (P == 3 ? 0x1p-48f : 0x1p-45f);
                 if (rho_f_fx) rho_f_fx[g] = v;
             }
         }
         if (COARSE) {
-            const int A0x = (tx * kTileFine) >> hshift, A0y = (ty * kTileFine) >> hshift,
-                      A0z = (tz * kTileFine) >> hshift;
+            const int lo = P == 3 ? 1 : 0;  // footprint starts one node below (TSC)
+            const int A0x = ((tx * kTileFine) >> hshift) - lo, A0y = ((ty * kTileFine) >> hshift) - lo,
+                      A0z = ((tz * kTileFine) >> hshift) - lo;
             for (int i = tid; i < NC * NC * NC; i += kBlock) {
                 const unsigned long long v = acc_c[i];
                 if (!v) continue;
@@ -235,12 +341,34 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
 }
 
 __global__ void coarse_finalize(const unsigned long long *__restrict__ accum, int64_t m,
-                                float *__restrict__ rho, unsigned long long *__restrict__ fx) {
+                                float *__restrict__ rho, unsigned long long *__restrict__ fx,
+                                float unit) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     const unsigned long long v = accum[i];
-    rho[i] = (float)v * 0x1p-45f;
+    rho[i] = (float)v * unit;
     if (fx) fx[i] = v;
+}
+
+template <int P>
+int launch_deposit_kernels(bool fine, bool coarse, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                           int n_f, int nt, float *rho_f, unsigned long long *ffx,
+                           unsigned long long *cacc, int n_c, int hshift, uint32_t *status,
+                           const uint32_t *order, uint32_t *queue, int ntiles, hipStream_t s) {
+    if (fine && coarse)
+        deposit_kernel<true, true, P><<<persistent_grid(deposit_kernel<true, true, P>, kBlock, ntiles),
+                                        kBlock, 0, s>>>(pos, cs, (int)n, n_f, nt, rho_f, ffx, cacc,
+                                                        n_c, hshift, status, order, queue);
+    else if (fine)
+        deposit_kernel<true, false, P><<<persistent_grid(deposit_kernel<true, false, P>, kBlock, ntiles),
+                                         kBlock, 0, s>>>(pos, cs, (int)n, n_f, nt, rho_f, ffx, cacc,
+                                                         n_c, hshift, status, order, queue);
+    else
+        deposit_kernel<false, true, P><<<persistent_grid(deposit_kernel<false, true, P>, kBlock, ntiles),
+                                         kBlock, 0, s>>>(pos, cs, (int)n, n_f, nt, nullptr, nullptr,
+                                                         cacc, n_c, hshift, status, order, queue);
+    CUBE2_LAUNCH_CHECK();
+    return CUBE2_OK;
 }
 
 }  // namespace
@@ -269,23 +397,17 @@ int launch_deposit(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int6
     const uint32_t *order = tile_order_ptr(work, L);
     uint32_t *queue = tile_queue_ptr(ctx, work, L);
     const int ntiles = (int)blocks;
-    if (fine && coarse)
-        deposit_kernel<true, true><<<persistent_grid(deposit_kernel<true, true>, kBlock, ntiles),
-                                     kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, rho_f, ffx, cacc,
-                                                     n_c, hshift, status, order, queue);
-    else if (fine)
-        deposit_kernel<true, false><<<persistent_grid(deposit_kernel<true, false>, kBlock, ntiles),
-                                      kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, rho_f, ffx,
-                                                      cacc, n_c, hshift, status, order, queue);
+    if (ctx->tsc)
+        r = launch_deposit_kernels<3>(fine, coarse, pos, cs, n, ctx->n_f, nt, rho_f, ffx, cacc, n_c,
+                                      hshift, status, order, queue, ntiles, s);
     else
-        deposit_kernel<false, true><<<persistent_grid(deposit_kernel<false, true>, kBlock, ntiles),
-                                      kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, nullptr,
-                                                      nullptr, cacc, n_c, hshift, status, order,
-                                                      queue);
-    CUBE2_LAUNCH_CHECK();
+        r = launch_deposit_kernels<2>(fine, coarse, pos, cs, n, ctx->n_f, nt, rho_f, ffx, cacc, n_c,
+                                      hshift, status, order, queue, ntiles, s);
+    if (r) return r;
     if (coarse) {
         coarse_finalize<<<(unsigned)((mc + 255) / 256), 256, 0, s>>>(
-            cacc, mc, rho_c, reinterpret_cast<unsigned long long *>(rho_c_fx));
+            cacc, mc, rho_c, reinterpret_cast<unsigned long long *>(rho_c_fx),
+            ctx->tsc ? 0x1p-48f : 0x1p-45f);
         CUBE2_LAUNCH_CHECK();
     }
     return CUBE2_OK;

@@ -1,5 +1,6 @@
 // fp64.hip -- pieces of the FP64 plain form that have no FP32 twin:
-//   * the density in FP64: the deposit's exact uint64 accumulator times 2^-45;
+//   * the density in FP64: the deposit's exact uint64 accumulator times its
+//     unit (2^-45 for CIC, 2^-48 for TSC);
 //   * the PP force (eq. 4d) in FP64, one thread per particle looping over its
 //     27 neighbour IOS cells in HBM, with the pair law of eq. (2) evaluated
 //     from the FP64 rows of the same exact piecewise-polynomial table that
@@ -11,10 +12,10 @@
 namespace cube2 {
 namespace {
 
-__global__ void fx_to_f64_kernel(uint64_t *buf, int64_t m) {
+__global__ void fx_to_f64_kernel(uint64_t *buf, int64_t m, double unit) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
-    const double v = (double)buf[i] * 0x1p-45;
+    const double v = (double)buf[i] * unit;
     buf[i] = (uint64_t)__double_as_longlong(v);
 }
 
@@ -75,9 +76,9 @@ __global__ __launch_bounds__(kBlock) void pp64_kernel(
 
 }  // namespace
 
-int launch_fx_to_f64(uint64_t *buf, int64_t m, hipStream_t s) {
+int launch_fx_to_f64(uint64_t *buf, int64_t m, double unit, hipStream_t s) {
     if (m <= 0) return CUBE2_OK;
-    fx_to_f64_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(buf, m);
+    fx_to_f64_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(buf, m, unit);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }

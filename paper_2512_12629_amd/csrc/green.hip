@@ -5,7 +5,7 @@
 //   G(k) = -4 pi sum_a W^2(k_a) (d . k_a) dS2(|k_a|) / |k_a|^2
 //          / ( |d|^2 [sum_a W^2(k_a)]^2 )
 // with k_a = k + 2 pi a, |a_d| <= nmax (section 2.1.2: max |n| <= 2),
-// W(k) = prod_d sinc^2(k_d / 2) (CIC, eq. 9 with exponent 2),
+// W(k) = prod_d sinc^p(k_d / 2) (eq. 9: p = 2 for CIC, 3 for TSC),
 // d_d = 4/3 sin k_d - 1/6 sin 2 k_d (eq. 10, D = i d),
 // dS2 = S^2(|k|, b_a) - S^2(|k|, b_prev) (eq. 12; S of eq. 13; S(k, inf) = 0).
 // This is eq. (11) with D . R* = -4 pi (d . k_a) dS2 / k_a^2.  G = 0 where
@@ -32,7 +32,8 @@ __device__ double profile_k(double u) {
 }
 
 template <typename T>
-__global__ void green_kernel(T *__restrict__ out, int n, double ba, double bprev, int nmax) {
+__global__ void green_kernel(T *__restrict__ out, int n, double ba, double bprev, int nmax,
+                             int p) {
     const int h = n / 2 + 1;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)h * h * h) return;
@@ -49,14 +50,15 @@ __global__ void green_kernel(T *__restrict__ out, int n, double ba, double bprev
         out[idx] = T(0);
         return;
     }
-    // Per-axis alias windows w[a][j] = sinc^4((k_a + 2 pi j)/2), j = -nmax..nmax.
+    // Per-axis alias windows w[a][j] = sinc^(2p)((k_a + 2 pi j)/2), j = -nmax..nmax
+    // (W^2 of eq. 9: p = 2 for CIC, 3 for TSC).
     double w[3][9];
     for (int a = 0; a < 3; ++a)
         for (int j = -nmax; j <= nmax; ++j) {
             const double t = (double)m[a] / (double)n + (double)j;  // (k + 2 pi j)/2 = pi t
-            double s = (t == 0.0) ? 1.0 : sinpi(t) / (kPi * t);
-            s = s * s;
-            w[a][j + nmax] = s * s;
+            const double s = (t == 0.0) ? 1.0 : sinpi(t) / (kPi * t);
+            const double s2 = s * s;
+            w[a][j + nmax] = p == 3 ? s2 * s2 * s2 : s2 * s2;
         }
     double U = 0.0, V = 0.0;
     for (int jz = -nmax; jz <= nmax; ++jz)
@@ -104,8 +106,8 @@ int launch_green(cube2_ctx *ctx, hipStream_t s) {
         float *g = reinterpret_cast<float *>(ctx->tables + L.g_off);
         const double ba = L.b_a / L.H;
         const double bp = L.b_prev > 0.0 ? L.b_prev / L.H : -1.0;
-        green_kernel<float><<<(unsigned)((pts + 255) / 256), 256, 0, s>>>(g, L.n, ba, bp,
-                                                                          ctx->cfg.alias_nmax);
+        green_kernel<float><<<(unsigned)((pts + 255) / 256), 256, 0, s>>>(
+            g, L.n, ba, bp, ctx->cfg.alias_nmax, ctx->tsc ? 3 : 2);
         CUBE2_LAUNCH_CHECK();
         if (ctx->fp64) {
             twiddle64_kernel<<<(L.n + 255) / 256, 256, 0, s>>>(
@@ -113,7 +115,7 @@ int launch_green(cube2_ctx *ctx, hipStream_t s) {
             CUBE2_LAUNCH_CHECK();
             green_kernel<double><<<(unsigned)((pts + 255) / 256), 256, 0, s>>>(
                 reinterpret_cast<double *>(ctx->tables + L.g64_off), L.n, ba, bp,
-                ctx->cfg.alias_nmax);
+                ctx->cfg.alias_nmax, ctx->tsc ? 3 : 2);
             CUBE2_LAUNCH_CHECK();
         }
     }

@@ -9,6 +9,9 @@
 // the 6 potential values along each axis around its 2x2 CIC footprint and
 // forms E = -[(2/3)(phi(+1) - phi(-1)) - (1/12)(phi(+2) - phi(-2))] at its two
 // nodes per axis, weighted with the deposit's 15-bit integer weights.
+// With TSC assignment (eq. 5) each particle has three nodes per axis around
+// its nearest node, with the deposit's 16-bit weights, and the staged tiles
+// carry one more halo node on each side.
 // The kernel is templated on the real type: float for the production path,
 // double for the FP64 plain form.
 #include "common.hpp"
@@ -16,8 +19,12 @@
 namespace cube2 {
 namespace {
 
-constexpr int kFS = kTileFine + 5;        // 21: fine tile with halo
-constexpr int kCSMax = kTileFine / 2 + 5; // 13: coarse tile with halo (ratio 2)
+// TSC: nodes n0-1..n0+1 with n0 in [0, 16/H] plus the stencil: 3 below, 4 above
+template <int P> struct InterpGeo {
+    static constexpr int HLO = P == 3 ? 3 : 2;                 // halo below the tile
+    static constexpr int FS = kTileFine + (P == 3 ? 7 : 5);    // 21 or 23
+    static constexpr int CSMAX = kTileFine / 2 + (P == 3 ? 7 : 5);
+};
 
 // FD force at the particle's two nodes along one axis, CIC-weighted.
 // p points at phi(node j) on that axis; st is the axis stride in LDS.
@@ -51,13 +58,60 @@ __device__ __forceinline__ void gather(const T *P, int S, int jx, int jy, int jz
         }
 }
 
-template <bool TWO, typename T>
+// FD force at the particle's three TSC nodes along one axis (n0-1, n0, n0+1),
+// weighted; p points at phi(n0) on that axis, st is the axis stride in LDS.
+template <typename T>
+__device__ __forceinline__ T axis_force3(const T *p, int st, const T (&w)[3]) {
+    const T pm3 = p[-3 * st], pm2 = p[-2 * st], pm1 = p[-st], p0 = p[0], p1 = p[st],
+            p2 = p[2 * st], p3 = p[3 * st];
+    const T c1 = T(2.0 / 3.0), c2 = T(1.0 / 12.0);
+    const T e0 = -(c1 * (p0 - pm2) - c2 * (p1 - pm3));
+    const T e1 = -(c1 * (p1 - pm1) - c2 * (p2 - pm2));
+    const T e2 = -(c1 * (p2 - p0) - c2 * (p3 - pm1));
+    return w[0] * e0 + w[1] * e1 + w[2] * e2;
+}
+
+// TSC-weighted force of a staged potential tile P (side S) at the particle
+// whose nearest node is (nx, ny, nz) in LDS coordinates.
+template <typename T>
+__device__ __forceinline__ void gather3(const T *P, int S, int nx, int ny, int nz,
+                                        const T (&wx)[3], const T (&wy)[3], const T (&wz)[3],
+                                        T &ax, T &ay, T &az) {
+    const int SS = S * S;
+    ax = ay = az = T(0);
+#pragma unroll
+    for (int s1 = 0; s1 < 3; ++s1)
+#pragma unroll
+        for (int s2 = 0; s2 < 3; ++s2) {
+            ax += wy[s1] * wz[s2] * axis_force3(P + (nz - 1 + s2) * SS + (ny - 1 + s1) * S + nx, 1, wx);
+            ay += wx[s1] * wz[s2] * axis_force3(P + (nz - 1 + s2) * SS + ny * S + nx - 1 + s1, S, wy);
+            az += wx[s1] * wy[s2] * axis_force3(P + nz * SS + (ny - 1 + s2) * S + nx - 1 + s1, SS, wz);
+        }
+}
+
+// TSC weights (eq. 5, 16-bit fixed point as the deposit) of the 15-bit
+// fraction f of one axis: nearest-node shift hi and the three weights.
+template <typename T>
+__device__ __forceinline__ int tsc_axis(int f, T (&w)[3]) {
+    const int hi = f >= 16384 ? 1 : 0;
+    const int m = f - (hi << 15);
+    const uint32_t a = (uint32_t)(16384 - m), b = (uint32_t)(16384 + m);
+    const uint32_t w0 = (a * a + 16384u) >> 15, w2 = (b * b + 16384u) >> 15;
+    const T inv = T(1.0 / 65536.0);
+    w[0] = (T)w0 * inv;
+    w[2] = (T)w2 * inv;
+    w[1] = (T)(65536u - w0 - w2) * inv;
+    return hi;
+}
+
+template <bool TWO, int P, typename T>
 __global__ __launch_bounds__(kBlock) void interp_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs, int n, int n_f, int nt,
     const T *__restrict__ phi_f, const T *__restrict__ phi_c, int n_c, int hshift, T scale_f,
     T scale_c, T *__restrict__ acc, int accumulate) {
-    __shared__ T pf[kFS * kFS * kFS];
-    __shared__ T pc[TWO ? kCSMax * kCSMax * kCSMax : 1];
+    constexpr int FS = InterpGeo<P>::FS, HLO = InterpGeo<P>::HLO, CSM = InterpGeo<P>::CSMAX;
+    __shared__ T pf[FS * FS * FS];
+    __shared__ T pc[TWO ? CSM * CSM * CSM : 1];
     __shared__ uint32_t cst[kTileCells + 1];
 
     int tx, ty, tz;
@@ -66,22 +120,24 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(
     const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
     stage_cell_starts<kBlock>(cst, cs, key0);
     const int ax0 = tx * kTileFine, ay0 = ty * kTileFine, az0 = tz * kTileFine;
-    stage_block<kFS, kBlock>(pf, phi_f, n_f, ax0 - 2, ay0 - 2, az0 - 2);
-    const int CS = (kTileFine >> hshift) + 5;
+    stage_block<FS, kBlock>(pf, phi_f, n_f, ax0 - HLO, ay0 - HLO, az0 - HLO);
+    const int CS = (kTileFine >> hshift) + FS - kTileFine;
     if (TWO) {
-        const int cx0 = ax0 >> hshift, cy0 = ay0 >> hshift, cz0 = az0 >> hshift;
-        switch (CS) {
-            case 13: stage_block<13, kBlock>(pc, phi_c, n_c, cx0 - 2, cy0 - 2, cz0 - 2); break;
-            case 9: stage_block<9, kBlock>(pc, phi_c, n_c, cx0 - 2, cy0 - 2, cz0 - 2); break;
-            default: stage_block<7, kBlock>(pc, phi_c, n_c, cx0 - 2, cy0 - 2, cz0 - 2); break;
+        const int cx0 = (ax0 >> hshift) - HLO, cy0 = (ay0 >> hshift) - HLO,
+                  cz0 = (az0 >> hshift) - HLO;
+        switch (hshift) {
+            case 1: stage_block<kTileFine / 2 + FS - kTileFine, kBlock>(pc, phi_c, n_c, cx0, cy0, cz0); break;
+            case 2: stage_block<kTileFine / 4 + FS - kTileFine, kBlock>(pc, phi_c, n_c, cx0, cy0, cz0); break;
+            default: stage_block<kTileFine / 8 + FS - kTileFine, kBlock>(pc, phi_c, n_c, cx0, cy0, cz0); break;
         }
     }
     __syncthreads();
     const uint32_t p0 = cst[0], p1 = cst[kTileCells];
     const T inv = T(1.0 / 32768.0);
-    // two particles per thread at a time: both cell searches and all position
-    // loads are issued before the first particle is processed
-    constexpr int kBatch = 2;
+    // two particles per thread at a time (one for TSC, whose gather needs
+    // more registers): the cell searches and all position loads are issued
+    // before the first particle is processed
+    constexpr int kBatch = P == 3 ? 1 : 2;
     for (uint32_t pb = p0 + tid; pb < p1; pb += kBlock * kBatch) {
         int ub[kBatch];
         uint32_t ob[kBatch][3];
@@ -103,33 +159,59 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(
             const int u = ub[k];
             const int uc[3] = {u & 7, (u >> 3) & 7, u >> 6};
             int jf[3], jc[3];
-            T wf[3][2], wc[3][2];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const uint32_t o = ob[k][d];
-                const int f = (int)(o & 0x7FFFu);
-                jf[d] = 2 * uc[d] + (int)(o >> 15) + 2;       // +2: LDS halo
-                wf[d][1] = (T)f * inv;
-                wf[d][0] = (T)(32768 - f) * inv;
-                if (TWO) {
-                    const uint32_t q = ((uint32_t)uc[d] << 16) + o;  // tile-relative, 2^-15 units
-                    const int fc = (int)((q >> hshift) & 0x7FFFu);
-                    jc[d] = (int)(q >> (kFracBits + hshift)) + 2;
-                    wc[d][1] = (T)fc * inv;
-                    wc[d][0] = (T)(32768 - fc) * inv;
-                }
-            }
             T a[3];
-            gather(pf, kFS, jf[0], jf[1], jf[2], wf[0], wf[1], wf[2], a[0], a[1], a[2]);
-            a[0] *= scale_f;
-            a[1] *= scale_f;
-            a[2] *= scale_f;
-            if (TWO) {
-                T c[3];
-                gather(pc, CS, jc[0], jc[1], jc[2], wc[0], wc[1], wc[2], c[0], c[1], c[2]);
-                a[0] += scale_c * c[0];
-                a[1] += scale_c * c[1];
-                a[2] += scale_c * c[2];
+            if (P == 3) {
+                T wf[3][3], wc[3][3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const uint32_t o = ob[k][d];
+                    // nearest node n0 = fine cell + hi, in LDS coordinates
+                    jf[d] = 2 * uc[d] + (int)(o >> 15) + tsc_axis<T>((int)(o & 0x7FFFu), wf[d]) + HLO;
+                    if (TWO) {
+                        const uint32_t q = ((uint32_t)uc[d] << 16) + o;  // tile-relative, 2^-15 units
+                        const uint32_t y = q >> hshift;
+                        jc[d] = (int)(y >> kFracBits) + tsc_axis<T>((int)(y & 0x7FFFu), wc[d]) + HLO;
+                    }
+                }
+                gather3(pf, FS, jf[0], jf[1], jf[2], wf[0], wf[1], wf[2], a[0], a[1], a[2]);
+                a[0] *= scale_f;
+                a[1] *= scale_f;
+                a[2] *= scale_f;
+                if (TWO) {
+                    T c[3];
+                    gather3(pc, CS, jc[0], jc[1], jc[2], wc[0], wc[1], wc[2], c[0], c[1], c[2]);
+                    a[0] += scale_c * c[0];
+                    a[1] += scale_c * c[1];
+                    a[2] += scale_c * c[2];
+                }
+            } else {
+                T wf[3][2], wc[3][2];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const uint32_t o = ob[k][d];
+                    const int f = (int)(o & 0x7FFFu);
+                    jf[d] = 2 * uc[d] + (int)(o >> 15) + HLO;
+                    wf[d][1] = (T)f * inv;
+                    wf[d][0] = (T)(32768 - f) * inv;
+                    if (TWO) {
+                        const uint32_t q = ((uint32_t)uc[d] << 16) + o;  // tile-relative, 2^-15 units
+                        const int fc = (int)((q >> hshift) & 0x7FFFu);
+                        jc[d] = (int)(q >> (kFracBits + hshift)) + HLO;
+                        wc[d][1] = (T)fc * inv;
+                        wc[d][0] = (T)(32768 - fc) * inv;
+                    }
+                }
+                gather(pf, FS, jf[0], jf[1], jf[2], wf[0], wf[1], wf[2], a[0], a[1], a[2]);
+                a[0] *= scale_f;
+                a[1] *= scale_f;
+                a[2] *= scale_f;
+                if (TWO) {
+                    T c[3];
+                    gather(pc, CS, jc[0], jc[1], jc[2], wc[0], wc[1], wc[2], c[0], c[1], c[2]);
+                    a[0] += scale_c * c[0];
+                    a[1] += scale_c * c[1];
+                    a[2] += scale_c * c[2];
+                }
             }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -142,23 +224,34 @@ __global__ __launch_bounds__(kBlock) void interp_kernel(
 
 }  // namespace
 
+template <int P, typename T>
+void launch_interp_kernel(cube2_ctx *ctx, unsigned blocks, const uint16_t *pos, const uint32_t *cs,
+                          int64_t n, const T *phi_f, const T *phi_c, double gm, T *acc,
+                          int accumulate, hipStream_t s) {
+    const int nt = ctx->nt;
+    if (ctx->n_levels > 1) {
+        const Level &C = ctx->lv[1];
+        interp_kernel<true, P, T><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, phi_f,
+                                                            phi_c, C.n, C.hshift, (T)gm,
+                                                            (T)(gm / ((double)C.H * C.H)), acc,
+                                                            accumulate);
+    } else {
+        interp_kernel<false, P, T><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, phi_f,
+                                                             nullptr, 1, 0, (T)gm, T(0), acc,
+                                                             accumulate);
+    }
+}
+
 template <typename T>
 int interp_levels(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                   const T *phi_f, const T *phi_c, T *acc, int accumulate, hipStream_t s) {
     const int nt = ctx->nt;
     const unsigned blocks = (unsigned)(nt * nt * nt);
     const double gm = ctx->cfg.g_newton * ctx->cfg.m_p;
-    if (ctx->n_levels > 1) {
-        const Level &C = ctx->lv[1];
-        interp_kernel<true, T><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, phi_f,
-                                                         phi_c, C.n, C.hshift, (T)gm,
-                                                         (T)(gm / ((double)C.H * C.H)), acc,
-                                                         accumulate);
-    } else {
-        interp_kernel<false, T><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, phi_f,
-                                                          nullptr, 1, 0, (T)gm, T(0), acc,
-                                                          accumulate);
-    }
+    if (ctx->tsc)
+        launch_interp_kernel<3, T>(ctx, blocks, pos, cs, n, phi_f, phi_c, gm, acc, accumulate, s);
+    else
+        launch_interp_kernel<2, T>(ctx, blocks, pos, cs, n, phi_f, phi_c, gm, acc, accumulate, s);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }
