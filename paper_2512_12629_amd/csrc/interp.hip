@@ -104,8 +104,10 @@ __device__ __forceinline__ int tsc_axis(int f, T (&w)[3]) {
     return hi;
 }
 
+// At least two waves per SIMD: left alone, the compiler gives the two-level
+// TSC gather all 256 VGPRs and one wave per SIMD.
 template <bool TWO, int P, typename T>
-__global__ __launch_bounds__(kBlock) void interp_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void interp_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs, int n, int n_f, int nt,
     const T *__restrict__ phi_f, const T *__restrict__ phi_c, int n_c, int hshift, T scale_f,
     T scale_c, T *__restrict__ acc, int accumulate) {
