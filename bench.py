@@ -203,6 +203,70 @@ def fp64_comparison(m, cfg, c, pos, cs, N, ms32, stream, timed):
             "force_rel_err_max": float(e.max()), "fine_potential_rel_err": perr}
 
 
+def pair_force_eq2(r, b):
+    """R(r, b) of eq. (2) (G m = 1), the softened pair force the method
+    approximates; r, b in fine cells."""
+    r = np.asarray(r, dtype=np.float64)
+    t = r / b
+    inner = (64 / 5 * t - 256 / 5 * t ** 3 + 32 * t ** 4 + 1536 / 35 * t ** 5 - 192 / 5 * t ** 6) / b ** 2
+    outer = (3 / 35 / np.maximum(t, 1e-300) ** 2 - 32 / 5 + 256 / 5 * t - 96 * t ** 2 + 256 / 5 * t ** 3
+             + 32 * t ** 4 - 1536 / 35 * t ** 5 + 64 / 5 * t ** 6) / b ** 2
+    return np.where(t >= 1, 1 / np.maximum(r, 1e-300) ** 2, np.where(t < 0.5, inner, outer))
+
+
+def pairwise_experiment(args):
+    """The pairwise force-accuracy experiment of section 3.1 (Fig. 1) with
+    isolated boundaries (appendix A): single particle pairs at random
+    positions and orientations in the isolation box, the GPU's total force
+    (both PM levels + PP) against the softened pair force R(r, b_pp), per
+    log-spaced bin of r: magnitude residual F/R - 1 and direction error
+    theta = acos(F.R / F R)."""
+    import torch
+    import paper_2512_12629_amd as m
+    n_f, cr = 256, 4
+    flags = m.CUBE2_ISOLATED | (m.CUBE2_ASSIGN_TSC if args.assign == "tsc" else 0)
+    cfg = m.Config(n_fine=n_f, coarse_ratio=cr, flags=flags)
+    c = m.Cube2(cfg, n_max=2)
+    L = n_f / 2                                   # isolation box, fine cells
+    edges = np.exp(np.linspace(np.log(0.05), np.log(L / 2), 31))
+    rng = np.random.default_rng(12629)
+    bins = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        res, th = [], []
+        for _ in range(args.pairs_per_bin):
+            r = float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+            u = rng.standard_normal(3)
+            u /= np.linalg.norm(u)
+            a0 = 2.0 + rng.random(3) * (L - 4.0 - r * np.abs(u))
+            xf = np.stack([a0, a0 + r * u], axis=1)
+            x32 = (xf / n_f).astype(np.float32)
+            pos, cs, perm = c.pack(torch.from_numpy(x32).cuda())
+            acc = np.empty((3, 2))
+            acc[:, perm.cpu().numpy().astype(np.int64)] = c.force(pos, cs).double().cpu().numpy()
+            q = np.floor(x32.astype(np.float64) * (n_f << 15)) / (1 << 15)   # quantised fine positions
+            d = q[:, 1] - q[:, 0]
+            rq = float(np.linalg.norm(d))
+            R = float(pair_force_eq2(rq, cfg.b_pp))
+            F = acc[:, 0]
+            res.append(np.linalg.norm(F) / R - 1.0)
+            th.append(float(np.arccos(np.clip(F @ d / (np.linalg.norm(F) * rq), -1.0, 1.0))))
+        res, th = np.array(res), np.array(th)
+        bins.append({"r_lo": float(lo), "r_hi": float(hi), "resid_mean": float(res.mean()),
+                     "resid_std": float(res.std()), "resid_min": float(res.min()),
+                     "resid_max": float(res.max()), "theta_mean": float(th.mean()),
+                     "theta_max": float(th.max())})
+    allres = np.array([b[k] for b in bins for k in ("resid_min", "resid_max")])
+    out = {"experiment": "pairwise force accuracy, isolated boundaries (section 3.1, appendix A)",
+           "config": {"n_fine": n_f, "coarse_ratio": cr, "isolation_box_fine_cells": L,
+                      "b_coarse": cfg.b_coarse, "b_fine": cfg.b_fine, "b_pp": cfg.b_pp,
+                      "assign": args.assign, "pairs_per_bin": args.pairs_per_bin},
+           "max_abs_resid": float(np.abs(allres).max()),
+           "rms_resid_all_bins": float(np.sqrt(np.mean([b["resid_std"] ** 2 + b["resid_mean"] ** 2
+                                                        for b in bins]))),
+           "bins": bins}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +280,10 @@ def main():
                     help="skip the comparison with the FP64 plain form")
     ap.add_argument("--assign", choices=["cic", "tsc"], default="cic",
                     help="mass assignment of the PM levels (CIC, or TSC of eq. 5)")
+    ap.add_argument("--pairwise", action="store_true",
+                    help="run the pairwise force-accuracy experiment (isolated boundaries) "
+                         "instead of the benchmark")
+    ap.add_argument("--pairs-per-bin", type=int, default=16)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timing, run a plain copy kernel (y = -x) of this many MiB "
                          "read + the same written, as the reference for HBM counter passes")
@@ -224,6 +292,10 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU decomposition is a design, not a build)", file=sys.stderr)
         sys.exit(2)
+
+    if args.pairwise:
+        pairwise_experiment(args)
+        return
 
     import torch
     import paper_2512_12629_amd as m

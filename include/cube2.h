@@ -73,13 +73,19 @@ enum cube2_flags {
                                  PP may be disabled for fast runs) */
     CUBE2_FP64_FORM = 2,      /* also build the FP64 tables and size the work
                                  buffer for the *_f64 entry points */
-    CUBE2_ASSIGN_TSC = 4      /* TSC assignment (eq. 5) on every PM level instead
+    CUBE2_ASSIGN_TSC = 4,     /* TSC assignment (eq. 5) on every PM level instead
                                  of CIC: 16-bit fixed-point weights, density =
                                  accumulator * 2^-48, G with W = sinc^3 (eq. 9);
                                  cube2_deposit_backward and
                                  cube2_pm_force_backward return
                                  CUBE2_EUNSUPPORTED (their adjoints are built for
                                  CIC) */
+    CUBE2_ISOLATED = 8        /* isolated boundaries (appendix A): the mesh is
+                                 twice the isolation box, the particles must lie
+                                 in [0, n_fine/2)^3 fine cells, and the
+                                 untruncated level's target force is cut at
+                                 r = n_fine/2 (its transform times
+                                 1 - sinc(k L), eq. A2) */
 };
 
 /* Force parameters (section 2.1.1 and 2.2.2).  All lengths in fine cells. */

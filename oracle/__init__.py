@@ -73,8 +73,8 @@ def lib():
             "orc_refforce": (d, [d, d]),
             "orc_refforce_dr": (d, [d, d]),
             "orc_profile_k": (d, [d, d]),
-            "orc_green_point": (d, [i, i, i, i, d, d, i, i]),
-            "orc_green_table": (None, [i, d, d, i, i, p]),
+            "orc_green_point": (d, [i, i, i, i, d, d, i, i, d]),
+            "orc_green_table": (None, [i, d, d, i, i, d, p]),
             "orc_alias_w2_1d": (d, [d, i, i]),
             "orc_deposit_fx": (None, [i64, p, i, d, p]),
             "orc_deposit": (None, [i64, p, i, d, i, p]),
@@ -130,6 +130,9 @@ class Params:
     G_N: float = 1.0
     alias_nmax: int = 2
     assign: int = 2          # 2 = CIC, 3 = TSC (eq. 5)
+    isolated: bool = False   # isolated boundaries (appendix A): particles in the
+                             # first half of the box, the untruncated level's
+                             # target force truncated at half the box length
 
     def levels(self):
         """[(H, n, b_alpha, b_prev)] in fine-cell units; b_prev=inf for PM1."""
@@ -176,17 +179,19 @@ def _b(b):
     return -1.0 if math.isinf(b) else float(b)
 
 
-def green_point(n, m, b_a, b_prev, nmax=2, p=2):
-    """G at integer wave vector m (level units: b in level cells)."""
+def green_point(n, m, b_a, b_prev, nmax=2, p=2, iso_L=0.0):
+    """G at integer wave vector m (level units: b in level cells); iso_L > 0:
+    isolated boundaries, target force truncated at r = iso_L (appendix A)."""
     return lib().orc_green_point(int(n), int(m[0]), int(m[1]), int(m[2]),
-                                 float(b_a), _b(b_prev), int(nmax), int(p))
+                                 float(b_a), _b(b_prev), int(nmax), int(p), float(iso_L))
 
 
-def green_table(n, b_a, b_prev, nmax=2, p=2):
+def green_table(n, b_a, b_prev, nmax=2, p=2, iso_L=0.0):
     """Octant table G[m3][m2][m1], m_d in [0, n/2], level units."""
     h = n // 2 + 1
     out = np.zeros((h, h, h))
-    lib().orc_green_table(int(n), float(b_a), _b(b_prev), int(nmax), int(p), _p(out))
+    lib().orc_green_table(int(n), float(b_a), _b(b_prev), int(nmax), int(p), float(iso_L),
+                          _p(out))
     return out
 
 
@@ -322,7 +327,9 @@ class Oracle:
     def green(self, level: int) -> np.ndarray:
         if level not in self._G:
             H, n, b_a, b_prev = self.p.levels()[level]
-            self._G[level] = green_table(n, b_a / H, b_prev / H, self.p.alias_nmax, self.p.assign)
+            iso_L = n / 2 if (self.p.isolated and math.isinf(b_prev)) else 0.0
+            self._G[level] = green_table(n, b_a / H, b_prev / H, self.p.alias_nmax, self.p.assign,
+                                         iso_L)
         return self._G[level]
 
     # -- forward ------------------------------------------------------------

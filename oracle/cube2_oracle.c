@@ -118,10 +118,13 @@ static double sin_frac(long m, long n)
  * (eq. (10), one component per axis), and the target force of the level,
  * eq. (12) with the Newtonian 4 pi restored:
  *     R(k) = -4 pi i k [S^2(|k|, b_a) - S^2(|k|, b_prev)] / |k|^2.
- * Where |D|^2 = 0 (every k_d in {0, pi}), G = 0.
+ * Where |D|^2 = 0 (every k_d in {0, pi}), G = 0.  With iso_L > 0 the target
+ * force is the one truncated at r = iso_L (appendix A): R(k) is multiplied
+ * by 1 - sinc(|k| iso_L), for a mesh of twice that length (isolated
+ * boundaries).
  */
 double orc_green_point(int n, int m1, int m2, int m3, double b_a, double b_prev,
-                       int nmax, int p)
+                       int nmax, int p, double iso_L)
 {
     int m[3] = {m1, m2, m3};
     double k[3], d[3], dd = 0.0;
@@ -146,6 +149,9 @@ double orc_green_point(int n, int m1, int m2, int m3, double b_a, double b_prev,
                 double kmag = sqrt(kk);
                 double sa = orc_profile_k(kmag, b_a), sp = orc_profile_k(kmag, b_prev);
                 double dS2 = sa * sa - sp * sp;
+                /* isolated boundaries (appendix A, eq. A2): the target force
+                 * truncated at r = L has the transform [1 - sinc(k L)] R(k) */
+                if (iso_L > 0.0) dS2 *= 1.0 - sinc(kmag * iso_L);
                 /* D . R* with D = i d and R* = +4 pi i k_n dS2 / k_n^2 */
                 double dk = d[0] * kn[0] + d[1] * kn[1] + d[2] * kn[2];
                 V += W2 * dk * dS2 / kk;
@@ -154,7 +160,8 @@ double orc_green_point(int n, int m1, int m2, int m3, double b_a, double b_prev,
 }
 
 /* Octant table G[m3][m2][m1], m_d in [0, n/2]. */
-void orc_green_table(int n, double b_a, double b_prev, int nmax, int p, double *out)
+void orc_green_table(int n, double b_a, double b_prev, int nmax, int p, double iso_L,
+                     double *out)
 {
     int h = n / 2 + 1;
 #pragma omp parallel for collapse(2) schedule(dynamic)
@@ -162,7 +169,7 @@ void orc_green_table(int n, double b_a, double b_prev, int nmax, int p, double *
         for (int m2 = 0; m2 < h; ++m2)
             for (int m1 = 0; m1 < h; ++m1)
                 out[((size_t)m3 * h + m2) * h + m1] =
-                    orc_green_point(n, m1, m2, m3, b_a, b_prev, nmax, p);
+                    orc_green_point(n, m1, m2, m3, b_a, b_prev, nmax, p, iso_L);
 }
 
 /* Sum over aliases of W^2 in one dimension (used by the identity checks). */

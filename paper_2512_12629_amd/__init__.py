@@ -31,6 +31,7 @@ LIB_PATH = os.path.join(_HERE, "_build", "libcube2.so")
 CUBE2_PP_OFF = 1
 CUBE2_FP64_FORM = 2
 CUBE2_ASSIGN_TSC = 4
+CUBE2_ISOLATED = 8
 _ERRORS = {0: "ok", -1: "invalid argument", -2: "unsupported configuration",
            -3: "tables or work buffer too small", -4: "deposit overflow guard",
            -5: "HIP runtime error", -6: "tables not initialised"}

@@ -126,6 +126,7 @@ int cube2_create(const cube2_config *cfg, cube2_ctx **out) {
     ctx->n_levels = c.coarse_ratio ? 2 : 1;
     ctx->fp64 = (c.flags & CUBE2_FP64_FORM) != 0;
     ctx->tsc = (c.flags & CUBE2_ASSIGN_TSC) != 0;
+    ctx->isolated = (c.flags & CUBE2_ISOLATED) != 0;
     Level &F = ctx->lv[0];
     F.n = c.n_fine;
     F.H = 1;

@@ -71,6 +71,7 @@ struct cube2_ctx {
     size_t pp64_off = 0;               // FP64 rows (CUBE2_FP64_FORM only)
     bool fp64 = false;                 // CUBE2_FP64_FORM
     bool tsc = false;                  // CUBE2_ASSIGN_TSC: TSC instead of CIC on every PM level
+    bool isolated = false;             // CUBE2_ISOLATED: isolated boundaries (appendix A)
     int n_f = 0, n_ios = 0, nt = 0;   // fine cells, IOS cells, tiles per side
     int64_t n_cells = 0;               // IOS cells
     int n_levels = 1;                  // 1 or 2; level 0 = fine, 1 = coarse

@@ -9,7 +9,8 @@
 // d_d = 4/3 sin k_d - 1/6 sin 2 k_d (eq. 10, D = i d),
 // dS2 = S^2(|k|, b_a) - S^2(|k|, b_prev) (eq. 12; S of eq. 13; S(k, inf) = 0).
 // This is eq. (11) with D . R* = -4 pi (d . k_a) dS2 / k_a^2.  G = 0 where
-// |d| = 0.  The table is stored as FP32 over the octant |m_d| <= n/2 (and,
+// |d| = 0.  With isolated boundaries (appendix A) the untruncated level's
+// dS2 is multiplied by 1 - sinc(|k_a| L), L half the mesh length.  The table is stored as FP32 over the octant |m_d| <= n/2 (and,
 // for the FP64 plain form, a second time in FP64).
 #include "common.hpp"
 
@@ -33,7 +34,7 @@ __device__ double profile_k(double u) {
 
 template <typename T>
 __global__ void green_kernel(T *__restrict__ out, int n, double ba, double bprev, int nmax,
-                             int p) {
+                             int p, double iso_L) {
     const int h = n / 2 + 1;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)h * h * h) return;
@@ -73,7 +74,10 @@ __global__ void green_kernel(T *__restrict__ out, int n, double ba, double bprev
                 const double km = sqrt(kk);
                 const double sa = profile_k(0.5 * km * ba);
                 const double sp = bprev > 0.0 ? profile_k(0.5 * km * bprev) : 0.0;
-                V += W2 * (d[0] * kx + d[1] * ky + d[2] * kz) * (sa * sa - sp * sp) / kk;
+                // isolated boundaries (appendix A): the target force truncated
+                // at r = iso_L, whose transform is [1 - sinc(k iso_L)] R(k)
+                const double iso = iso_L > 0.0 ? 1.0 - sin(km * iso_L) / (km * iso_L) : 1.0;
+                V += W2 * (d[0] * kx + d[1] * ky + d[2] * kz) * (sa * sa - sp * sp) * iso / kk;
             }
     out[idx] = (T)(-4.0 * kPi * V / (dd * U * U));
 }
@@ -106,8 +110,10 @@ int launch_green(cube2_ctx *ctx, hipStream_t s) {
         float *g = reinterpret_cast<float *>(ctx->tables + L.g_off);
         const double ba = L.b_a / L.H;
         const double bp = L.b_prev > 0.0 ? L.b_prev / L.H : -1.0;
+        // isolated boundaries: the untruncated level's force is cut at half the box
+        const double iso_L = (ctx->isolated && bp <= 0.0) ? 0.5 * L.n : 0.0;
         green_kernel<float><<<(unsigned)((pts + 255) / 256), 256, 0, s>>>(
-            g, L.n, ba, bp, ctx->cfg.alias_nmax, ctx->tsc ? 3 : 2);
+            g, L.n, ba, bp, ctx->cfg.alias_nmax, ctx->tsc ? 3 : 2, iso_L);
         CUBE2_LAUNCH_CHECK();
         if (ctx->fp64) {
             twiddle64_kernel<<<(L.n + 255) / 256, 256, 0, s>>>(
@@ -115,7 +121,7 @@ int launch_green(cube2_ctx *ctx, hipStream_t s) {
             CUBE2_LAUNCH_CHECK();
             green_kernel<double><<<(unsigned)((pts + 255) / 256), 256, 0, s>>>(
                 reinterpret_cast<double *>(ctx->tables + L.g64_off), L.n, ba, bp,
-                ctx->cfg.alias_nmax, ctx->tsc ? 3 : 2);
+                ctx->cfg.alias_nmax, ctx->tsc ? 3 : 2, iso_L);
             CUBE2_LAUNCH_CHECK();
         }
     }
