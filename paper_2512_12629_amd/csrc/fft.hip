@@ -21,6 +21,8 @@
 // double for the FP64 plain form (same passes, FP64 twiddles and G).
 #include "common.hpp"
 
+#include <type_traits>
+
 namespace cube2 {
 namespace {
 
@@ -166,46 +168,103 @@ struct Split {
 
 // ---- column (strided) line FFTs ------------------------------------------
 
+template <int N, typename T>
+constexpr bool split_exchange() { return sizeof(T) == 4 && N >= 512; }
+
 // MODE 0: one transform with sign SIGN.  MODE 2: forward, times G/n^3,
 // inverse (the z pass).  Workgroup = COLS adjacent columns x one line.
+// The 1024- and 512-point FP32 transforms move their LDS exchanges as real
+// and imaginary halves in two rounds: 66 KB of LDS instead of 128 KB, so two
+// workgroups share a CU and one's loads overlap the other's arithmetic.  The
+// z pass loads its G values at the start for the same reason.
 template <int N, int COLS, int SIGN, int MODE, typename T>
 __global__ __launch_bounds__(COLS *Split<N>::TMAX) void col_fft(
     typename Cx<T>::c *__restrict__ data, int64_t jstride, int64_t line_stride,
     const typename Cx<T>::c *__restrict__ tw, const T *__restrict__ G, int n, int pitch, T scale) {
     using C = typename Cx<T>::c;
     constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
+    constexpr bool SPLIT = split_exchange<N, T>();
+    // complex exchange: rows padded by COLS values below 16 columns
     constexpr int PAD = COLS < 16 ? COLS : 0;
     constexpr int RS1 = N2 * COLS + PAD;  // row stride of the forward exchange
     constexpr int RS2 = N1 * COLS + PAD;  // row stride of the inverse exchange
     constexpr int LDS1 = N1 * RS1, LDS2 = (MODE == 2) ? N2 * RS2 : 0;
     constexpr int LDSN = LDS1 > LDS2 ? LDS1 : LDS2;
-    __shared__ C sh[LDSN];
+    // split exchange: rows of floats padded by 16
+    constexpr int RF1 = N2 * COLS + 16, RF2 = N1 * COLS + 16;
+    constexpr int LDF1 = N1 * RF1, LDF2 = (MODE == 2) ? N2 * RF2 : 0;
+    constexpr int LDSF = LDF1 > LDF2 ? LDF1 : LDF2;
+    __shared__ C sh[SPLIT ? 1 : LDSN];
+    __shared__ T shf[SPLIT ? LDSF : 1];
 
     const int t = threadIdx.x;
     const int col = t % COLS;
     const int64_t base = (int64_t)blockIdx.y * line_stride + (int64_t)blockIdx.x * COLS + col;
     C *line = data + base;
 
+    // z pass: the G values of this thread's k1 (kz = k1 + N1 k2)
+    constexpr int NG = MODE == 2 ? N2 : 1;
+    T g[NG];
+    if (MODE == 2 && t < COLS * N1) {
+        const int h = n / 2 + 1;
+        const int kx = blockIdx.x * COLS + col;
+        const int ky = blockIdx.y;
+        const int my = ky <= n - ky ? ky : n - ky;
+        const int q = t / COLS;
+#pragma unroll
+        for (int k2 = 0; k2 < NG; ++k2) {
+            const int kz = q + N1 * k2;
+            const int mz = kz <= n - kz ? kz : n - kz;
+            g[k2] = kx < h ? G[((int64_t)mz * h + my) * h + kx] : T(0);
+        }
+    }
+
     // forward (or the single) transform, phase 1: thread owns j2, all j1
+    C v1[N1];
     if (t < COLS * N2) {
         const int j2 = t / COLS;
-        C v[N1];
 #pragma unroll
-        for (int j1 = 0; j1 < N1; ++j1) v[j1] = line[(int64_t)(j1 * N2 + j2) * jstride];
-        dft<N1, SIGN>(v);
+        for (int j1 = 0; j1 < N1; ++j1) v1[j1] = line[(int64_t)(j1 * N2 + j2) * jstride];
+        dft<N1, SIGN>(v1);
 #pragma unroll
         for (int k1 = 0; k1 < N1; ++k1) {
-            C w = tw[(j2 * k1) & (N - 1)];
-            C y = (SIGN < 0) ? cmul(v[k1], w) : cmulc(v[k1], w);
-            sh[k1 * RS1 + j2 * COLS + col] = y;
+            const C w = tw[(j2 * k1) & (N - 1)];
+            v1[k1] = (SIGN < 0) ? cmul(v1[k1], w) : cmulc(v1[k1], w);
+        }
+        if constexpr (SPLIT) {
+#pragma unroll
+            for (int k1 = 0; k1 < N1; ++k1) shf[k1 * RF1 + j2 * COLS + col] = v1[k1].x;
+        } else {
+#pragma unroll
+            for (int k1 = 0; k1 < N1; ++k1) sh[k1 * RS1 + j2 * COLS + col] = v1[k1];
         }
     }
     __syncthreads();
+    // phase 2: thread owns k1, all j2
     C v2[N2];
-    int k1 = t / COLS;
-    if (t < COLS * N1) {
+    const int k1 = t / COLS;
+    if constexpr (SPLIT) {
+        if (t < COLS * N1) {
 #pragma unroll
-        for (int j2 = 0; j2 < N2; ++j2) v2[j2] = sh[k1 * RS1 + j2 * COLS + col];
+            for (int j2 = 0; j2 < N2; ++j2) v2[j2].x = shf[k1 * RF1 + j2 * COLS + col];
+        }
+        __syncthreads();
+        if (t < COLS * N2) {
+            const int j2 = t / COLS;
+#pragma unroll
+            for (int kk = 0; kk < N1; ++kk) shf[kk * RF1 + j2 * COLS + col] = v1[kk].y;
+        }
+        __syncthreads();
+        if (t < COLS * N1) {
+#pragma unroll
+            for (int j2 = 0; j2 < N2; ++j2) v2[j2].y = shf[k1 * RF1 + j2 * COLS + col];
+        }
+    }
+    if (t < COLS * N1) {
+        if constexpr (!SPLIT) {
+#pragma unroll
+            for (int j2 = 0; j2 < N2; ++j2) v2[j2] = sh[k1 * RS1 + j2 * COLS + col];
+        }
         dft<N2, SIGN>(v2);  // v2[k2] = X[k1 + N1 k2]
     }
     if (MODE == 0) {
@@ -218,31 +277,48 @@ __global__ __launch_bounds__(COLS *Split<N>::TMAX) void col_fft(
     // ---- z pass: times G / n^3, then the inverse transform ----
     __syncthreads();  // all reads of the forward exchange are done
     if (t < COLS * N1) {
-        const int h = n / 2 + 1;
-        const int kx = blockIdx.x * COLS + col;
-        const int ky = blockIdx.y;
-        const int my = ky <= n - ky ? ky : n - ky;
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) {
-            const int kz = k1 + N1 * k2;
-            const int mz = kz <= n - kz ? kz : n - kz;
-            const T g = kx < h ? G[((int64_t)mz * h + my) * h + kx] * scale : T(0);
-            v2[k2] = cmk(v2[k2].x * g, v2[k2].y * g);
+            const T gs = g[k2 < NG ? k2 : 0] * scale;
+            v2[k2] = cmk(v2[k2].x * gs, v2[k2].y * gs);
         }
         // inverse phase 1: thread owns b = k1, holds X[a*N1 + b], a = k2
         dft<N2, +1>(v2);
 #pragma unroll
-        for (int ka = 0; ka < N2; ++ka) {
-            C w = tw[(k1 * ka) & (N - 1)];
-            sh[ka * RS2 + k1 * COLS + col] = cmulc(v2[ka], w);
+        for (int ka = 0; ka < N2; ++ka) v2[ka] = cmulc(v2[ka], tw[(k1 * ka) & (N - 1)]);
+        if constexpr (SPLIT) {
+#pragma unroll
+            for (int ka = 0; ka < N2; ++ka) shf[ka * RF2 + k1 * COLS + col] = v2[ka].x;
+        } else {
+#pragma unroll
+            for (int ka = 0; ka < N2; ++ka) sh[ka * RS2 + k1 * COLS + col] = v2[ka];
         }
     }
     __syncthreads();
-    if (t < COLS * N2) {
-        const int ka = t / COLS;
-        C v[N1];
+    // inverse phase 2: thread owns ka, all b
+    C v[N1];
+    const int ka = t / COLS;
+    if constexpr (SPLIT) {
+        if (t < COLS * N2) {
 #pragma unroll
-        for (int b = 0; b < N1; ++b) v[b] = sh[ka * RS2 + b * COLS + col];
+            for (int b = 0; b < N1; ++b) v[b].x = shf[ka * RF2 + b * COLS + col];
+        }
+        __syncthreads();
+        if (t < COLS * N1) {
+#pragma unroll
+            for (int kk = 0; kk < N2; ++kk) shf[kk * RF2 + k1 * COLS + col] = v2[kk].y;
+        }
+        __syncthreads();
+        if (t < COLS * N2) {
+#pragma unroll
+            for (int b = 0; b < N1; ++b) v[b].y = shf[ka * RF2 + b * COLS + col];
+        }
+    }
+    if (t < COLS * N2) {
+        if constexpr (!SPLIT) {
+#pragma unroll
+            for (int b = 0; b < N1; ++b) v[b] = sh[ka * RS2 + b * COLS + col];
+        }
         dft<N1, +1>(v);  // v[kb] = x[ka + N2 kb]
 #pragma unroll
         for (int kb = 0; kb < N1; ++kb) line[(int64_t)(ka + N2 * kb) * jstride] = v[kb];
@@ -251,9 +327,15 @@ __global__ __launch_bounds__(COLS *Split<N>::TMAX) void col_fft(
 
 // ---- x pass: real-to-complex and complex-to-real rows ---------------------
 
+// Row geometry: M = M1 * M2 points per row, TR threads per row, M1 <= M2:
+// the first phase of each row transform runs M2 threads (in r2c_x the one
+// that loads the row from HBM), so that for M = 512 every thread of a row
+// issues loads; measured faster than the opposite split in both directions.
 template <int M>
 struct RowGeo {
-    static constexpr int M1 = Split<M>::N1, M2 = Split<M>::N2, TR = Split<M>::TMAX;
+    static constexpr int M1 = Split<M>::N2;
+    static constexpr int M2 = Split<M>::N1;
+    static constexpr int TR = Split<M>::TMAX;
     static constexpr int ROWS = 256 / TR > 0 ? 256 / TR : 1;
     static constexpr int RS = M2 + 1;                       // exchange row stride
     static constexpr int XLEN = (M + 1) > M1 * RS ? (M + 1) : M1 * RS;  // per-row LDS
