@@ -34,11 +34,14 @@ namespace cube2 {
 namespace {
 
 // Gathered box of IOS cells per axis: [c0-1, c0+8) for CIC, [c0-1, c0+9) for TSC.
-template <int P> struct DepGeo {
+// CR: the smallest coarse ratio the LDS coarse footprint is sized for (2, or
+// 4 for ratios 4 and 8, which keeps the block within 40 KB of LDS: four
+// workgroups per CU).
+template <int P, int CR = 4> struct DepGeo {
     static constexpr int BOX = kTileIos + (P == 3 ? 2 : 1);
     static constexpr int SEGS = BOX * BOX * BOX;              // 729 or 1000
     static constexpr int SEG_PER_THREAD = (SEGS + kBlock - 1) / kBlock;
-    static constexpr int CMAX = kTileFine / 2 + (P == 3 ? 3 : 1);  // coarse nodes per axis (ratio 2)
+    static constexpr int CMAX = kTileFine / CR + (P == 3 ? 3 : 1);  // coarse nodes per axis
 };
 
 // TSC weights of offset m (units 2^-15, m in [-2^14, 2^14)) in units of 2^-16.
@@ -203,35 +206,33 @@ __device__ __forceinline__ void deposit_coarse_wave(bool own, const int (&b)[3],
         }
 }
 
-template <bool FINE, bool COARSE, int P>
+template <bool FINE, bool COARSE, int P, int CR>
 __global__ __launch_bounds__(kBlock) void deposit_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs, int n, int n_f, int nt,
     float *__restrict__ rho_f, unsigned long long *__restrict__ rho_f_fx,
     unsigned long long *__restrict__ coarse_acc, int n_c, int hshift, uint32_t *status,
     const uint32_t *__restrict__ order, uint32_t *__restrict__ queue) {
-    constexpr int kBox = DepGeo<P>::BOX, kSegs = DepGeo<P>::SEGS;
-    constexpr int kSegPerThread = DepGeo<P>::SEG_PER_THREAD, kCoarseMax = DepGeo<P>::CMAX;
+    using Geo = DepGeo<P, CR>;
+    constexpr int kBox = Geo::BOX, kSegs = Geo::SEGS;
+    constexpr int kSegPerThread = Geo::SEG_PER_THREAD, kCoarseMax = Geo::CMAX;
     __shared__ uint32_t seg_pre[kSegs + 1];
     __shared__ uint32_t seg_src[kSegs];
     __shared__ unsigned long long acc_f[FINE ? kTileFine * kTileFine * kTileFine : 1];
     __shared__ unsigned long long acc_c[COARSE ? kCoarseMax * kCoarseMax * kCoarseMax : 1];
     __shared__ uint32_t scan_sh[kBlock / 64 + 1];
-    __shared__ int tile_sh;
+    __shared__ int next_sh;
 
     const int tid = threadIdx.x;
     const int n_ios = nt * kTileIos;
     const int NC = (kTileFine >> hshift) + (P == 3 ? 3 : 1);  // coarse nodes per axis touched
-    int round = 0, tx, ty, tz;
-    while (claim_tile(order, queue, nt * nt * nt, nt, round, &tile_sh, tx, ty, tz)) {
-        const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
+    const int ntiles = nt * nt * nt;
 
-        if (FINE)
-            for (int i = tid; i < kTileFine * kTileFine * kTileFine; i += kBlock) acc_f[i] = 0ull;
-        if (COARSE)
-            for (int i = tid; i < NC * NC * NC; i += kBlock) acc_c[i] = 0ull;
-
-        // particle ranges of the box of IOS cells [c0-1, c0+kBox-1)
-        uint32_t cnt[kSegPerThread], src[kSegPerThread], sum = 0;
+    // Particle ranges (start, count) of this thread's segments of the box of
+    // IOS cells [c0-1, c0+kBox-1) around tile t.
+    uint32_t cnt[kSegPerThread], src[kSegPerThread];
+    auto load_segments = [&](int t) {
+        const int c0x = (t % nt) * kTileIos, c0y = ((t / nt) % nt) * kTileIos,
+                  c0z = (t / (nt * nt)) * kTileIos;
 #pragma unroll
         for (int k = 0; k < kSegPerThread; ++k) {
             const int s = tid * kSegPerThread + k;
@@ -244,9 +245,37 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
                     const uint32_t key = cell_key(wrapn(c0x + bx - 1, n_ios), wrapn(c0y + by - 1, n_ios),
                                                   wrapn(c0z + bz - 1, n_ios), nt);
                     src[k] = cs[key];
-                    cnt[k] = cs[key + 1] - src[k];
+                    cnt[k] = cs[key + 1];  // end; the count is formed where it is used
                 }
             }
+        }
+    };
+
+    // Persistent workgroups over the heaviest-first tile order.  The loop is
+    // software-pipelined: the claim of the next tile is in flight while the
+    // current one deposits, and the next tile's segment ranges are loaded
+    // while the current one writes its nodes.
+    if (tid == 0) {
+        const int slot = claim_slot(queue, ntiles);
+        next_sh = slot < ntiles ? (int)order[slot] : -1;
+    }
+    __syncthreads();
+    int t = next_sh;
+    if (t >= 0) load_segments(t);
+    while (t >= 0) {
+        const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
+        int slot = ntiles;
+        if (tid == 0) slot = claim_slot(queue, ntiles);
+
+        if (FINE)
+            for (int i = tid; i < kTileFine * kTileFine * kTileFine; i += kBlock) acc_f[i] = 0ull;
+        if (COARSE)
+            for (int i = tid; i < NC * NC * NC; i += kBlock) acc_c[i] = 0ull;
+
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kSegPerThread; ++k) {
+            cnt[k] -= src[k];
             sum += cnt[k];
         }
         uint32_t total;
@@ -260,18 +289,21 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
             }
             pre += cnt[k];
         }
+        if (tid == 0) seg_pre[kSegs] = total;
+        __syncthreads();
         if (tid == 0) {
-            seg_pre[kSegs] = total;
             // Overflow guard: a fine node sums at most `total` weights of 2^45
             // (CIC) or 2^47 (TSC) each; a coarse node sums the own particles
-            // of at most 8 tiles.
-            const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
-            const uint32_t own = cs[key0 + kTileCells] - cs[key0];
+            // of at most 8 tiles.  The own cells' particles are one contiguous
+            // range, from the first own segment to the end of the last.
+            const int s_first = (1 * kBox + 1) * kBox + 1;
+            const int s_last = (kTileIos * kBox + kTileIos) * kBox + kTileIos;
+            const uint32_t own =
+                seg_src[s_last] + (seg_pre[s_last + 1] - seg_pre[s_last]) - seg_src[s_first];
             const uint32_t fine_max = P == 3 ? (1u << 17) : (1u << 19);
             const uint32_t own_max = P == 3 ? (1u << 14) : (1u << 16);
             if ((FINE && total >= fine_max) || (COARSE && own >= own_max)) atomicOr(status, 1u);
         }
-        __syncthreads();
 
         // The loop runs wave-uniformly (every lane of a wave takes the same
         // trips) so that the coarse weights can be summed over the wave; each
@@ -311,7 +343,11 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
                 }
             }
         }
+        // the next tile (the claim made at the top of this one has returned)
+        if (tid == 0) next_sh = slot < ntiles ? (int)order[slot] : -1;
         __syncthreads();
+        const int t_next = next_sh;
+        if (t_next >= 0) load_segments(t_next);
 
         if (FINE) {
             const int a0x = tx * kTileFine, a0y = ty * kTileFine, a0z = tz * kTileFine;
@@ -337,6 +373,8 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
                 atomicAdd(&coarse_acc[g], v);
             }
         }
+        t = t_next;
+        __syncthreads();  // this tile is done with the LDS arrays
     }  // tiles
 }
 
@@ -350,23 +388,41 @@ __global__ void coarse_finalize(const unsigned long long *__restrict__ accum, in
     if (fx) fx[i] = v;
 }
 
+template <bool FINE, bool COARSE, int P, int CR>
+void launch_one_deposit(const uint16_t *pos, const uint32_t *cs, int64_t n, int n_f, int nt,
+                        float *rho_f, unsigned long long *ffx, unsigned long long *cacc, int n_c,
+                        int hshift, uint32_t *status, const uint32_t *order, uint32_t *queue,
+                        int ntiles, hipStream_t s) {
+    auto k = deposit_kernel<FINE, COARSE, P, CR>;
+    k<<<persistent_grid(k, kBlock, ntiles), kBlock, 0, s>>>(pos, cs, (int)n, n_f, nt, rho_f, ffx, cacc,
+                                                          n_c, hshift, status, order, queue);
+}
+
 template <int P>
 int launch_deposit_kernels(bool fine, bool coarse, const uint16_t *pos, const uint32_t *cs, int64_t n,
                            int n_f, int nt, float *rho_f, unsigned long long *ffx,
                            unsigned long long *cacc, int n_c, int hshift, uint32_t *status,
                            const uint32_t *order, uint32_t *queue, int ntiles, hipStream_t s) {
-    if (fine && coarse)
-        deposit_kernel<true, true, P><<<persistent_grid(deposit_kernel<true, true, P>, kBlock, ntiles),
-                                        kBlock, 0, s>>>(pos, cs, (int)n, n_f, nt, rho_f, ffx, cacc,
-                                                        n_c, hshift, status, order, queue);
-    else if (fine)
-        deposit_kernel<true, false, P><<<persistent_grid(deposit_kernel<true, false, P>, kBlock, ntiles),
-                                         kBlock, 0, s>>>(pos, cs, (int)n, n_f, nt, rho_f, ffx, cacc,
-                                                         n_c, hshift, status, order, queue);
-    else
-        deposit_kernel<false, true, P><<<persistent_grid(deposit_kernel<false, true, P>, kBlock, ntiles),
-                                         kBlock, 0, s>>>(pos, cs, (int)n, n_f, nt, nullptr, nullptr,
-                                                         cacc, n_c, hshift, status, order, queue);
+    if (coarse && (kTileFine >> hshift) + (P == 3 ? 3 : 1) > DepGeo<P, 2>::CMAX) return CUBE2_EINVAL;
+    const bool r2 = hshift < 2;  // coarse ratio 2: the wider footprint
+    if (fine && coarse) {
+        if (r2)
+            launch_one_deposit<true, true, P, 2>(pos, cs, n, n_f, nt, rho_f, ffx, cacc, n_c, hshift,
+                                                 status, order, queue, ntiles, s);
+        else
+            launch_one_deposit<true, true, P, 4>(pos, cs, n, n_f, nt, rho_f, ffx, cacc, n_c, hshift,
+                                                 status, order, queue, ntiles, s);
+    } else if (fine) {
+        launch_one_deposit<true, false, P, 4>(pos, cs, n, n_f, nt, rho_f, ffx, cacc, n_c, hshift,
+                                              status, order, queue, ntiles, s);
+    } else {
+        if (r2)
+            launch_one_deposit<false, true, P, 2>(pos, cs, n, n_f, nt, nullptr, nullptr, cacc, n_c,
+                                                  hshift, status, order, queue, ntiles, s);
+        else
+            launch_one_deposit<false, true, P, 4>(pos, cs, n, n_f, nt, nullptr, nullptr, cacc, n_c,
+                                                  hshift, status, order, queue, ntiles, s);
+    }
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }

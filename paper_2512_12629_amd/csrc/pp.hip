@@ -385,7 +385,14 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                         float fx = 0.f, fy = 0.f, fz = 0.f;
                         uint32_t v = v0;
                         if (ADJ) {
-                            for (; v < v1; ++v) {
+                            for (; v + 1 < v1; v += 2) {
+                                const float4 qa = xs[v], aa = as_[v], qb = xs[v + 1], ab = as_[v + 1];
+                                pair_adjoint(qa.x - xi, qa.y - yi, qa.z - zi, aa.x - aix, aa.y - aiy,
+                                             aa.z - aiz, negc, fx, fy, fz);
+                                pair_adjoint(qb.x - xi, qb.y - yi, qb.z - zi, ab.x - aix, ab.y - aiy,
+                                             ab.z - aiz, negc, fx, fy, fz);
+                            }
+                            if (v < v1) {
                                 const float4 qa = xs[v], aa = as_[v];
                                 pair_adjoint(qa.x - xi, qa.y - yi, qa.z - zi, aa.x - aix, aa.y - aiy,
                                              aa.z - aiz, negc, fx, fy, fz);
