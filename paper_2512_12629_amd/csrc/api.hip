@@ -27,6 +27,9 @@ size_t table_layout(cube2_ctx *c) {
         size_t h = (size_t)(L.n / 2 + 1);
         L.g_off = off;
         off = align_up(off + h * h * h * sizeof(float), 256);
+        // z-pass copy: [my][kx / 16][mz][kx % 16], kx padded to the pitch
+        L.gz_off = off;
+        off = align_up(off + h * (size_t)pitch_of(L.n) * h * sizeof(float), 256);
     }
     c->pp_aoff = off;
     off = align_up(off + (size_t)kARows * kARowFloats * sizeof(float), 256);

@@ -34,6 +34,7 @@ struct Level {
     double b_prev = 0;  // truncation (fine cells); <= 0 means infinity
     size_t tw_off = 0;  // byte offset of the twiddle table in `tables`
     size_t g_off = 0;   // byte offset of the octant Green's table
+    size_t gz_off = 0;  // the same values in the z pass's order (FP32, see fft.hip)
     size_t tw64_off = 0, g64_off = 0;  // FP64 copies (CUBE2_FP64_FORM only)
 };
 

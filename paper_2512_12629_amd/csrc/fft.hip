@@ -176,9 +176,11 @@ constexpr bool split_exchange() { return sizeof(T) == 4 && N >= 512; }
 // The 1024- and 512-point FP32 transforms move their LDS exchanges as real
 // and imaginary halves in two rounds: 66 KB of LDS instead of 128 KB, so two
 // workgroups share a CU and one's loads overlap the other's arithmetic.  The
-// z pass loads its G values at the start for the same reason.
+// z pass loads its G values at the start for the same reason, from a copy of
+// the table laid out so that each workgroup's values are one contiguous block.
 template <int N, int COLS, int SIGN, int MODE, typename T>
-__global__ __launch_bounds__(COLS *Split<N>::TMAX) void col_fft(
+__global__ __launch_bounds__(COLS *Split<N>::TMAX)
+__attribute__((amdgpu_waves_per_eu(split_exchange<N, T>() ? 4 : 1))) void col_fft(
     typename Cx<T>::c *__restrict__ data, int64_t jstride, int64_t line_stride,
     const typename Cx<T>::c *__restrict__ tw, const T *__restrict__ G, int n, int pitch, T scale) {
     using C = typename Cx<T>::c;
@@ -202,8 +204,12 @@ __global__ __launch_bounds__(COLS *Split<N>::TMAX) void col_fft(
     const int64_t base = (int64_t)blockIdx.y * line_stride + (int64_t)blockIdx.x * COLS + col;
     C *line = data + base;
 
-    // z pass: the G values of this thread's k1 (kz = k1 + N1 k2)
+    // z pass: the G values of this thread's k1 (kz = k1 + N1 k2).  FP32
+    // reads the z-ordered copy [my][kx / 16][mz][kx % 16] (one contiguous
+    // block per workgroup, zero in the pad columns), FP64 the octant table.
     constexpr int NG = MODE == 2 ? N2 : 1;
+    constexpr bool ZORDER = sizeof(T) == 4;
+    static_assert(!ZORDER || COLS == 16, "the z-ordered table is in groups of 16 columns");
     T g[NG];
     if (MODE == 2 && t < COLS * N1) {
         const int h = n / 2 + 1;
@@ -211,24 +217,40 @@ __global__ __launch_bounds__(COLS *Split<N>::TMAX) void col_fft(
         const int ky = blockIdx.y;
         const int my = ky <= n - ky ? ky : n - ky;
         const int q = t / COLS;
+        // (the z-ordered table has fewer than 2^31 entries for n <= 1024)
+        const uint32_t gb = ((uint32_t)my * gridDim.x + blockIdx.x) * (uint32_t)h * COLS + col;
 #pragma unroll
         for (int k2 = 0; k2 < NG; ++k2) {
             const int kz = q + N1 * k2;
             const int mz = kz <= n - kz ? kz : n - kz;
-            g[k2] = kx < h ? G[((int64_t)mz * h + my) * h + kx] : T(0);
+            if (ZORDER)
+                g[k2] = G[gb + (uint32_t)mz * COLS];
+            else
+                g[k2] = kx < h ? G[((int64_t)mz * h + my) * h + kx] : T(0);
         }
     }
 
     // forward (or the single) transform, phase 1: thread owns j2, all j1
     C v1[N1];
+    // split-exchange transforms read their twiddles from an LDS copy (8 KB,
+    // still two workgroups per CU): fewer registers held by global loads
+    __shared__ C twl[SPLIT ? N : 1];
     if (t < COLS * N2) {
         const int j2 = t / COLS;
 #pragma unroll
         for (int j1 = 0; j1 < N1; ++j1) v1[j1] = line[(int64_t)(j1 * N2 + j2) * jstride];
+    }
+    if (SPLIT) {
+        for (int i = t; i < N; i += COLS * Split<N>::TMAX) twl[i] = tw[i];
+        __syncthreads();
+    }
+    const C *twp = SPLIT ? twl : tw;
+    if (t < COLS * N2) {
+        const int j2 = t / COLS;
         dft<N1, SIGN>(v1);
 #pragma unroll
         for (int k1 = 0; k1 < N1; ++k1) {
-            const C w = tw[(j2 * k1) & (N - 1)];
+            const C w = twp[(j2 * k1) & (N - 1)];
             v1[k1] = (SIGN < 0) ? cmul(v1[k1], w) : cmulc(v1[k1], w);
         }
         if constexpr (SPLIT) {
@@ -285,7 +307,7 @@ __global__ __launch_bounds__(COLS *Split<N>::TMAX) void col_fft(
         // inverse phase 1: thread owns b = k1, holds X[a*N1 + b], a = k2
         dft<N2, +1>(v2);
 #pragma unroll
-        for (int ka = 0; ka < N2; ++ka) v2[ka] = cmulc(v2[ka], tw[(k1 * ka) & (N - 1)]);
+        for (int ka = 0; ka < N2; ++ka) v2[ka] = cmulc(v2[ka], twp[(k1 * ka) & (N - 1)]);
         if constexpr (SPLIT) {
 #pragma unroll
             for (int ka = 0; ka < N2; ++ka) shf[ka * RF2 + k1 * COLS + col] = v2[ka].x;
@@ -515,7 +537,7 @@ int run(cube2_ctx *ctx, int level, int op, const T *rin, T *rout, typename Cx<T>
     const Level &L = ctx->lv[level];
     const bool f64 = sizeof(T) == 8;
     const C *tw = reinterpret_cast<const C *>(ctx->tables + (f64 ? L.tw64_off : L.tw_off));
-    const T *G = reinterpret_cast<const T *>(ctx->tables + (f64 ? L.g64_off : L.g_off));
+    const T *G = reinterpret_cast<const T *>(ctx->tables + (f64 ? L.g64_off : L.gz_off));
     switch (L.n) {
         case 8: return run_level<8, T>(op, rin, rout, spec, tw, G, L.pitch, s);
         case 16: return run_level<16, T>(op, rin, rout, spec, tw, G, L.pitch, s);

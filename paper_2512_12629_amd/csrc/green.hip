@@ -83,6 +83,21 @@ __global__ void green_kernel(T *__restrict__ out, int n, double ba, double bprev
 }
 
 // W_n^m = exp(-2 pi i m / n), m = 0..n-1, from FP64.
+// The octant table g[mz][my][kx] re-laid out for the z pass of the FFT:
+// gz[my][kx / 16][mz][kx % 16], kx padded to the spectrum pitch with zeros,
+// so that each z-line workgroup (16 adjacent kx, one ky) reads one
+// contiguous block.
+__global__ void green_zorder_kernel(const float *__restrict__ g, float *__restrict__ gz, int h,
+                                    int ngrp) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)h * ngrp * h * 16) return;
+    const int c = (int)(idx & 15);
+    const int64_t r = idx >> 4;
+    const int mz = (int)(r % h), grp = (int)((r / h) % ngrp), my = (int)(r / ((int64_t)h * ngrp));
+    const int kx = grp * 16 + c;
+    gz[idx] = kx < h ? g[((int64_t)mz * h + my) * h + kx] : 0.0f;
+}
+
 __global__ void twiddle_kernel(float2 *__restrict__ tw, int n) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n) return;
@@ -114,6 +129,11 @@ int launch_green(cube2_ctx *ctx, hipStream_t s) {
         const double iso_L = (ctx->isolated && bp <= 0.0) ? 0.5 * L.n : 0.0;
         green_kernel<float><<<(unsigned)((pts + 255) / 256), 256, 0, s>>>(
             g, L.n, ba, bp, ctx->cfg.alias_nmax, ctx->tsc ? 3 : 2, iso_L);
+        CUBE2_LAUNCH_CHECK();
+        const int ngrp = L.pitch / 16;
+        const int64_t zpts = h * ngrp * h * 16;
+        green_zorder_kernel<<<(unsigned)((zpts + 255) / 256), 256, 0, s>>>(
+            g, reinterpret_cast<float *>(ctx->tables + L.gz_off), (int)h, ngrp);
         CUBE2_LAUNCH_CHECK();
         if (ctx->fp64) {
             twiddle64_kernel<<<(L.n + 255) / 256, 256, 0, s>>>(
