@@ -356,7 +356,9 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
                           lz = i / (kTileFine * kTileFine);
                 const int64_t g = ((int64_t)(a0z + lz) * n_f + (a0y + ly)) * n_f + (a0x + lx);
                 const unsigned long long v = acc_f[i];
-                rho_f[g] = (float)v * (P == 3 ? 0x1p-48f : 0x1p-45f);
+                // streaming store: a tile row is half a cache line, and the
+                // mesh is read back only by the next kernel
+                __builtin_nontemporal_store((float)v * (P == 3 ? 0x1p-48f : 0x1p-45f), &rho_f[g]);
                 if (rho_f_fx) rho_f_fx[g] = v;
             }
         }

@@ -176,8 +176,9 @@ constexpr bool split_exchange() { return sizeof(T) == 4 && N >= 512; }
 // The 1024- and 512-point FP32 transforms move their LDS exchanges as real
 // and imaginary halves in two rounds: 66 KB of LDS instead of 128 KB, so two
 // workgroups share a CU and one's loads overlap the other's arithmetic.  The
-// z pass loads its G values at the start for the same reason, from a copy of
-// the table laid out so that each workgroup's values are one contiguous block.
+// z pass issues its G loads before the second forward sub-transform, from a
+// copy of the table laid out so that each workgroup's values are one
+// contiguous block.
 template <int N, int COLS, int SIGN, int MODE, typename T>
 __global__ __launch_bounds__(COLS *Split<N>::TMAX)
 __attribute__((amdgpu_waves_per_eu(split_exchange<N, T>() ? 4 : 1))) void col_fft(
@@ -211,7 +212,8 @@ __attribute__((amdgpu_waves_per_eu(split_exchange<N, T>() ? 4 : 1))) void col_ff
     constexpr bool ZORDER = sizeof(T) == 4;
     static_assert(!ZORDER || COLS == 16, "the z-ordered table is in groups of 16 columns");
     T g[NG];
-    if (MODE == 2 && t < COLS * N1) {
+    auto load_g = [&]() {
+        if (MODE != 2 || t >= COLS * N1) return;
         const int h = n / 2 + 1;
         const int kx = blockIdx.x * COLS + col;
         const int ky = blockIdx.y;
@@ -228,7 +230,7 @@ __attribute__((amdgpu_waves_per_eu(split_exchange<N, T>() ? 4 : 1))) void col_ff
             else
                 g[k2] = kx < h ? G[((int64_t)mz * h + my) * h + kx] : T(0);
         }
-    }
+    };
 
     // forward (or the single) transform, phase 1: thread owns j2, all j1
     C v1[N1];
@@ -287,6 +289,7 @@ __attribute__((amdgpu_waves_per_eu(split_exchange<N, T>() ? 4 : 1))) void col_ff
 #pragma unroll
             for (int j2 = 0; j2 < N2; ++j2) v2[j2] = sh[k1 * RS1 + j2 * COLS + col];
         }
+        load_g();  // z pass: in flight during the second sub-transform
         dft<N2, SIGN>(v2);  // v2[k2] = X[k1 + N1 k2]
     }
     if (MODE == 0) {
