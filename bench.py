@@ -225,7 +225,8 @@ def pairwise_experiment(args):
     import paper_2512_12629_amd as m
     n_f, cr = 256, 4
     flags = m.CUBE2_ISOLATED | (m.CUBE2_ASSIGN_TSC if args.assign == "tsc" else 0)
-    cfg = m.Config(n_fine=n_f, coarse_ratio=cr, flags=flags)
+    cfg = m.Config(n_fine=n_f, coarse_ratio=cr, b_fine=args.pair_b_fine, b_pp=args.pair_b_pp,
+                   flags=flags)
     c = m.Cube2(cfg, n_max=2)
     L = n_f / 2                                   # isolation box, fine cells
     edges = np.exp(np.linspace(np.log(0.05), np.log(L / 2), 31))
@@ -237,7 +238,8 @@ def pairwise_experiment(args):
             r = float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
             u = rng.standard_normal(3)
             u /= np.linalg.norm(u)
-            a0 = 2.0 + rng.random(3) * (L - 4.0 - r * np.abs(u))
+            # both particles inside [2, L - 2] on every axis
+            a0 = 2.0 + np.maximum(-r * u, 0.0) + rng.random(3) * (L - 4.0 - r * np.abs(u))
             xf = np.stack([a0, a0 + r * u], axis=1)
             x32 = (xf / n_f).astype(np.float32)
             pos, cs, perm = c.pack(torch.from_numpy(x32).cuda())
@@ -284,6 +286,11 @@ def main():
                     help="run the pairwise force-accuracy experiment (isolated boundaries) "
                          "instead of the benchmark")
     ap.add_argument("--pairs-per-bin", type=int, default=16)
+    ap.add_argument("--pair-b-fine", type=float, default=2.0,
+                    help="fine softening (= PP cutoff) of the pairwise experiment; 3.5 is the "
+                         "paper's beta = 3.5")
+    ap.add_argument("--pair-b-pp", type=float, default=0.2,
+                    help="PP softening of the pairwise experiment (the paper's Fig. 1: ~0.06)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timing, run a plain copy kernel (y = -x) of this many MiB "
                          "read + the same written, as the reference for HBM counter passes")

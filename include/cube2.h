@@ -94,8 +94,11 @@ typedef struct cube2_config {
     int32_t coarse_ratio;  /* 0 = one PM level; else the coarse spacing in fine
                               cells: 2, 4 or 8, with n_fine/coarse_ratio >= 8 */
     double  b_coarse;      /* coarse softening b_1 (ignored with one level) */
-    double  b_fine;        /* fine softening, also the PP cutoff; (0, 2] so
-                              that PP pairs lie in adjacent IOS cells */
+    double  b_fine;        /* fine softening, also the PP cutoff; (0, 4]:
+                              up to 2 PP pairs lie in adjacent IOS cells (27
+                              neighbour cells), above 2 within two cells (125
+                              neighbour cells, ~5x the PP work at equal
+                              density) */
     double  b_pp;          /* PP softening b_PP, 0 < b_pp < b_fine */
     double  m_p;           /* particle mass */
     double  g_newton;      /* coupling constant G */
@@ -108,7 +111,7 @@ typedef struct cube2_ctx cube2_ctx;
 
 /* Validate `cfg` and create a host-side context (no device work).
  * Returns CUBE2_EUNSUPPORTED for sizes or ratios outside the set above, or
- * when no grid of K <= 64 equal intervals of [0, b_fine) has b_pp/2, b_pp
+ * when no grid of K <= 128 equal intervals of [0, b_fine) has b_pp/2, b_pp
  * and b_fine/2 on its edges (the exact pair-law pieces of eq. 2 need that),
  * and CUBE2_EINVAL for non-positive softenings or b_pp >= b_fine. */
 int cube2_create(const cube2_config *cfg, cube2_ctx **out);
@@ -141,8 +144,9 @@ int cube2_green_table(const cube2_ctx *ctx, int level, float *out, cube2_stream_
  * forward PP kernel evaluates it -- the same table, indexed by s = |D|^2,
  * and the same FP32 operations -- on the host, for inspecting its accuracy.
  * d (host, 3*n floats: d[k*n+i] is component k of separation i, fine
- * cells, each |component| < 4) in, g (host, n floats) out.  No device
- * work; CUBE2_EINVAL for a NULL pointer, n < 0 or a component of 4 or more. */
+ * cells, each |component| < 4, or < 6 when b_fine > 2) in, g (host, n
+ * floats) out.  No device work; CUBE2_EINVAL for a NULL pointer, n < 0 or a
+ * component beyond that bound. */
 int cube2_pair_law_f32(const cube2_ctx *ctx, const float *d, float *g, int64_t n);
 
 /* The FP32 pair law and its derivative g_s = dg/ds (s = |D|^2) exactly as

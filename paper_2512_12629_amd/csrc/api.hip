@@ -114,7 +114,7 @@ int cube2_create(const cube2_config *cfg, cube2_ctx **out) {
         if (c.n_fine / c.coarse_ratio < 8) return CUBE2_EUNSUPPORTED;
         if (!(c.b_coarse > c.b_fine)) return CUBE2_EINVAL;
     }
-    if (!(c.b_fine > 0.0) || c.b_fine > 2.0) return CUBE2_EUNSUPPORTED;
+    if (!(c.b_fine > 0.0) || c.b_fine > 4.0) return CUBE2_EUNSUPPORTED;
     if (!(c.b_pp > 0.0) || !(c.b_pp < c.b_fine)) return CUBE2_EINVAL;
     if (!(c.m_p > 0.0) || !std::isfinite(c.g_newton)) return CUBE2_EINVAL;
     if (c.alias_nmax < 0 || c.alias_nmax > 4) return CUBE2_EUNSUPPORTED;
@@ -123,6 +123,7 @@ int cube2_create(const cube2_config *cfg, cube2_ctx **out) {
     if (!ctx) return CUBE2_EINVAL;
     ctx->cfg = c;
     ctx->n_f = c.n_fine;
+    ctx->pp_halo = c.b_fine > 2.0 ? 2 : 1;  // PP cutoff within 1 or 2 IOS cells (2 fine cells each)
     ctx->n_ios = c.n_fine / 2;
     ctx->nt = ctx->n_ios / kTileIos;
     ctx->n_cells = (int64_t)ctx->n_ios * ctx->n_ios * ctx->n_ios;

@@ -42,20 +42,20 @@ struct Level {
 
 namespace cube2 {
 // Pair-law table of the PP kernels (built on the host, see pp.hip).
-constexpr int kPairKMax = 64;      // grid intervals of [0, b_f)
+constexpr int kPairKMax = 128;     // grid intervals of [0, b_f)
 constexpr int kPairRow = 12;       // floats per interval: 9 coefficients, y map, pad
 // FP32 forward pair law, indexed by s = r^2: one row of 4 cubic coefficients
-// per 1/16 of an octave, for s in [2^-31, 2^6).  The row of s is its float
+// per 1/16 of an octave, for s in [2^-31, 2^7).  The row of s is its float
 // bit pattern shifted right by 19 (exponent and top 4 mantissa bits) minus
 // kSRow0.
 constexpr int kSMantBits = 4;
 constexpr int kSRow0 = (127 - 31) << kSMantBits;
-constexpr int kSRows = (6 + 31) << kSMantBits;  // 592
+constexpr int kSRows = (7 + 31) << kSMantBits;  // 608
 // FP32 adjoint pair law (g and dg/ds), indexed the same way with 1/8 octave
 // pieces: one row of 6 quintic coefficients, padded to 8 floats.
 constexpr int kAMantBits = 3;
 constexpr int kARow0 = (127 - 31) << kAMantBits;
-constexpr int kARows = (6 + 31) << kAMantBits;  // 296
+constexpr int kARows = (7 + 31) << kAMantBits;  // 304
 constexpr int kARowFloats = 8;
 }  // namespace cube2
 
@@ -64,6 +64,7 @@ struct cube2_ctx {
     int pp_K = 0;                      // intervals of the pair-law grid
     float pp_kinv = 0.f;               // K / b_f
     float pp_negc = 0.f;               // -1/b_f^2, rounded away from zero (FP32 pair law)
+    int pp_halo = 1;                   // PP neighbour reach in IOS cells: 1 (b_f <= 2), 2 (b_f <= 4)
     std::vector<float> pp_arows;       // kARows * kARowFloats: the FP32 adjoint pair law by s
     size_t pp_aoff = 0;                // byte offset of pp_arows in `tables`
     std::vector<float> pp_srows;       // kSRows * 4 floats: the FP32 forward pair law by s = r^2

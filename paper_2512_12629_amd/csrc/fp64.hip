@@ -2,7 +2,8 @@
 //   * the density in FP64: the deposit's exact uint64 accumulator times its
 //     unit (2^-45 for CIC, 2^-48 for TSC);
 //   * the PP force (eq. 4d) in FP64, one thread per particle looping over its
-//     27 neighbour IOS cells in HBM, with the pair law of eq. (2) evaluated
+//     neighbour IOS cells (27, or 125 for b_f > 2) in HBM, with the pair
+//     law of eq. (2) evaluated
 //     from the FP64 rows of the same exact piecewise-polynomial table that
 //     the FP32 kernel uses (re-expanded on the host in FP64).
 // It favours plainness over speed: it is the yardstick the FP32 path is
@@ -22,7 +23,7 @@ __global__ void fx_to_f64_kernel(uint64_t *buf, int64_t m, double unit) {
 __global__ __launch_bounds__(kBlock) void pp64_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs, int n, int nt,
     const double *__restrict__ rows, int K, double kinv, double gm, double *__restrict__ acc,
-    int accumulate) {
+    int accumulate, int reach) {
     __shared__ uint32_t cst[kTileCells + 1];
     int tx, ty, tz;
     tile_of_block(blockIdx.x, nt, tx, ty, tz);
@@ -39,9 +40,9 @@ __global__ __launch_bounds__(kBlock) void pp64_kernel(
 #pragma unroll
         for (int d = 0; d < 3; ++d) oi[d] = pos[(int64_t)d * n + p];
         double a[3] = {0.0, 0.0, 0.0};
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
+        for (int dz = -reach; dz <= reach; ++dz)
+            for (int dy = -reach; dy <= reach; ++dy)
+                for (int dx = -reach; dx <= reach; ++dx) {
                     const uint32_t key = cell_key(wrapn(c[0] + dx, n_ios), wrapn(c[1] + dy, n_ios),
                                                   wrapn(c[2] + dz, n_ios), nt);
                     const uint32_t j0 = cs[key], j1 = cs[key + 1];
@@ -89,7 +90,7 @@ int launch_pp64(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t
     const int nt = ctx->nt;
     pp64_kernel<<<(unsigned)(nt * nt * nt), kBlock, 0, s>>>(
         pos, cs, (int)n, nt, rows, ctx->pp_K, (double)ctx->pp_K / ctx->cfg.b_fine,
-        ctx->cfg.g_newton * ctx->cfg.m_p, acc, accumulate);
+        ctx->cfg.g_newton * ctx->cfg.m_p, acc, accumulate, ctx->pp_halo);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }

@@ -1,20 +1,22 @@
 // pp.hip -- the short-range particle-particle force (eq. 4d): for every pair
 // closer than the fine softening b_f (the cutoff of the finest PM level),
 //   a_i += G m [R(r, b_pp) - R(r, b_f)] (x_j - x_i) / r,
-// with R of eq. (2).  Because b_f <= 2 fine cells = one IOS cell, every pair
-// lies in the same or in adjacent IOS cells, so the cell-sorted particle
-// order is the linked list of the paper (section 2.3).
+// with R of eq. (2).  An IOS cell is 2 fine cells, so for b_f <= 2 every
+// pair lies in the same or in adjacent IOS cells (27 neighbour cells), and
+// for 2 < b_f <= 4 within two cells (125); the cell-sorted particle order is
+// the linked list of the paper (section 2.3).
 //
-// One workgroup per tile.  The particles of the tile and of its one-cell halo
-// (a 10^3 box of IOS cells) are staged in LDS as FP32 positions relative to
-// the tile origin in fine cells.  Offsets are multiples of 2^-15 below 2^5,
-// so these floats and their differences are exact: the pair separation is
-// the exact integer one.  Each thread takes one particle of the tile and
-// loops over its 27 neighbour cells, which in the staged box are 9
-// contiguous ranges (x-rows of three cells); neighbours in a dense cell are
-// read by all lanes of a wave at the same LDS address (a broadcast).  Per
-// range the pair sum is accumulated in FP32 and then added to the total with
-// Kahan compensation.  Boxes too large for LDS read the same data from HBM.
+// One workgroup per tile.  The particles of the tile and of its halo of H
+// cells (a (8 + 2H)^3 box of IOS cells) are staged in LDS as FP32 positions
+// relative to the tile origin in fine cells.  Offsets are multiples of 2^-15
+// below 2^5, so these floats and their differences are exact: the pair
+// separation is the exact integer one.  Each thread takes one particle of the
+// tile and loops over its neighbour cells, which in the staged box are
+// (2H + 1)^2 contiguous ranges (x-rows of 2H + 1 cells); neighbours in a
+// dense cell are read by all lanes of a wave at the same LDS address (a
+// broadcast).  Per range the pair sum is accumulated in FP32 and then added
+// to the total with Kahan compensation.  Boxes too large for LDS read the
+// same data from HBM.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -24,15 +26,22 @@
 namespace cube2 {
 namespace {
 
-constexpr int kPB = kTileIos + 2;          // 10 IOS cells per axis
-constexpr int kPSegs = kPB * kPB * kPB;    // 1000
-// Forward: 512 threads, 3840 staged particles (60 KB): 2 blocks (4 waves per
-// SIMD) per CU.  Adjoint: the cotangent is staged too, so it runs 1024-thread
-// blocks with 4096 staged particles (128 KB): 1 block (4 waves per SIMD).
-template <bool ADJ> struct PPGeo {
+// H: the neighbour reach in IOS cells, 1 for b_f <= 2 fine cells (27
+// neighbour cells) and 2 for b_f <= 4 (125).  The staged box has
+// 8 + 2H IOS cells per axis.
+template <int H> struct PPBox {
+    static constexpr int PB = kTileIos + 2 * H;   // 10 or 12 IOS cells per axis
+    static constexpr int SEGS = PB * PB * PB;      // 1000 or 1728
+    static constexpr int W = 2 * H + 1;            // neighbour cells per axis
+};
+// Forward: 512 threads, 3840 staged particles (60 KB; 3456 with the wider
+// box): 2 blocks (4 waves per SIMD) per CU.  Adjoint: the cotangent is staged
+// too, so it runs 1024-thread blocks with 4096 staged particles (128 KB):
+// 1 block (4 waves per SIMD).
+template <bool ADJ, int H> struct PPGeo {
     static constexpr int BLOCK = ADJ ? 1024 : 512;
-    static constexpr int CAP = ADJ ? 4096 : 3840;
-    static constexpr int SEG_PER_THREAD = (kPSegs + BLOCK - 1) / BLOCK;
+    static constexpr int CAP = ADJ ? 4096 : (H == 1 ? 3840 : 3456);
+    static constexpr int SEG_PER_THREAD = (PPBox<H>::SEGS + BLOCK - 1) / BLOCK;
 };
 
 }  // namespace
@@ -70,8 +79,8 @@ template <bool ADJ> struct PPGeo {
 // its own part near the cutoff, as rounding of r does in any evaluation.  The
 // row index is the bit pattern of s shifted right, the local variable the
 // remaining 19 mantissa bits read as a float in [0, 1/16).  Every pair
-// separation in the staged box is below 4 fine cells per axis, so s < 48 and
-// the row exists; the 2^-31 added to s (below the smallest nonzero
+// separation in the staged box is below 2(H + 1) fine cells per axis (4 or
+// 6), so s < 108 < 2^7 and the row exists; the 2^-31 added to s (below the smallest nonzero
 // separation squared, 2^-30) keeps a coincident pair on row 0, where g is
 // finite and g D = 0.
 
@@ -149,14 +158,14 @@ __device__ __forceinline__ void pair_adjoint(float dx, float dy, float dz, float
 
 // Heavy tiles are done in z-chunks: own cells are ordered z-major, so the own
 // cells of z-layers [z0, z1) are a contiguous particle range and the box cells
-// they need are the contiguous box layers [z0, z1 + 2), a contiguous slice of
+// they need are the contiguous box layers [z0, z1 + 2H), a contiguous slice of
 // the staged list.
 
 // ADJ = false: acc = G m sum_j g D (forward).  ADJ = true: out = G m sum_j
 // J(D) (abar_j - abar_i) for the cotangent abar (the adjoint), which stages
 // abar_j beside x_j and so holds half as many particles per chunk.
-template <bool ADJ>
-__global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *__restrict__ pos,
+template <bool ADJ, int H>
+__global__ __launch_bounds__((PPGeo<ADJ, H>::BLOCK)) void pp_kernel(const uint16_t *__restrict__ pos,
                                                      const uint32_t *__restrict__ cs, int n,
                                                      int nt, const float4 *__restrict__ table,
                                                      float negc, float gm,
@@ -164,9 +173,10 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                                                      float *__restrict__ acc, int accumulate,
                                                      const uint32_t *__restrict__ order,
                                                      uint32_t *__restrict__ queue, int ntiles) {
-    constexpr int CAP = PPGeo<ADJ>::CAP;
-    constexpr int kPPBlock = PPGeo<ADJ>::BLOCK;
-    constexpr int kPSegPerThread = PPGeo<ADJ>::SEG_PER_THREAD;
+    constexpr int CAP = PPGeo<ADJ, H>::CAP;
+    constexpr int kPPBlock = PPGeo<ADJ, H>::BLOCK;
+    constexpr int kPSegPerThread = PPGeo<ADJ, H>::SEG_PER_THREAD;
+    constexpr int kPB = PPBox<H>::PB, kPSegs = PPBox<H>::SEGS, kW = PPBox<H>::W;
     __shared__ uint32_t seg_pre[kPSegs + 1];
     __shared__ uint32_t seg_src[kPSegs];
     __shared__ float4 xs[CAP];
@@ -214,8 +224,8 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
             src[k] = 0;
             if (s < kPSegs) {
                 const int bx = s % kPB, by = (s / kPB) % kPB, bz = s / (kPB * kPB);
-                const uint32_t key = cell_key(wrapn(c0x + bx - 1, n_ios), wrapn(c0y + by - 1, n_ios),
-                                              wrapn(c0z + bz - 1, n_ios), nt);
+                const uint32_t key = cell_key(wrapn(c0x + bx - H, n_ios), wrapn(c0y + by - H, n_ios),
+                                              wrapn(c0z + bz - H, n_ios), nt);
                 src[k] = cs[key];
                 cnt[k] = cs[key + 1] - src[k];
             }
@@ -240,13 +250,13 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
         // own cells (box segments with coordinates 1..8): their particle
         // starts relative to the tile's first particle, from the box ranges
         // (the own cells' particles are one contiguous range)
-        const uint32_t p0 = seg_src[(1 * kPB + 1) * kPB + 1];
+        const uint32_t p0 = seg_src[(H * kPB + H) * kPB + H];
         for (int i = tid; i <= kTileCells; i += kPPBlock) {
             if (i < kTileCells) {
-                const int s = (((i >> 6) + 1) * kPB + ((i >> 3) & 7) + 1) * kPB + (i & 7) + 1;
+                const int s = (((i >> 6) + H) * kPB + ((i >> 3) & 7) + H) * kPB + (i & 7) + H;
                 cst[i] = seg_src[s] - p0;
             } else {
-                const int s = (8 * kPB + 8) * kPB + 8;  // last own cell
+                const int s = ((7 + H) * kPB + 7 + H) * kPB + 7 + H;  // last own cell
                 cst[i] = seg_src[s] + (seg_pre[s + 1] - seg_pre[s]) - p0;
             }
         }
@@ -257,7 +267,7 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                 bool fits = true;
                 for (int c = 0; c < C; ++c) {
                     const int z0 = c * 8 / C, z1 = (c + 1) * 8 / C;
-                    if (seg_pre[(z1 + 2) * kPB * kPB] - seg_pre[z0 * kPB * kPB] > (uint32_t)CAP)
+                    if (seg_pre[(z1 + 2 * H) * kPB * kPB] - seg_pre[z0 * kPB * kPB] > (uint32_t)CAP)
                         fits = false;
                 }
                 if (fits) break;
@@ -270,7 +280,7 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
 
         for (int c = 0; c < C; ++c) {
             const int z0 = c * 8 / C, z1 = (c + 1) * 8 / C;
-            const uint32_t vb = seg_pre[z0 * kPB * kPB], ve = seg_pre[(z1 + 2) * kPB * kPB];
+            const uint32_t vb = seg_pre[z0 * kPB * kPB], ve = seg_pre[(z1 + 2 * H) * kPB * kPB];
             const bool staged = ve - vb <= (uint32_t)CAP;
             if (c > 0) __syncthreads();  // previous chunk done with xs
             if (!ADJ && staged && C == 1 && maxcnt <= 4) {
@@ -294,9 +304,9 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                     for (int i = 0; i < 4; ++i) {
                         if ((uint32_t)i >= cnt[k]) continue;
                         float4 q;
-                        q.x = (float)(2 * (bx - 1)) + (float)o[i][0] * inv;
-                        q.y = (float)(2 * (by - 1)) + (float)o[i][1] * inv;
-                        q.z = (float)(2 * (bz - 1)) + (float)o[i][2] * inv;
+                        q.x = (float)(2 * (bx - H)) + (float)o[i][0] * inv;
+                        q.y = (float)(2 * (by - H)) + (float)o[i][1] * inv;
+                        q.z = (float)(2 * (bz - H)) + (float)o[i][2] * inv;
                         q.w = 0.0f;
                         xs[pre_k[k] + i] = q;
                         if (ADJ) {
@@ -338,9 +348,9 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                         const int s = sg[k];
                         const int bx = s % kPB, by = (s / kPB) % kPB, bz = s / (kPB * kPB);
                         float4 q;
-                        q.x = (float)(2 * (bx - 1)) + (float)o[k][0] * inv;
-                        q.y = (float)(2 * (by - 1)) + (float)o[k][1] * inv;
-                        q.z = (float)(2 * (bz - 1)) + (float)o[k][2] * inv;
+                        q.x = (float)(2 * (bx - H)) + (float)o[k][0] * inv;
+                        q.y = (float)(2 * (by - H)) + (float)o[k][1] * inv;
+                        q.z = (float)(2 * (bz - H)) + (float)o[k][2] * inv;
                         q.w = 0.0f;
                         const uint32_t v = v0 + k * kPPBlock;
                         xs[v - vb] = q;
@@ -354,7 +364,7 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
             for (uint32_t lp = q0 + tid; lp < q1; lp += kPPBlock) {
                 const int u = seg_search(cst, kTileCells, lp);
                 const uint32_t p = p0 + lp;
-                const int bx = (u & 7) + 1, by = ((u >> 3) & 7) + 1, bz = (u >> 6) + 1;
+                const int bx = (u & 7) + H, by = ((u >> 3) & 7) + H, bz = (u >> 6) + H;
                 float xi, yi, zi;
                 if (staged) {
                     // the particle itself is staged: same exact floats, no HBM read
@@ -364,9 +374,9 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                     yi = qi.y;
                     zi = qi.z;
                 } else {
-                    xi = (float)(2 * (bx - 1)) + (float)pos[p] * inv;
-                    yi = (float)(2 * (by - 1)) + (float)pos[(int64_t)n + p] * inv;
-                    zi = (float)(2 * (bz - 1)) + (float)pos[2 * (int64_t)n + p] * inv;
+                    xi = (float)(2 * (bx - H)) + (float)pos[p] * inv;
+                    yi = (float)(2 * (by - H)) + (float)pos[(int64_t)n + p] * inv;
+                    zi = (float)(2 * (bz - H)) + (float)pos[2 * (int64_t)n + p] * inv;
                 }
                 float aix = 0.f, aiy = 0.f, aiz = 0.f;
                 if (ADJ) {
@@ -378,10 +388,10 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                 if (staged) {
                     // the three x-neighbours of a cell are consecutive box segments,
                     // so the 27 neighbour cells are 9 contiguous ranges of xs
-                    for (int row = 0; row < 9; ++row) {
-                        const int oy = row % 3 - 1, oz = row / 3 - 1;
+                    for (int row = 0; row < kW * kW; ++row) {
+                        const int oy = row % kW - H, oz = row / kW - H;
                         const int sm = ((bz + oz) * kPB + (by + oy)) * kPB + bx;
-                        const uint32_t v0 = seg_pre[sm - 1] - vb, v1 = seg_pre[sm + 2] - vb;
+                        const uint32_t v0 = seg_pre[sm - H] - vb, v1 = seg_pre[sm + H + 1] - vb;
                         float fx = 0.f, fy = 0.f, fz = 0.f;
                         uint32_t v = v0;
                         if (ADJ) {
@@ -413,12 +423,12 @@ __global__ __launch_bounds__(PPGeo<ADJ>::BLOCK) void pp_kernel(const uint16_t *_
                         kahan_add(sz, cz, fz);
                     }
                 } else {
-                    for (int nb = 0; nb < 27; ++nb) {
-                        const int ox = nb % 3 - 1, oy = (nb / 3) % 3 - 1, oz = nb / 9 - 1;
+                    for (int nb = 0; nb < kW * kW * kW; ++nb) {
+                        const int ox = nb % kW - H, oy = (nb / kW) % kW - H, oz = nb / (kW * kW) - H;
                         const int s = ((bz + oz) * kPB + (by + oy)) * kPB + (bx + ox);
                         const uint32_t v0 = seg_pre[s], v1 = seg_pre[s + 1];
-                        const float bxo = (float)(2 * (bx + ox - 1)), byo = (float)(2 * (by + oy - 1)),
-                                    bzo = (float)(2 * (bz + oz - 1));
+                        const float bxo = (float)(2 * (bx + ox - H)), byo = (float)(2 * (by + oy - H)),
+                                    bzo = (float)(2 * (bz + oz - H));
                         float fx = 0.f, fy = 0.f, fz = 0.f;
                         for (uint32_t v = v0; v < v1; ++v) {
                             const uint32_t pj = seg_src[s] + (v - v0);
@@ -614,8 +624,8 @@ int build_pair_table(cube2_ctx *ctx) {
 
 namespace {
 
-template <bool ADJ>
-int launch_pp_kernel(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+template <bool ADJ, int H>
+int launch_pp_kernel_h(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                      const float *abar, float *out, int accumulate, unsigned char *work,
                      const WorkLayout &L, hipStream_t s) {
     const float4 *table =
@@ -626,11 +636,21 @@ int launch_pp_kernel(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, in
     if (r) return r;
     const uint32_t *order = tile_order_ptr(work, L);
     uint32_t *queue = tile_queue_ptr(ctx, work, L);
-    pp_kernel<ADJ><<<persistent_grid(pp_kernel<ADJ>, PPGeo<ADJ>::BLOCK, ntiles), PPGeo<ADJ>::BLOCK, 0, s>>>(
+    auto k = pp_kernel<ADJ, H>;
+    k<<<persistent_grid(k, PPGeo<ADJ, H>::BLOCK, ntiles), PPGeo<ADJ, H>::BLOCK, 0, s>>>(
         pos, cs, (int)n, nt, table, ctx->pp_negc,
         (float)(ctx->cfg.g_newton * ctx->cfg.m_p), abar, out, accumulate, order, queue, ntiles);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
+}
+
+template <bool ADJ>
+int launch_pp_kernel(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                     const float *abar, float *out, int accumulate, unsigned char *work,
+                     const WorkLayout &L, hipStream_t s) {
+    if (ctx->pp_halo == 1)
+        return launch_pp_kernel_h<ADJ, 1>(ctx, pos, cs, n, abar, out, accumulate, work, L, s);
+    return launch_pp_kernel_h<ADJ, 2>(ctx, pos, cs, n, abar, out, accumulate, work, L, s);
 }
 
 }  // namespace
@@ -653,7 +673,9 @@ extern "C" int cube2_pair_law_f32(const cube2_ctx *ctx, const float *d, float *g
     if (!ctx || n < 0 || (n > 0 && (!d || !g))) return CUBE2_EINVAL;
     for (int64_t i = 0; i < n; ++i) {
         const float dx = d[i], dy = d[n + i], dz = d[2 * n + i];
-        if (!(std::fabs(dx) < 4.0f && std::fabs(dy) < 4.0f && std::fabs(dz) < 4.0f))
+        // the staged box's reach: below 2 (halo + 1) fine cells per axis
+        const float lim = 2.0f * (float)(ctx->pp_halo + 1);
+        if (!(std::fabs(dx) < lim && std::fabs(dy) < lim && std::fabs(dz) < lim))
             return CUBE2_EINVAL;
         // the operations of pair_accumulate, in the same order
         const float s = std::fmaf(dz, dz, std::fmaf(dy, dy, std::fmaf(dx, dx, 0x1p-31f)));
@@ -678,7 +700,9 @@ extern "C" int cube2_pair_jacobian_f32(const cube2_ctx *ctx, const float *d, flo
     if (!ctx || n < 0 || (n > 0 && (!d || !g || !gs))) return CUBE2_EINVAL;
     for (int64_t i = 0; i < n; ++i) {
         const float dx = d[i], dy = d[n + i], dz = d[2 * n + i];
-        if (!(std::fabs(dx) < 4.0f && std::fabs(dy) < 4.0f && std::fabs(dz) < 4.0f))
+        // the staged box's reach: below 2 (halo + 1) fine cells per axis
+        const float lim = 2.0f * (float)(ctx->pp_halo + 1);
+        if (!(std::fabs(dx) < lim && std::fabs(dy) < lim && std::fabs(dz) < lim))
             return CUBE2_EINVAL;
         // the operations of pair_adjoint, in the same order
         const float s = std::fmaf(dz, dz, std::fmaf(dy, dy, std::fmaf(dx, dx, 0x1p-31f)));

@@ -58,10 +58,12 @@ def test_create_validates_configuration(L):
     assert _create(L, _cfg(coarse_ratio=3))[0] == -2
     assert _create(L, _cfg(n_fine=32, coarse_ratio=8))[0] == -2   # coarse mesh < 8
     assert _create(L, _cfg(b_pp=2.0))[0] == -1          # b_pp >= b_fine
-    assert _create(L, _cfg(b_fine=3.0))[0] == -2        # PP beyond one IOS cell
+    assert _create(L, _cfg(b_fine=4.5))[0] == -2        # PP beyond two IOS cells
+    assert _create(L, _cfg(b_fine=3.5, b_pp=0.0625))[0] == 0   # two-cell PP reach, K = 112
+    assert _create(L, _cfg(b_fine=3.5, b_pp=0.06))[0] == -2    # no K <= 128 aligns 0.03
     assert _create(L, _cfg(coarse_ratio=4, b_coarse=1.0))[0] == -1
     assert _create(L, _cfg(alias_nmax=9))[0] == -2
-    # b_pp/2 = 0.03 is on no grid of K <= 64 equal intervals of [0, 2)
+    # b_pp/2 = 0.03 is on no grid of K <= 128 equal intervals of [0, 2)
     assert _create(L, _cfg(b_pp=0.06))[0] == -2
     assert _create(L, _cfg(b_pp=0.1))[0] == 0           # K = 40
 

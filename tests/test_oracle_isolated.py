@@ -67,7 +67,8 @@ def _pairwise_residuals(p, seed, per_bin=8, nbins=15):
             r = float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
             u = rng.standard_normal(3)
             u /= np.linalg.norm(u)
-            a0 = 2.0 + rng.random(3) * (L - 4.0 - r * np.abs(u))
+            # both particles inside [2, L - 2] on every axis
+            a0 = 2.0 + np.maximum(-r * u, 0.0) + rng.random(3) * (L - 4.0 - r * np.abs(u))
             F = o.accel(np.stack([a0, a0 + r * u], axis=1))[:, 0]
             res.append(np.linalg.norm(F) / oracle.refforce(r, p.b_pp) - 1.0)
     return np.array(res)

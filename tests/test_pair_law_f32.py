@@ -26,7 +26,7 @@ import pytest
 import oracle
 from oracle import exact
 
-CONFIGS = [(2.0, 0.2), (1.5, 0.1), (1.0, 0.3)]
+CONFIGS = [(2.0, 0.2), (1.5, 0.1), (1.0, 0.3), (3.5, 0.0625)]
 
 
 def _ctx(b_f, b_pp):
