@@ -87,6 +87,9 @@ def lib():
             "orc_interp_adjoint_mesh": (None, [i64, p, i, d, i, p, p]),
             "orc_interp_adjoint_pos": (None, [i64, p, i, d, i, p, p, p]),
             "orc_deposit_adjoint_pos": (None, [i64, p, i, d, i, p, p]),
+            "orc_interp_adjoint_mesh_tsc": (None, [i64, p, i, d, i, p, p]),
+            "orc_interp_adjoint_pos_tsc": (None, [i64, p, i, d, i, p, p, p]),
+            "orc_deposit_adjoint_pos_tsc": (None, [i64, p, i, d, i, p, p]),
             "orc_pp_g": (d, [d, d, d]),
             "orc_pp_dg": (d, [d, d, d]),
             "orc_pp_brute": (None, [i64, p, d, d, d, p]),
@@ -387,7 +390,7 @@ class Oracle:
           rhobar = K phibar                           (G real, even: K^T = K)
           xbar_i = c grad_x W . (abar_i . E) + grad_x W . rhobar
         """
-        assert self.p.assign == 2, "the oracle adjoints are written for CIC"
+        tsc = self.p.assign == 3
         H = self.p.levels()[level][0]
         n = self.p.levels()[level][1]
         c = self.p.G_N * self.p.m_p / H ** 2
@@ -397,15 +400,17 @@ class Oracle:
         _, _, E = self.level_mesh(xf, level)
         xbar = np.zeros((3, N))
         ab_c = np.ascontiguousarray(abar * c)
-        lib().orc_interp_adjoint_pos(N, _p(xf), int(n), float(H), int(self.quant),
-                                     _p(np.ascontiguousarray(E)), _p(ab_c), _p(xbar))
+        L = lib()
+        adj_pos = L.orc_interp_adjoint_pos_tsc if tsc else L.orc_interp_adjoint_pos
+        adj_mesh = L.orc_interp_adjoint_mesh_tsc if tsc else L.orc_interp_adjoint_mesh
+        dep_pos = L.orc_deposit_adjoint_pos_tsc if tsc else L.orc_deposit_adjoint_pos
+        adj_pos(N, _p(xf), int(n), float(H), int(self.quant),
+                _p(np.ascontiguousarray(E)), _p(ab_c), _p(xbar))
         Eb = np.zeros((3, n, n, n))
-        lib().orc_interp_adjoint_mesh(N, _p(xf), int(n), float(H), int(self.quant),
-                                      _p(ab_c), _p(Eb))
+        adj_mesh(N, _p(xf), int(n), float(H), int(self.quant), _p(ab_c), _p(Eb))
         phibar = fd_force_adjoint(Eb)
         rhobar = np.ascontiguousarray(potential(phibar, self.green(level)))
-        lib().orc_deposit_adjoint_pos(N, _p(xf), int(n), float(H), int(self.quant),
-                                      _p(rhobar), _p(xbar))
+        dep_pos(N, _p(xf), int(n), float(H), int(self.quant), _p(rhobar), _p(xbar))
         return xbar
 
     def pm_adjoint(self, xf, abar):
@@ -428,15 +433,15 @@ class Oracle:
 
     def deposit_adjoint(self, xf, rhobar, level=None):
         """x-bar of the unit-mass density of the finest level for rhobar."""
-        assert self.p.assign == 2, "the oracle adjoints are written for CIC"
         if level is None:
             level = len(self.p.levels()) - 1
         H, n, _, _ = self.p.levels()[level]
         xf = np.ascontiguousarray(xf, dtype=np.float64)
         xbar = np.zeros((3, xf.shape[1]))
-        lib().orc_deposit_adjoint_pos(xf.shape[1], _p(xf), int(n), float(H), int(self.quant),
-                                      _p(np.ascontiguousarray(rhobar, dtype=np.float64)),
-                                      _p(xbar))
+        dep_pos = lib().orc_deposit_adjoint_pos_tsc if self.p.assign == 3 else \
+            lib().orc_deposit_adjoint_pos
+        dep_pos(xf.shape[1], _p(xf), int(n), float(H), int(self.quant),
+                _p(np.ascontiguousarray(rhobar, dtype=np.float64)), _p(xbar))
         return xbar
 
 

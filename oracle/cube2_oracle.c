@@ -520,6 +520,95 @@ void orc_deposit_adjoint_pos(int64_t N, const double *x, int n, double H, int qu
     }
 }
 
+/* TSC versions of the three adjoints above (eq. 5).  The weights are the
+ * forward's; their derivative with respect to the particle coordinate is
+ * that of the continuous eq. (5) at the (quantised) offset d from the
+ * nearest node, per axis in level units:
+ *   dW(n0-1)/dy = -(1/2 - d),  dW(n0)/dy = -2 d,  dW(n0+1)/dy = 1/2 + d,
+ * divided by H for fine-cell coordinates (the fixed-point rounding of the
+ * weights is taken as the identity, as the quantisation of positions is). */
+static inline void tsc_setup(double xv, double H, int quant, long *n0, double w[3], double dw[3])
+{
+    long m;
+    double d;
+    tsc_coord(xv, H, quant, n0, &m, &d);
+    tsc_weights(m, d, quant, w);
+    dw[0] = -(0.5 - d) / H;
+    dw[1] = -2.0 * d / H;
+    dw[2] = (0.5 + d) / H;
+}
+
+/* Adjoint of orc_interp_tsc with respect to the meshes: Eb(n0+s-1) += W_s abar_i. */
+void orc_interp_adjoint_mesh_tsc(int64_t N, const double *x, int n, double H, int quant,
+                                 const double *abar, double *Eb)
+{
+    size_t n3 = (size_t)n * n * n;
+    for (int64_t i = 0; i < N; ++i) {
+        long n0[3];
+        double w[3][3], dw[3][3];
+        for (int d = 0; d < 3; ++d) tsc_setup(x[d * N + i], H, quant, &n0[d], w[d], dw[d]);
+        for (int sz = 0; sz < 3; ++sz)
+            for (int sy = 0; sy < 3; ++sy)
+                for (int sx = 0; sx < 3; ++sx) {
+                    double W = w[0][sx] * w[1][sy] * w[2][sz];
+                    size_t c = midx(n0[0] + sx - 1, n0[1] + sy - 1, n0[2] + sz - 1, n);
+                    for (int d = 0; d < 3; ++d) Eb[d * n3 + c] += W * abar[d * N + i];
+                }
+    }
+}
+
+/* grad W_s = (dW_x w_y w_z, w_x dW_y w_z, w_x w_y dW_z) for the node offsets s. */
+static inline void tsc_grad(const double w[3][3], const double dw[3][3], int sx, int sy, int sz,
+                            double g[3])
+{
+    g[0] = dw[0][sx] * w[1][sy] * w[2][sz];
+    g[1] = w[0][sx] * dw[1][sy] * w[2][sz];
+    g[2] = w[0][sx] * w[1][sy] * dw[2][sz];
+}
+
+/* Position adjoint of the TSC interpolation: xbar_i += sum_s grad W_s (abar_i . E(n0+s-1)). */
+void orc_interp_adjoint_pos_tsc(int64_t N, const double *x, int n, double H, int quant,
+                                const double *E, const double *abar, double *xbar)
+{
+    size_t n3 = (size_t)n * n * n;
+#pragma omp parallel for
+    for (int64_t i = 0; i < N; ++i) {
+        long n0[3];
+        double w[3][3], dw[3][3];
+        for (int d = 0; d < 3; ++d) tsc_setup(x[d * N + i], H, quant, &n0[d], w[d], dw[d]);
+        for (int sz = 0; sz < 3; ++sz)
+            for (int sy = 0; sy < 3; ++sy)
+                for (int sx = 0; sx < 3; ++sx) {
+                    size_t c = midx(n0[0] + sx - 1, n0[1] + sy - 1, n0[2] + sz - 1, n);
+                    double dot = 0.0;
+                    for (int d = 0; d < 3; ++d) dot += abar[d * N + i] * E[d * n3 + c];
+                    double g[3];
+                    tsc_grad(w, dw, sx, sy, sz, g);
+                    for (int d = 0; d < 3; ++d) xbar[d * N + i] += g[d] * dot;
+                }
+    }
+}
+
+/* Position adjoint of the TSC deposit: xbar_i += sum_s grad W_s rhobar(n0+s-1). */
+void orc_deposit_adjoint_pos_tsc(int64_t N, const double *x, int n, double H, int quant,
+                                 const double *rhobar, double *xbar)
+{
+#pragma omp parallel for
+    for (int64_t i = 0; i < N; ++i) {
+        long n0[3];
+        double w[3][3], dw[3][3];
+        for (int d = 0; d < 3; ++d) tsc_setup(x[d * N + i], H, quant, &n0[d], w[d], dw[d]);
+        for (int sz = 0; sz < 3; ++sz)
+            for (int sy = 0; sy < 3; ++sy)
+                for (int sx = 0; sx < 3; ++sx) {
+                    double rb = rhobar[midx(n0[0] + sx - 1, n0[1] + sy - 1, n0[2] + sz - 1, n)];
+                    double g[3];
+                    tsc_grad(w, dw, sx, sy, sz, g);
+                    for (int d = 0; d < 3; ++d) xbar[d * N + i] += g[d] * rb;
+                }
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* PP: eq. (4d) with the PM3 softening replaced by the fine one         */
 /* ------------------------------------------------------------------ */

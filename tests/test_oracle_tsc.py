@@ -130,3 +130,68 @@ def test_tsc_force_more_accurate_than_cic_against_ewald():
     ref = oracle.reference_accel(xf, p)
     bad = np.median(np.linalg.norm(o.accel(xf) - ref, axis=0) / np.linalg.norm(ref, axis=0))
     assert bad > 2 * med[3]
+
+
+# ------------------------------------------------------------ TSC adjoints --
+
+def _away_from_midpoints(xf, Hs, margin):
+    """Positions whose level coordinates stay clear of the half-integers,
+    where the nearest TSC node changes (eq. 5 is C1 there, but its second
+    derivative jumps)."""
+    ok = np.ones(xf.shape[1], dtype=bool)
+    for H in Hs:
+        fr = np.mod(xf / H, 1.0)
+        ok &= np.all(np.abs(fr - 0.5) > margin, axis=0)
+    return ok
+
+
+@pytest.mark.parametrize("two_level", [False, True])
+def test_tsc_force_adjoint_matches_finite_differences(two_level):
+    # <xbar, v> = d/de sum(abar . a(x + e v)), FP64 central differences of
+    # the continuous-position TSC forward
+    p = oracle.Params(n_fine=32, coarse_ratio=4 if two_level else 0, b_coarse=14.0, assign=3)
+    o = oracle.Oracle(p, quant=False)
+    rng = np.random.default_rng(61)
+    xf = rng.random((3, 200)) * 32
+    xf = np.ascontiguousarray(xf[:, _away_from_midpoints(xf, [1, 4], 0.02)])
+    N = xf.shape[1]
+    abar = rng.standard_normal((3, N))
+    xbar = o.accel_adjoint(xf, abar)
+    for _ in range(3):
+        v = rng.standard_normal((3, N))
+        h = 1e-5
+        fd = (np.sum(abar * o.accel(xf + h * v)) - np.sum(abar * o.accel(xf - h * v))) / (2 * h)
+        assert np.sum(xbar * v) == pytest.approx(fd, rel=2e-6)
+
+
+def test_tsc_deposit_adjoint_matches_finite_differences():
+    o = oracle.Oracle(oracle.Params(n_fine=16, assign=3), quant=False)
+    rng = np.random.default_rng(62)
+    xf = rng.random((3, 100)) * 16
+    xf = np.ascontiguousarray(xf[:, _away_from_midpoints(xf, [1], 0.02)])
+    rhobar = rng.standard_normal((16, 16, 16))
+    xbar = o.deposit_adjoint(xf, rhobar)
+    v = rng.standard_normal(xf.shape)
+    h = 1e-6
+    f = lambda y: np.sum(rhobar * oracle.deposit(y, 16, 1, quant=False, p=3))
+    fd = (f(xf + h * v) - f(xf - h * v)) / (2 * h)
+    assert np.sum(xbar * v) == pytest.approx(fd, rel=1e-7)
+
+
+def test_tsc_weight_derivatives_are_those_of_eq5():
+    """The per-axis derivative used by the adjoints, checked through the
+    deposit adjoint of a single particle against the slope of eq. 5 written
+    out as a function of the node distance."""
+    o = oracle.Oracle(oracle.Params(n_fine=16, assign=3), quant=False)
+    W = lambda t: np.where(np.abs(t) <= 0.5, 0.75 - t * t,
+                           np.where(np.abs(t) <= 1.5, 0.5 * (1.5 - np.abs(t)) ** 2, 0.0))
+    dW = lambda t: np.where(np.abs(t) <= 0.5, -2 * t,
+                            np.where(np.abs(t) <= 1.5, -np.sign(t) * (1.5 - np.abs(t)), 0.0))
+    for y in (5.1, 5.3, 5.49, 5.51, 5.9):
+        x = np.array([[y], [7.2], [8.6]])
+        for node in (4, 5, 6, 7):
+            rhobar = np.zeros((16, 16, 16))
+            rhobar[8, 7, node] = 1.0        # [z][y][x]: only the x node varies
+            xb = o.deposit_adjoint(x, rhobar)
+            expect = dW(y - node) * W(7.2 - 7) * W(8.6 - 8)
+            assert xb[0, 0] == pytest.approx(expect, abs=1e-14)
