@@ -404,10 +404,9 @@ def main():
 
         stages["kick_drift_resort"] = float(np.mean(t_full)) - ms
         out["full_step_ms"] = float(np.mean(t_full))
-        if args.assign == "cic":  # the PM adjoints are built for CIC
-            t_bwd = timed(backward, max(2, args.steps // 2))
-            out["backward_ms"] = float(np.mean(t_bwd))
-            out["backward_forward_ratio"] = float(np.mean(t_bwd)) / ms
+        t_bwd = timed(backward, max(2, args.steps // 2))
+        out["backward_ms"] = float(np.mean(t_bwd))
+        out["backward_forward_ratio"] = float(np.mean(t_bwd)) / ms
         out["stages_ms"] = stages
 
         # roofline of the dominant kernel

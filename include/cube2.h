@@ -76,10 +76,8 @@ enum cube2_flags {
     CUBE2_ASSIGN_TSC = 4,     /* TSC assignment (eq. 5) on every PM level instead
                                  of CIC: 16-bit fixed-point weights, density =
                                  accumulator * 2^-48, G with W = sinc^3 (eq. 9);
-                                 cube2_deposit_backward and
-                                 cube2_pm_force_backward return
-                                 CUBE2_EUNSUPPORTED (their adjoints are built for
-                                 CIC) */
+                                 the adjoints use the same weights and the
+                                 slopes of eq. 5 */
     CUBE2_ISOLATED = 8        /* isolated boundaries (appendix A): the mesh is
                                  twice the isolation box, the particles must lie
                                  in [0, n_fine/2)^3 fine cells, and the
@@ -240,8 +238,9 @@ int cube2_status(cube2_ctx *ctx, cube2_stream_t stream);
 
 /* Adjoint of cube2_deposit for the FP32 density of `level`: given rho_bar
  * (device, n^3), x_bar[d*n+i] (device, fine-cell units) = sum_nodes rho_bar
- * * d(W)/dx_d with the CIC weights' derivative (left-continuous at faces).
- * accumulate != 0 adds. */
+ * * d(W)/dx_d with the CIC weights' derivative (left-continuous at faces),
+ * or with CUBE2_ASSIGN_TSC the TSC weights and the slopes of eq. 5 at the
+ * particle's offset from its nearest node.  accumulate != 0 adds. */
 int cube2_deposit_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
                            int64_t n, int level, const float *rho_bar, float *x_bar,
                            int accumulate, void *work, size_t work_bytes, cube2_stream_t stream);

@@ -332,7 +332,6 @@ int cube2_deposit_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *
                            int64_t n, int level, const float *rho_bar, float *x_bar,
                            int accumulate, void *work, size_t work_bytes, cube2_stream_t stream) {
     CHECK_READY();
-    if (ctx->tsc) return CUBE2_EUNSUPPORTED;  // adjoints are built for CIC
     if (n < 0 || n > INT32_MAX || !cell_start || !rho_bar || (n > 0 && (!pos || !x_bar)))
         return CUBE2_EINVAL;
     if (level < 0 || level >= ctx->n_levels) return CUBE2_EINVAL;
@@ -347,7 +346,6 @@ int cube2_pm_force_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t 
                             int64_t n, const float *acc_bar, float *x_bar, int accumulate,
                             void *work, size_t work_bytes, cube2_stream_t stream) {
     CHECK_READY();
-    if (ctx->tsc) return CUBE2_EUNSUPPORTED;  // adjoints are built for CIC
     if (n < 0 || n > INT32_MAX || !cell_start || (n > 0 && (!pos || !acc_bar || !x_bar)))
         return CUBE2_EINVAL;
     CHECK_WORK(n);

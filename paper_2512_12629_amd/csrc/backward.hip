@@ -9,7 +9,10 @@
 //   rhobar     = K phibar    (G real and even: K symmetric; same FFT pipeline)
 //   xbar_i    += sum_n grad W(y_i - n) [c abar_i . E(n) + rhobar(n)]
 // grad W of the CIC weights is piecewise constant: (1/H) (+-1) times the two
-// other weights (left-continuous at cell faces).
+// other weights (left-continuous at cell faces).  With TSC assignment (eq. 5,
+// context flag CUBE2_ASSIGN_TSC) the weights are the forward's 16-bit ones
+// and their slopes those of eq. 5 at the offset d from the nearest node:
+// -(1/2 - d), -2d, 1/2 + d (1/H), the rounding taken as the identity.
 //
 // The scatters of c*abar onto the meshes accumulate in LDS in 64-bit fixed
 // point (integer LDS atomics are an order of magnitude faster than FP32 ones
@@ -61,17 +64,24 @@ __device__ __forceinline__ unsigned long long to_fixed(float v) {
 // the stencil transpose phibar = D . Abar on the 16^3 interior.
 // ---------------------------------------------------------------------------
 
-constexpr int kAB = kTileIos + 3;            // 11 IOS cells per axis: [c0-2, c0+9)
-constexpr int kASegs = kAB * kAB * kAB;      // 1331
 constexpr int kAN = kTileFine + 4;           // 20 nodes per axis: [a0-2, a0+18)
 constexpr int kAN3 = kAN * kAN * kAN;
 constexpr int kPhiBlock = 512;
-constexpr int kASegPerThread = (kASegs + kPhiBlock - 1) / kPhiBlock;  // 3
+// IOS cells per axis whose particles reach the 20^3 nodes: [c0-2, c0+9) for
+// CIC, [c0-2, c0+10) for TSC (a particle in fine cell j feeds j-1 .. j+2)
+template <int P> struct PhiGeo {
+    static constexpr int AB = kTileIos + (P == 3 ? 4 : 3);   // 11 or 12
+    static constexpr int SEGS = AB * AB * AB;
+    static constexpr int SEG_PER_THREAD = (SEGS + kPhiBlock - 1) / kPhiBlock;
+};
 
+template <int P>
 __global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs,
     const float *__restrict__ abar, int n, int n_f, int nt, float c,
     const unsigned int *__restrict__ amax_bits, float *__restrict__ phibar) {
+    constexpr int kAB = PhiGeo<P>::AB, kASegs = PhiGeo<P>::SEGS;
+    constexpr int kASegPerThread = PhiGeo<P>::SEG_PER_THREAD;
     __shared__ uint32_t seg_pre[kASegs + 1];
     __shared__ uint32_t seg_src[kASegs];
     __shared__ unsigned long long A[kAN3];   // one component at a time, fixed point
@@ -144,24 +154,28 @@ __global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
                 if (sg[k] < 0) continue;
                 const int s = sg[k];
                 const int b[3] = {s % kAB, (s / kAB) % kAB, s / (kAB * kAB)};
-                int j[3];
-                float w[3][2];
+                int j[3];          // first node of the footprint in the 20^3 box
+                float w[3][P];
 #pragma unroll
                 for (int e = 0; e < 3; ++e) {
-                    j[e] = 2 * (b[e] - 2) + (int)(o[k][e] >> 15) + 2;  // node in the 20^3 box
+                    j[e] = 2 * (b[e] - 2) + (int)(o[k][e] >> 15) + 2;  // fine cell's node
                     const int f = (int)(o[k][e] & 0x7FFFu);
-                    w[e][1] = (float)f * inv;
-                    w[e][0] = (float)(32768 - f) * inv;
+                    if constexpr (P == 3) {
+                        j[e] += tsc_axis<float>(f, w[e]) - 1;
+                    } else {
+                        w[e][1] = (float)f * inv;
+                        w[e][0] = (float)(32768 - f) * inv;
+                    }
                 }
 #pragma unroll
-                for (int sz = 0; sz < 2; ++sz)
+                for (int sz = 0; sz < P; ++sz)
 #pragma unroll
-                    for (int sy = 0; sy < 2; ++sy) {
+                    for (int sy = 0; sy < P; ++sy) {
                         const int nz = j[2] + sz, ny = j[1] + sy;
                         if ((unsigned)nz >= (unsigned)kAN || (unsigned)ny >= (unsigned)kAN) continue;
                         const float wyz = w[1][sy] * w[2][sz] * ab[k];
 #pragma unroll
-                        for (int sx = 0; sx < 2; ++sx) {
+                        for (int sx = 0; sx < P; ++sx) {
                             const int nx = j[0] + sx;
                             if ((unsigned)nx >= (unsigned)kAN) continue;
                             atomicAdd(&A[(nz * kAN + ny) * kAN + nx], to_fixed(wyz * w[0][sx]));
@@ -196,18 +210,23 @@ __global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
 // to a 3-component coarse mesh, then the stencil transpose on that mesh
 // ---------------------------------------------------------------------------
 
-constexpr int kCN = kTileFine / 2 + 1;  // 9 coarse nodes per axis (ratio 2)
+// coarse nodes per axis of a tile's footprint at ratio 2: 9 (CIC), 11 (TSC,
+// one more on each side)
+template <int P> constexpr int coarse_nodes_max() { return kTileFine / 2 + (P == 3 ? 3 : 1); }
 
+template <int P>
 __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs,
     const float *__restrict__ abar, int n, int nt, int n_c, int hshift, float c,
     const unsigned int *__restrict__ amax_bits, float *__restrict__ Amesh) {
+    constexpr int kCN = coarse_nodes_max<P>();
     __shared__ unsigned long long A[3][kCN * kCN * kCN];   // fixed point
     __shared__ uint32_t cst[kTileCells + 1];
     int tx, ty, tz;
     tile_of_block(blockIdx.x, nt, tx, ty, tz);
     const int tid = threadIdx.x;
-    const int NC = (kTileFine >> hshift) + 1;
+    const int lo = P == 3 ? 1 : 0;                          // footprint starts lo nodes below
+    const int NC = (kTileFine >> hshift) + 1 + 2 * lo;
     for (int i = tid; i < 3 * kCN * kCN * kCN; i += kBlock) (&A[0][0])[i] = 0ull;
     const float S = fixed_scale(amax_bits, c), invS = 1.0f / S;
     const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
@@ -223,8 +242,8 @@ __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
     for (uint32_t w0 = pbeg + (uint32_t)(tid - lane); w0 < pend; w0 += kBlock) {
         const uint32_t p = w0 + lane;
         const bool valid = p < pend;
-        int j[3] = {0, 0, 0};
-        float w[3][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}}, ab[3] = {0.f, 0.f, 0.f};
+        int j[3] = {0, 0, 0};   // first footprint node, tile-footprint coordinates
+        float w[3][P] = {}, ab[3] = {0.f, 0.f, 0.f};
         if (valid) {
             const int u = seg_search(cst, kTileCells, p);
             const int uc[3] = {u & 7, (u >> 3) & 7, u >> 6};
@@ -233,8 +252,12 @@ __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
                 const uint32_t q = ((uint32_t)uc[d] << 16) + pos[(int64_t)d * n + p];
                 j[d] = (int)(q >> (kFracBits + hshift));
                 const int f = (int)((q >> hshift) & 0x7FFFu);
-                w[d][1] = (float)f * inv;
-                w[d][0] = (float)(32768 - f) * inv;
+                if constexpr (P == 3) {
+                    j[d] += tsc_axis<float>(f, w[d]);   // n0 - 1 + lo
+                } else {
+                    w[d][1] = (float)f * inv;
+                    w[d][0] = (float)(32768 - f) * inv;
+                }
                 ab[d] = c * S * abar[(int64_t)d * n + p];
             }
         }
@@ -244,11 +267,11 @@ __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
         const int key0 = __shfl(key, lead, 64);
         const bool uniform = __ballot(valid && key != key0) == 0ull;
 #pragma unroll
-        for (int sz = 0; sz < 2; ++sz)
+        for (int sz = 0; sz < P; ++sz)
 #pragma unroll
-            for (int sy = 0; sy < 2; ++sy)
+            for (int sy = 0; sy < P; ++sy)
 #pragma unroll
-                for (int sx = 0; sx < 2; ++sx) {
+                for (int sx = 0; sx < P; ++sx) {
                     const float W = w[0][sx] * w[1][sy] * w[2][sz];
                     const int off = (sz * NC + sy) * NC + sx;
                     const unsigned long long q0 = to_fixed(W * ab[0]), q1 = to_fixed(W * ab[1]),
@@ -269,8 +292,8 @@ __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
                 }
     }
     __syncthreads();
-    const int A0x = (tx * kTileFine) >> hshift, A0y = (ty * kTileFine) >> hshift,
-              A0z = (tz * kTileFine) >> hshift;
+    const int A0x = ((tx * kTileFine) >> hshift) - lo, A0y = ((ty * kTileFine) >> hshift) - lo,
+              A0z = ((tz * kTileFine) >> hshift) - lo;
     const int64_t m = (int64_t)n_c * n_c * n_c;
     for (int i = tid; i < NC * NC * NC; i += kBlock) {
         const int lx = i % NC, ly = (i / NC) % NC, lz = i / (NC * NC);
@@ -311,51 +334,77 @@ __global__ void divergence_kernel(const float *__restrict__ A, int n, float *__r
 //   T = c (abar . E) + rhobar   (PM adjoint)   or   T = rhobar (deposit adjoint)
 // ---------------------------------------------------------------------------
 
-constexpr int kFS = kTileFine + 5;   // potential tile with stencil halo
-constexpr int kRS = kTileFine + 1;   // rhobar tile: nodes a .. a+16
-constexpr int kCSMax = kTileFine / 2 + 5;
-constexpr int kCRMax = kTileFine / 2 + 1;
+// Staged tiles per level (side S, first node o below the tile origin): the
+// potential with the stencil halo and the rhobar nodes of the footprints.
+template <int P> struct GatherGeo {
+    static constexpr int PLO = P == 3 ? 3 : 2;   // potential: nodes from -PLO
+    static constexpr int PX = P == 3 ? 7 : 5;    // potential side = tile nodes + PX
+    static constexpr int RLO = P == 3 ? 1 : 0;   // rhobar: nodes from -RLO
+    static constexpr int RX = P == 3 ? 3 : 1;    // rhobar side = tile nodes + RX
+    static constexpr int FS = kTileFine + PX, RS = kTileFine + RX;
+    static constexpr int CSMAX = kTileFine / 2 + PX, CRMAX = kTileFine / 2 + RX;
+};
 
 __device__ __forceinline__ float fd_at(const float *P, int idx, int st) {
     return -((2.0f / 3.0f) * (P[idx + st] - P[idx - st]) -
              (1.0f / 12.0f) * (P[idx + 2 * st] - P[idx - 2 * st]));
 }
 
-// adds (1/H) sum_s grad W_s T_s to xb
-template <bool WITH_E>
-__device__ __forceinline__ void level_gather(const float *P, int S, const float *Rb, int SR,
-                                             const int (&j)[3], const float (&w)[3][2],
-                                             const float (&ab)[3], float c, float invH,
-                                             float (&xb)[3]) {
+// adds invH sum_s grad W_s T_s to xb; j is the first footprint node (tile
+// coordinates), w the weights and dw their slopes in level units
+template <bool WITH_E, int P>
+__device__ __forceinline__ void level_gather(const float *Pt, int S, const float *Rb, int SR,
+                                             const int (&j)[3], const float (&w)[3][P],
+                                             const float (&dw)[3][P], const float (&ab)[3],
+                                             float c, float invH, float (&xb)[3]) {
+    constexpr int PLO = GatherGeo<P>::PLO, RLO = GatherGeo<P>::RLO;
     float g[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-    for (int sz = 0; sz < 2; ++sz)
+    for (int sz = 0; sz < P; ++sz)
 #pragma unroll
-        for (int sy = 0; sy < 2; ++sy)
+        for (int sy = 0; sy < P; ++sy)
 #pragma unroll
-            for (int sx = 0; sx < 2; ++sx) {
-                float T = Rb[((j[2] + sz) * SR + j[1] + sy) * SR + j[0] + sx];
+            for (int sx = 0; sx < P; ++sx) {
+                float T = Rb[((j[2] + sz + RLO) * SR + j[1] + sy + RLO) * SR + j[0] + sx + RLO];
                 if (WITH_E) {
-                    const int idx = ((j[2] + sz + 2) * S + j[1] + sy + 2) * S + j[0] + sx + 2;
-                    const float ex = fd_at(P, idx, 1), ey = fd_at(P, idx, S), ez = fd_at(P, idx, S * S);
+                    const int idx = ((j[2] + sz + PLO) * S + j[1] + sy + PLO) * S + j[0] + sx + PLO;
+                    const float ex = fd_at(Pt, idx, 1), ey = fd_at(Pt, idx, S), ez = fd_at(Pt, idx, S * S);
                     T += c * (ab[0] * ex + ab[1] * ey + ab[2] * ez);
                 }
-                g[0] += (sx ? 1.0f : -1.0f) * w[1][sy] * w[2][sz] * T;
-                g[1] += (sy ? 1.0f : -1.0f) * w[0][sx] * w[2][sz] * T;
-                g[2] += (sz ? 1.0f : -1.0f) * w[0][sx] * w[1][sy] * T;
+                g[0] += dw[0][sx] * w[1][sy] * w[2][sz] * T;
+                g[1] += dw[1][sy] * w[0][sx] * w[2][sz] * T;
+                g[2] += dw[2][sz] * w[0][sx] * w[1][sy] * T;
             }
     xb[0] += g[0] * invH;
     xb[1] += g[1] * invH;
     xb[2] += g[2] * invH;
 }
 
-template <bool WITH_E, bool TWO>
+// weights, slopes and first footprint node of one axis from the 15-bit
+// fraction f of the level coordinate whose cell is j
+template <int P>
+__device__ __forceinline__ int axis_footprint(int j, int f, float (&w)[P], float (&dw)[P]) {
+    if constexpr (P == 3) {
+        return j + tsc_axis_grad<float>(f, w, dw) - 1;
+    } else {
+        const float inv = 1.0f / 32768.0f;
+        w[1] = (float)f * inv;
+        w[0] = (float)(32768 - f) * inv;
+        dw[0] = -1.0f;
+        dw[1] = 1.0f;
+        return j;
+    }
+}
+
+template <bool WITH_E, bool TWO, int P>
 __global__ __launch_bounds__(kBlock) void xbar_gather_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs,
     const float *__restrict__ abar, int n, int n_f, int nt, const float *__restrict__ phi_f,
     const float *__restrict__ rb_f, float c_f, const float *__restrict__ phi_c,
     const float *__restrict__ rb_c, float c_c, int n_c, int hshift, float *__restrict__ xbar,
     int accumulate) {
+    using G = GatherGeo<P>;
+    constexpr int kFS = G::FS, kRS = G::RS, kCSMax = G::CSMAX, kCRMax = G::CRMAX;
     __shared__ float pf[WITH_E ? kFS * kFS * kFS : 1];
     __shared__ float rf[kRS * kRS * kRS];
     __shared__ float pc[(WITH_E && TWO) ? kCSMax * kCSMax * kCSMax : 1];
@@ -367,54 +416,49 @@ __global__ __launch_bounds__(kBlock) void xbar_gather_kernel(
     const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
     stage_cell_starts<kBlock>(cst, cs, key0);
     const int a0x = tx * kTileFine, a0y = ty * kTileFine, a0z = tz * kTileFine;
-    if (WITH_E) stage_block<kFS, kBlock>(pf, phi_f, n_f, a0x - 2, a0y - 2, a0z - 2);
+    if (WITH_E) stage_block<kFS, kBlock>(pf, phi_f, n_f, a0x - G::PLO, a0y - G::PLO, a0z - G::PLO);
     if (rb_f) {
-        stage_block<kRS, kBlock>(rf, rb_f, n_f, a0x, a0y, a0z);
+        stage_block<kRS, kBlock>(rf, rb_f, n_f, a0x - G::RLO, a0y - G::RLO, a0z - G::RLO);
     } else {
         for (int i = tid; i < kRS * kRS * kRS; i += kBlock) rf[i] = 0.0f;
     }
-    const int CS = (kTileFine >> hshift) + 5, CR = (kTileFine >> hshift) + 1;
+    const int CS = (kTileFine >> hshift) + G::PX, CR = (kTileFine >> hshift) + G::RX;
     if (TWO) {
         const int cx0 = a0x >> hshift, cy0 = a0y >> hshift, cz0 = a0z >> hshift;
         if (WITH_E)
             for (int i = tid; i < CS * CS * CS; i += kBlock) {
                 const int lx = i % CS, ly = (i / CS) % CS, lz = i / (CS * CS);
-                pc[i] = phi_c[((int64_t)wrapn(cz0 + lz - 2, n_c) * n_c + wrapn(cy0 + ly - 2, n_c)) * n_c +
-                              wrapn(cx0 + lx - 2, n_c)];
+                pc[i] = phi_c[((int64_t)wrapn(cz0 + lz - G::PLO, n_c) * n_c +
+                               wrapn(cy0 + ly - G::PLO, n_c)) * n_c + wrapn(cx0 + lx - G::PLO, n_c)];
             }
         for (int i = tid; i < CR * CR * CR; i += kBlock) {
             const int lx = i % CR, ly = (i / CR) % CR, lz = i / (CR * CR);
-            rc[i] = rb_c[((int64_t)wrapn(cz0 + lz, n_c) * n_c + wrapn(cy0 + ly, n_c)) * n_c +
-                         wrapn(cx0 + lx, n_c)];
+            rc[i] = rb_c[((int64_t)wrapn(cz0 + lz - G::RLO, n_c) * n_c +
+                          wrapn(cy0 + ly - G::RLO, n_c)) * n_c + wrapn(cx0 + lx - G::RLO, n_c)];
         }
     }
     __syncthreads();
-    const float inv = 1.0f / 32768.0f;
     for (uint32_t p = cst[0] + tid; p < cst[kTileCells]; p += kBlock) {
         const int u = seg_search(cst, kTileCells, p);
         const int uc[3] = {u & 7, (u >> 3) & 7, u >> 6};
         int jf[3], jc[3];
-        float wf[3][2], wc[3][2], ab[3];
+        float wf[3][P], dwf[3][P], wc[3][P], dwc[3][P], ab[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const uint32_t o = pos[(int64_t)d * n + p];
-            const int f = (int)(o & 0x7FFFu);
-            jf[d] = 2 * uc[d] + (int)(o >> 15);
-            wf[d][1] = (float)f * inv;
-            wf[d][0] = (float)(32768 - f) * inv;
+            jf[d] = axis_footprint<P>(2 * uc[d] + (int)(o >> 15), (int)(o & 0x7FFFu), wf[d], dwf[d]);
             ab[d] = WITH_E ? abar[(int64_t)d * n + p] : 0.0f;
             if (TWO) {
                 const uint32_t q = ((uint32_t)uc[d] << 16) + o;
-                const int fc = (int)((q >> hshift) & 0x7FFFu);
-                jc[d] = (int)(q >> (kFracBits + hshift));
-                wc[d][1] = (float)fc * inv;
-                wc[d][0] = (float)(32768 - fc) * inv;
+                jc[d] = axis_footprint<P>((int)(q >> (kFracBits + hshift)), (int)((q >> hshift) & 0x7FFFu),
+                                          wc[d], dwc[d]);
             }
         }
         float xb[3] = {0.f, 0.f, 0.f};
-        level_gather<WITH_E>(pf, kFS, rf, kRS, jf, wf, ab, c_f, 1.0f, xb);
+        level_gather<WITH_E, P>(pf, kFS, rf, kRS, jf, wf, dwf, ab, c_f, 1.0f, xb);
         if (TWO)
-            level_gather<WITH_E>(pc, CS, rc, CR, jc, wc, ab, c_c, 1.0f / (float)(1 << hshift), xb);
+            level_gather<WITH_E, P>(pc, CS, rc, CR, jc, wc, dwc, ab, c_c, 1.0f / (float)(1 << hshift),
+                                    xb);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             float *dst = xbar + (int64_t)d * n + p;
@@ -425,29 +469,31 @@ __global__ __launch_bounds__(kBlock) void xbar_gather_kernel(
 
 }  // namespace
 
-int launch_deposit_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
-                            int level, const float *rho_bar, float *x_bar, int accumulate,
-                            hipStream_t s) {
+namespace {
+
+template <int P>
+void launch_deposit_backward_p(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                               int level, const float *rho_bar, float *x_bar, int accumulate,
+                               hipStream_t s) {
     const int nt = ctx->nt;
     const unsigned blocks = (unsigned)(nt * nt * nt);
     if (level == 0) {
-        xbar_gather_kernel<false, false><<<blocks, kBlock, 0, s>>>(
+        xbar_gather_kernel<false, false, P><<<blocks, kBlock, 0, s>>>(
             pos, cs, nullptr, (int)n, ctx->n_f, nt, nullptr, rho_bar, 0.f, nullptr, nullptr, 0.f, 1,
             0, x_bar, accumulate);
     } else {
         // coarse only: a zero fine rhobar contributes nothing
         const Level &C = ctx->lv[1];
-        xbar_gather_kernel<false, true><<<blocks, kBlock, 0, s>>>(
+        xbar_gather_kernel<false, true, P><<<blocks, kBlock, 0, s>>>(
             pos, cs, nullptr, (int)n, ctx->n_f, nt, nullptr, nullptr, 0.f, nullptr, rho_bar, 0.f,
             C.n, C.hshift, x_bar, accumulate);
     }
-    CUBE2_LAUNCH_CHECK();
-    return CUBE2_OK;
 }
 
-int launch_pm_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
-                       const float *acc_bar, float *x_bar, int accumulate, unsigned char *work,
-                       const WorkLayout &L, hipStream_t s) {
+template <int P>
+int launch_pm_backward_p(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                         const float *acc_bar, float *x_bar, int accumulate, unsigned char *work,
+                         const WorkLayout &L, hipStream_t s) {
     const int nt = ctx->nt;
     const unsigned blocks = (unsigned)(nt * nt * nt);
     const double gm = ctx->cfg.g_newton * ctx->cfg.m_p;
@@ -475,8 +521,8 @@ int launch_pm_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, 
         CUBE2_LAUNCH_CHECK();
     }
     // phibar of the fine level, then rhobar = K phibar in place
-    fine_phibar_kernel<<<blocks, kPhiBlock, 0, s>>>(pos, cs, acc_bar, (int)n, ctx->n_f, nt,
-                                                 (float)gm, amax, bf);
+    fine_phibar_kernel<P><<<blocks, kPhiBlock, 0, s>>>(pos, cs, acc_bar, (int)n, ctx->n_f, nt,
+                                                    (float)gm, amax, bf);
     CUBE2_LAUNCH_CHECK();
     r = launch_potential(ctx, 0, bf, bf, spec, s);
     if (r) return r;
@@ -489,23 +535,44 @@ int launch_pm_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, 
         float *Am = reinterpret_cast<float *>(spec);
         fill_f32<<<(unsigned)((3 * m + 255) / 256), 256, 0, s>>>(Am, 3 * m);
         CUBE2_LAUNCH_CHECK();
-        coarse_abar_kernel<<<blocks, kBlock, 0, s>>>(pos, cs, acc_bar, (int)n, nt, C.n, C.hshift,
-                                                     cc, amax, Am);
+        coarse_abar_kernel<P><<<blocks, kBlock, 0, s>>>(pos, cs, acc_bar, (int)n, nt, C.n, C.hshift,
+                                                        cc, amax, Am);
         CUBE2_LAUNCH_CHECK();
         divergence_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(Am, C.n, bc);
         CUBE2_LAUNCH_CHECK();
         r = launch_potential(ctx, 1, bc, bc, spec, s);
         if (r) return r;
-        xbar_gather_kernel<true, true><<<blocks, kBlock, 0, s>>>(
+        xbar_gather_kernel<true, true, P><<<blocks, kBlock, 0, s>>>(
             pos, cs, acc_bar, (int)n, ctx->n_f, nt, rf, bf, (float)gm, rc, bc, cc, C.n, C.hshift,
             x_bar, accumulate);
     } else {
-        xbar_gather_kernel<true, false><<<blocks, kBlock, 0, s>>>(
+        xbar_gather_kernel<true, false, P><<<blocks, kBlock, 0, s>>>(
             pos, cs, acc_bar, (int)n, ctx->n_f, nt, rf, bf, (float)gm, nullptr, nullptr, 0.f, 1, 0,
             x_bar, accumulate);
     }
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
+}
+
+}  // namespace
+
+int launch_deposit_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                            int level, const float *rho_bar, float *x_bar, int accumulate,
+                            hipStream_t s) {
+    if (ctx->tsc)
+        launch_deposit_backward_p<3>(ctx, pos, cs, n, level, rho_bar, x_bar, accumulate, s);
+    else
+        launch_deposit_backward_p<2>(ctx, pos, cs, n, level, rho_bar, x_bar, accumulate, s);
+    CUBE2_LAUNCH_CHECK();
+    return CUBE2_OK;
+}
+
+int launch_pm_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                       const float *acc_bar, float *x_bar, int accumulate, unsigned char *work,
+                       const WorkLayout &L, hipStream_t s) {
+    if (ctx->tsc)
+        return launch_pm_backward_p<3>(ctx, pos, cs, n, acc_bar, x_bar, accumulate, work, L, s);
+    return launch_pm_backward_p<2>(ctx, pos, cs, n, acc_bar, x_bar, accumulate, work, L, s);
 }
 
 }  // namespace cube2

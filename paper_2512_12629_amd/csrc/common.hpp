@@ -121,6 +121,34 @@ __device__ __forceinline__ void tile_of_block(int b, int nt, int &tx, int &ty, i
     tz = t / (nt * nt);
 }
 
+// TSC weights (eq. 5, 16-bit fixed point as the deposit) of the 15-bit
+// fraction f of one axis: nearest-node shift hi and the three weights.
+template <typename T>
+__device__ __forceinline__ int tsc_axis(int f, T (&w)[3]) {
+    const int hi = f >= 16384 ? 1 : 0;
+    const int m = f - (hi << 15);
+    const uint32_t a = (uint32_t)(16384 - m), b = (uint32_t)(16384 + m);
+    const uint32_t w0 = (a * a + 16384u) >> 15, w2 = (b * b + 16384u) >> 15;
+    const T inv = T(1.0 / 65536.0);
+    w[0] = (T)w0 * inv;
+    w[2] = (T)w2 * inv;
+    w[1] = (T)(65536u - w0 - w2) * inv;
+    return hi;
+}
+
+// The same weights with their derivatives in the particle coordinate (level
+// units): d = m 2^-15 is the offset from the nearest node, and the slopes of
+// eq. 5 at the three nodes are -(1/2 - d), -2d and 1/2 + d.
+template <typename T>
+__device__ __forceinline__ int tsc_axis_grad(int f, T (&w)[3], T (&dw)[3]) {
+    const int hi = tsc_axis<T>(f, w);
+    const T d = (T)(f - (hi << 15)) * T(1.0 / 32768.0);
+    dw[0] = -(T(0.5) - d);
+    dw[1] = T(-2) * d;
+    dw[2] = T(0.5) + d;
+    return hi;
+}
+
 __device__ __forceinline__ int wrapn(int i, int n) {  // n is a power of two
     return i & (n - 1);
 }

@@ -89,21 +89,6 @@ __device__ __forceinline__ void gather3(const T *P, int S, int nx, int ny, int n
         }
 }
 
-// TSC weights (eq. 5, 16-bit fixed point as the deposit) of the 15-bit
-// fraction f of one axis: nearest-node shift hi and the three weights.
-template <typename T>
-__device__ __forceinline__ int tsc_axis(int f, T (&w)[3]) {
-    const int hi = f >= 16384 ? 1 : 0;
-    const int m = f - (hi << 15);
-    const uint32_t a = (uint32_t)(16384 - m), b = (uint32_t)(16384 + m);
-    const uint32_t w0 = (a * a + 16384u) >> 15, w2 = (b * b + 16384u) >> 15;
-    const T inv = T(1.0 / 65536.0);
-    w[0] = (T)w0 * inv;
-    w[2] = (T)w2 * inv;
-    w[1] = (T)(65536u - w0 - w2) * inv;
-    return hi;
-}
-
 // At least two waves per SIMD: left alone, the compiler gives the two-level
 // TSC gather all 256 VGPRs and one wave per SIMD.
 template <bool TWO, int P, typename T>
