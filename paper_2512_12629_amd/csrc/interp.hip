@@ -79,7 +79,9 @@ __device__ __forceinline__ void gather3(const T *P, int S, int nx, int ny, int n
                                         T &ax, T &ay, T &az) {
     const int SS = S * S;
     ax = ay = az = T(0);
-#pragma unroll
+    // the outer loop stays rolled: unrolled, the 189 window reads of the nine
+    // lines per axis need 256 registers and spill
+#pragma unroll 1
     for (int s1 = 0; s1 < 3; ++s1)
 #pragma unroll
         for (int s2 = 0; s2 < 3; ++s2) {
