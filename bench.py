@@ -394,6 +394,18 @@ def main():
                 st[i], bufs[i] = bufs[i], st[i]
 
         t_full = timed(full_step, max(2, args.steps // 2))
+        # IOS velocities (section 2.3): int16 codes against a bulk field, encode + decode
+        nbv = m.cube2_vel_bulk_side(c.ctx)
+        vq = torch.empty((3, N), dtype=torch.int16, device="cuda")
+        vbulk = torch.empty((3, nbv, nbv, nbv), dtype=torch.float32, device="cuda")
+        vsc = torch.empty(1, dtype=torch.float32, device="cuda")
+        vdec = torch.empty_like(st[2])
+
+        def vel_codec():
+            m.cube2_vel_encode(c.ctx, st[0], st[1], st[2], vq, vbulk, vsc, c.work)
+            m.cube2_vel_decode(c.ctx, st[0], st[1], vq, vbulk, vsc, vdec)
+
+        t_vel = timed(vel_codec, max(2, args.steps // 2))
         # adjoint of the force (PM + PP), same positions
         abar = torch.randn((3, N), dtype=torch.float32, device="cuda")
         xbar = torch.empty_like(abar)
@@ -403,6 +415,7 @@ def main():
             m.cube2_pp_force_backward(c.ctx, st[0], st[1], abar, xbar, c.work, accumulate=True)
 
         stages["kick_drift_resort"] = float(np.mean(t_full)) - ms
+        stages["vel_encode_decode"] = float(np.mean(t_vel))
         out["full_step_ms"] = float(np.mean(t_full))
         t_bwd = timed(backward, max(2, args.steps // 2))
         out["backward_ms"] = float(np.mean(t_bwd))

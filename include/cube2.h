@@ -230,6 +230,28 @@ int cube2_kick_drift(cube2_ctx *ctx, const uint16_t *pos_in, const uint32_t *cel
 int cube2_reduce(cube2_ctx *ctx, const float *vel, const float *acc, int64_t n, double *out8,
                  void *work, size_t work_bytes, cube2_stream_t stream);
 
+/* IOS velocities (section 2.3: 16-bit velocities relative to a bulk
+ * velocity field on a mesh; the paper defers the conversion formula, this
+ * one is linear).  Bulk mesh: the coarse PM mesh, or cells of 4 fine cells
+ * with one level; cube2_vel_bulk_side gives its side nb (host int out).
+ *   v_bulk[d*nb^3 + (z*nb + y)*nb + x] = mean velocity of the particles in
+ *     bulk cell (x, y, z) (0 for an empty cell), FP32, from exact 64-bit
+ *     fixed-point sums;
+ *   v_scale[0] = s = max_i |v_i - v_bulk(c_i)| / 32767 (1 if all are 0);
+ *   vq[d*n+i] = rint((v - v_bulk(c_i)) / s), clamped to +-32767;
+ * decode: vel = v_bulk(c_i) + s * vq (FP32, two roundings), so that the
+ * round trip errs by at most s/2 plus FP32 rounding.  All arrays are device
+ * memory in the IOS order of pos/cell_start; vel is 3*n floats, vq 3*n
+ * int16, v_bulk 3*nb^3 floats, v_scale one float.  A bulk cell with 2^22
+ * particles or more sets the overflow status. */
+int cube2_vel_bulk_side(const cube2_ctx *ctx, int *side);
+int cube2_vel_encode(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                     const float *vel, int16_t *vq, float *v_bulk, float *v_scale, void *work,
+                     size_t work_bytes, cube2_stream_t stream);
+int cube2_vel_decode(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                     const int16_t *vq, const float *v_bulk, const float *v_scale, float *vel,
+                     cube2_stream_t stream);
+
 /* Synchronise the stream and return the device status (CUBE2_OK or
  * CUBE2_EOVERFLOW), clearing it. */
 int cube2_status(cube2_ctx *ctx, cube2_stream_t stream);

@@ -446,6 +446,63 @@ class Oracle:
 
 
 # ---------------------------------------------------------------------------
+# IOS velocities (section 2.3)
+# ---------------------------------------------------------------------------
+#
+# The paper stores each velocity component as a short integer relative to a
+# bulk velocity field on a mesh and defers the conversion formula to an
+# earlier paper.  Reading used here (linear): the bulk velocity of a cell is
+# the mean velocity of its particles, one global step s = max |v - v_bulk| /
+# 32767, q = rint((v - v_bulk) / s) as int16, decode v = v_bulk + s q.  The
+# arithmetic is FP32 in the order the GPU kernel uses (integer cell sums in
+# 64-bit fixed point with scale S = 2^(41 - e), max|v| < 2^e), so the
+# integer codes are decided in the same precision on both sides.
+# Parity of this step is defined by this reading only (no formula to pin it
+# to); its pins are the round-trip bound and the cell means.
+
+def vel_encode(q: np.ndarray, v: np.ndarray, n_fine: int, shift: int):
+    """(vq int16 (3, N), v_bulk float32 (3, nb, nb, nb), s float32) for IOS
+    positions q (int64, units of 2^-15 fine cells) and FP32 velocities v,
+    bulk cells of 2^shift fine cells (nb = n_fine >> shift)."""
+    q = np.asarray(q, dtype=np.int64)
+    v = np.asarray(v, dtype=np.float32)
+    nb = n_fine >> shift
+    N = v.shape[1]
+    cell = (q >> 15) >> shift
+    key = (cell[2] * nb + cell[1]) * nb + cell[0]
+    vmax = np.float32(np.abs(v).max()) if N else np.float32(0.0)
+    if vmax > 0 and np.isfinite(vmax) and vmax < 3.0e38:
+        e = int(np.frexp(vmax)[1])
+        S = np.float32(2.0 ** min(41 - e, 100))
+    else:
+        S = np.float32(1.0)
+    invS = np.float32(1.0) / S
+    fx = np.rint(v.astype(np.float64) * float(S)).astype(np.int64)
+    cnt = np.bincount(key, minlength=nb ** 3)
+    vb = np.zeros((3, nb ** 3), dtype=np.float32)
+    for d in range(3):
+        sums = np.zeros(nb ** 3, dtype=np.int64)
+        np.add.at(sums, key, fx[d])
+        has = cnt > 0
+        vb[d, has] = (sums[has].astype(np.float32) * invS) / cnt[has].astype(np.float32)
+    dev = v - vb[:, key]
+    m = np.float32(np.abs(dev).max()) if N else np.float32(0.0)
+    s = m / np.float32(32767.0) if m > 0 else np.float32(1.0)
+    vq = np.clip(np.rint(dev / s), -32767, 32767).astype(np.int16)
+    return vq, vb.reshape(3, nb, nb, nb), np.float32(s)
+
+
+def vel_decode(q: np.ndarray, vq: np.ndarray, v_bulk: np.ndarray, s, n_fine: int, shift: int):
+    """v = v_bulk(cell) + s q in FP32 (two roundings)."""
+    q = np.asarray(q, dtype=np.int64)
+    nb = n_fine >> shift
+    cell = (q >> 15) >> shift
+    key = (cell[2] * nb + cell[1]) * nb + cell[0]
+    vb = np.asarray(v_bulk, dtype=np.float32).reshape(3, -1)[:, key]
+    return vb + np.float32(s) * np.asarray(vq, dtype=np.int16).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
 # Time stepping (leapfrog kick-drift, sections 2.2.3 and 2.3)
 # ---------------------------------------------------------------------------
 

@@ -74,6 +74,9 @@ def _load():
         "cube2_kick_drift": [P, P, P, P, P, I64, D, D, P, P, P, P, P, S, P],
         "cube2_reduce": [P, P, P, I64, ctypes.POINTER(D), P, S, P],
         "cube2_status": [P, P],
+        "cube2_vel_bulk_side": [P, ctypes.POINTER(I)],
+        "cube2_vel_encode": [P, P, P, I64, P, P, P, P, P, S, P],
+        "cube2_vel_decode": [P, P, P, I64, P, P, P, P, P],
         "cube2_deposit_backward": [P, P, P, I64, I, P, P, I, P, S, P],
         "cube2_pm_force_backward": [P, P, P, I64, P, P, I, P, S, P],
         "cube2_pp_force_backward": [P, P, P, I64, P, P, I, P, S, P],
@@ -204,6 +207,23 @@ def cube2_reduce(ctx, vel, acc, work, stream=None):
     _check(_lib.cube2_reduce(ctx, _ptr(vel), _ptr(acc), acc.shape[1], out, _ptr(work),
                              work.numel(), _stream(stream)), "cube2_reduce")
     return list(out)
+
+
+def cube2_vel_bulk_side(ctx):
+    side = ctypes.c_int()
+    _check(_lib.cube2_vel_bulk_side(ctx, ctypes.byref(side)), "cube2_vel_bulk_side")
+    return side.value
+
+
+def cube2_vel_encode(ctx, pos, cs, vel, vq, v_bulk, v_scale, work, stream=None):
+    _check(_lib.cube2_vel_encode(ctx, _ptr(pos), _ptr(cs), pos.shape[1], _ptr(vel), _ptr(vq),
+                                 _ptr(v_bulk), _ptr(v_scale), _ptr(work), work.numel(),
+                                 _stream(stream)), "cube2_vel_encode")
+
+
+def cube2_vel_decode(ctx, pos, cs, vq, v_bulk, v_scale, vel, stream=None):
+    _check(_lib.cube2_vel_decode(ctx, _ptr(pos), _ptr(cs), pos.shape[1], _ptr(vq), _ptr(v_bulk),
+                                 _ptr(v_scale), _ptr(vel), _stream(stream)), "cube2_vel_decode")
 
 
 def cube2_status(ctx, stream=None):
@@ -415,6 +435,21 @@ class Cube2:
 
     def status(self):
         return cube2_status(self.ctx)
+
+    # -- IOS velocities ---------------------------------------------------------
+    def vel_encode(self, pos, cs, vel):
+        """(vq int16 (3, n), v_bulk (3, nb, nb, nb), v_scale (1,)) of FP32 velocities."""
+        nb = cube2_vel_bulk_side(self.ctx)
+        vq = torch.empty((3, pos.shape[1]), dtype=torch.int16, device=self.device)
+        vb = torch.empty((3, nb, nb, nb), dtype=torch.float32, device=self.device)
+        sc = torch.empty(1, dtype=torch.float32, device=self.device)
+        cube2_vel_encode(self.ctx, pos, cs, vel.contiguous(), vq, vb, sc, self.work)
+        return vq, vb, sc
+
+    def vel_decode(self, pos, cs, vq, v_bulk, v_scale):
+        vel = torch.empty((3, pos.shape[1]), dtype=torch.float32, device=self.device)
+        cube2_vel_decode(self.ctx, pos, cs, vq.contiguous(), v_bulk.contiguous(), v_scale, vel)
+        return vel
 
     # -- adjoints -------------------------------------------------------------
     def deposit_backward(self, pos, cs, rho_bar, level=0):

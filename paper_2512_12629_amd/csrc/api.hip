@@ -317,6 +317,34 @@ int cube2_reduce(cube2_ctx *ctx, const float *vel, const float *acc, int64_t n, 
                          reinterpret_cast<hipStream_t>(stream));
 }
 
+int cube2_vel_bulk_side(const cube2_ctx *ctx, int *side) {
+    CHECK_READY();
+    if (!side) return CUBE2_EINVAL;
+    *side = vel_bulk_side(ctx);
+    return CUBE2_OK;
+}
+
+int cube2_vel_encode(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                     const float *vel, int16_t *vq, float *v_bulk, float *v_scale, void *work,
+                     size_t work_bytes, cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start || !v_bulk || !v_scale) return CUBE2_EINVAL;
+    if (n > 0 && (!pos || !vel || !vq)) return CUBE2_EINVAL;
+    CHECK_WORK(n);
+    return launch_vel_encode(ctx, pos, cell_start, n, vel, vq, v_bulk, v_scale, work_, L_,
+                             reinterpret_cast<hipStream_t>(stream));
+}
+
+int cube2_vel_decode(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                     const int16_t *vq, const float *v_bulk, const float *v_scale, float *vel,
+                     cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start || !v_bulk || !v_scale) return CUBE2_EINVAL;
+    if (n > 0 && (!pos || !vq || !vel)) return CUBE2_EINVAL;
+    return launch_vel_decode(ctx, pos, cell_start, n, vq, v_bulk, v_scale, vel,
+                             reinterpret_cast<hipStream_t>(stream));
+}
+
 int cube2_status(cube2_ctx *ctx, cube2_stream_t stream) {
     CHECK_READY();
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);

@@ -367,6 +367,13 @@ inline unsigned persistent_grid(K kernel, int block, int ntiles) {
     const long g = (long)(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
     return (unsigned)(g < ntiles ? g : ntiles);
 }
+int vel_bulk_side(const cube2_ctx *ctx);
+int launch_vel_encode(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                      const float *vel, int16_t *vq, float *v_bulk, float *v_scale,
+                      unsigned char *work, const WorkLayout &L, hipStream_t s);
+int launch_vel_decode(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                      const int16_t *vq, const float *v_bulk, const float *v_scale, float *vel,
+                      hipStream_t s);
 int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, float *acc,
               int accumulate, unsigned char *work, const WorkLayout &L, hipStream_t s);
 int build_pair_table(cube2_ctx *ctx);

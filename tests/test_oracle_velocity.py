@@ -1,0 +1,69 @@
+"""Pins of the oracle's IOS velocity codec (section 2.3; the conversion is a
+linear reading, see oracle.vel_encode): what the definition fixes by itself.
+
+* the round trip errs by at most s/2 plus FP32 rounding, s = max deviation /
+  32767, and the largest deviation codes to +-32767 exactly;
+* each bulk velocity is the mean of its cell's velocities (FP64 mean, to a
+  few FP32 roundings); empty cells hold 0;
+* a velocity field constant per bulk cell codes to q = 0 everywhere and
+  decodes exactly; shifting every velocity by a constant shifts the bulk
+  field by it and leaves the codes unchanged (up to FP32 rounding ties)."""
+import numpy as np
+
+import oracle
+import synthetic
+
+
+def _case(seed, n_fine=32, n=20000):
+    x = synthetic.clustered(24, 0.3, 4, 512, 0.5 / n_fine, seed)[:, :n]
+    q = oracle.quantize(x, n_fine)
+    rng = np.random.default_rng(seed)
+    v = (rng.standard_normal(q.shape) * 3.0).astype(np.float32)
+    return q, v
+
+
+def test_round_trip_within_half_a_step():
+    q, v = _case(71)
+    vq, vb, s = oracle.vel_encode(q, v, 32, 2)
+    back = oracle.vel_decode(q, vq, vb, s, 32, 2)
+    err = np.abs(back.astype(np.float64) - v.astype(np.float64))
+    bound = 0.5 * float(s) + 4 * np.spacing(np.abs(v).astype(np.float32)).astype(np.float64)
+    assert np.all(err <= bound)
+    assert np.abs(vq.astype(np.int64)).max() == 32767
+
+
+def test_bulk_is_the_cell_mean():
+    q, v = _case(72)
+    shift, nb = 3, 4
+    _, vb, _ = oracle.vel_encode(q, v, 32, shift)
+    cell = (q >> 15) >> shift
+    key = (cell[2] * nb + cell[1]) * nb + cell[0]
+    cnt = np.bincount(key, minlength=nb ** 3)
+    for d in range(3):
+        ref = np.bincount(key, weights=v[d].astype(np.float64), minlength=nb ** 3)
+        has = cnt > 0
+        ref[has] /= cnt[has]
+        got = vb[d].reshape(-1).astype(np.float64)
+        assert np.all(got[~has] == 0.0)
+        assert np.allclose(got[has], ref[has], rtol=1e-6, atol=1e-6 * np.abs(v).max())
+
+
+def test_cellwise_constant_field_codes_to_zero():
+    q, _ = _case(73)
+    shift, nb = 2, 8
+    cell = (q >> 15) >> shift
+    key = (cell[2] * nb + cell[1]) * nb + cell[0]
+    table = np.arange(3 * nb ** 3, dtype=np.float32).reshape(3, -1) * np.float32(0.25)
+    v = table[:, key]
+    vq, vb, s = oracle.vel_encode(q, v, 32, shift)
+    assert np.all(vq == 0)
+    assert np.array_equal(oracle.vel_decode(q, vq, vb, s, 32, shift), v)
+
+
+def test_uniform_shift_moves_only_the_bulk():
+    q, v = _case(74)
+    vq, vb, s = oracle.vel_encode(q, v, 32, 2)
+    vq2, vb2, s2 = oracle.vel_encode(q, v + np.float32(8.0), 32, 2)
+    assert np.allclose(vb2.reshape(3, -1)[:, vb.reshape(3, -1)[0] != 0] - 8.0,
+                       vb.reshape(3, -1)[:, vb.reshape(3, -1)[0] != 0], atol=1e-5)
+    assert np.abs(vq2.astype(np.int64) - vq.astype(np.int64)).max() <= 1
