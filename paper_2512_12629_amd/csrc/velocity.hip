@@ -80,16 +80,41 @@ __global__ __launch_bounds__(kBlock) void vel_bulk_kernel(
     __syncthreads();
     const float S = vel_scale(amax[0]), invS = 1.0f / S;
     const uint32_t p0 = cst[0], p1 = cst[kTileCells];
-    for (uint32_t p = p0 + tid; p < p1; p += kBlock) {
-        const int u = seg_search(cst, kTileCells, p);
-        uint32_t o[3];
+    // Wave-uniform loop: when every lane of a wave is in the same bulk cell
+    // (dense cells), the wave sums its values first (exact integer sums) and
+    // one lane adds them, instead of 64 lanes contending for one address.
+    const int lane = tid & 63;
+    for (uint32_t w0 = p0 + (uint32_t)(tid - lane); w0 < p1; w0 += kBlock) {
+        const uint32_t p = w0 + (uint32_t)lane;
+        const bool valid = p < p1;
+        int lc = -1;
+        unsigned long long f[3] = {0ull, 0ull, 0ull};
+        if (valid) {
+            const int u = seg_search(cst, kTileCells, p);
+            uint32_t o[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) o[d] = pos[(int64_t)d * n + p];
-        const int lc = bulk_cell(u, o, shift, ct);
-        atomicAdd(&cnt[lc], 1u);
+            for (int d = 0; d < 3; ++d) o[d] = pos[(int64_t)d * n + p];
+            lc = bulk_cell(u, o, shift, ct);
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-            atomicAdd(&sum[d][lc], (unsigned long long)__float2ll_rn(vel[(int64_t)d * n + p] * S));
+            for (int d = 0; d < 3; ++d)
+                f[d] = (unsigned long long)__float2ll_rn(vel[(int64_t)d * n + p] * S);
+        }
+        const unsigned long long vm = __ballot(valid);
+        const int lead = first_lane(vm);
+        const int lc0 = __shfl(lc, lead, 64);
+        if (__ballot(valid && lc != lc0) == 0ull) {
+            const unsigned long long t0 = wave_sum(f[0]), t1 = wave_sum(f[1]), t2 = wave_sum(f[2]);
+            if (lane == lead) {
+                atomicAdd(&cnt[lc0], (uint32_t)__popcll(vm));
+                atomicAdd(&sum[0][lc0], t0);
+                atomicAdd(&sum[1][lc0], t1);
+                atomicAdd(&sum[2][lc0], t2);
+            }
+        } else if (valid) {
+            atomicAdd(&cnt[lc], 1u);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) atomicAdd(&sum[d][lc], f[d]);
+        }
     }
     __syncthreads();
     for (int i = tid; i < ncell; i += kBlock) {
