@@ -57,11 +57,14 @@ __device__ __forceinline__ int64_t bulk_index(int tx, int ty, int tz, int lc, in
 }
 
 // Per tile: cell counts and fixed-point velocity sums of its bulk cells, the
-// means written to v_bulk, and max |v - v_bulk| of its particles.
+// means written to v_bulk, and max |v - v_bulk| of its particles written to
+// tmax[tile] (one global atomic per wave on a single address would
+// serialise; the tile maxima are reduced by a second pass).
 __global__ __launch_bounds__(kBlock) void vel_bulk_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs, const float *__restrict__ vel,
-    int n, int nt, int shift, int nb, unsigned int *__restrict__ amax, float *__restrict__ v_bulk,
-    uint32_t *status) {
+    int n, int nt, int shift, int nb, const unsigned int *__restrict__ amax,
+    float *__restrict__ v_bulk, float *__restrict__ tmax, uint32_t *status) {
+    __shared__ float wmax[kBlock / 64];
     __shared__ uint32_t cnt[kTileCells];
     __shared__ unsigned long long sum[3][kTileCells];
     __shared__ float vb[3][kTileCells];
@@ -80,14 +83,16 @@ __global__ __launch_bounds__(kBlock) void vel_bulk_kernel(
     __syncthreads();
     const float S = vel_scale(amax[0]), invS = 1.0f / S;
     const uint32_t p0 = cst[0], p1 = cst[kTileCells];
-    // Wave-uniform loop: when every lane of a wave is in the same bulk cell
-    // (dense cells), the wave sums its values first (exact integer sums) and
-    // one lane adds them, instead of 64 lanes contending for one address.
+    // Particles are sorted by IOS cell, so equal bulk cells come in runs of
+    // consecutive lanes.  A segmented inclusive scan (exact integer sums)
+    // leaves each run's count and sums in its last lane, which adds them:
+    // one LDS atomic per run instead of one per particle on a few addresses.
     const int lane = tid & 63;
     for (uint32_t w0 = p0 + (uint32_t)(tid - lane); w0 < p1; w0 += kBlock) {
         const uint32_t p = w0 + (uint32_t)lane;
         const bool valid = p < p1;
         int lc = -1;
+        uint32_t c = 0u;
         unsigned long long f[3] = {0ull, 0ull, 0ull};
         if (valid) {
             const int u = seg_search(cst, kTileCells, p);
@@ -95,23 +100,31 @@ __global__ __launch_bounds__(kBlock) void vel_bulk_kernel(
 #pragma unroll
             for (int d = 0; d < 3; ++d) o[d] = pos[(int64_t)d * n + p];
             lc = bulk_cell(u, o, shift, ct);
+            c = 1u;
 #pragma unroll
             for (int d = 0; d < 3; ++d)
                 f[d] = (unsigned long long)__float2ll_rn(vel[(int64_t)d * n + p] * S);
         }
-        const unsigned long long vm = __ballot(valid);
-        const int lead = first_lane(vm);
-        const int lc0 = __shfl(lc, lead, 64);
-        if (__ballot(valid && lc != lc0) == 0ull) {
-            const unsigned long long t0 = wave_sum(f[0]), t1 = wave_sum(f[1]), t2 = wave_sum(f[2]);
-            if (lane == lead) {
-                atomicAdd(&cnt[lc0], (uint32_t)__popcll(vm));
-                atomicAdd(&sum[0][lc0], t0);
-                atomicAdd(&sum[1][lc0], t1);
-                atomicAdd(&sum[2][lc0], t2);
+        const int lc_up = __shfl_up(lc, 1, 64), lc_dn = __shfl_down(lc, 1, 64);
+        int head = (lane == 0 || lc != lc_up) ? 1 : 0;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t c_up = __shfl_up(c, off, 64);
+            const unsigned long long f0 = __shfl_up(f[0], off, 64), f1 = __shfl_up(f[1], off, 64),
+                                     f2 = __shfl_up(f[2], off, 64);
+            const int h_up = __shfl_up(head, off, 64);
+            if (lane >= off) {
+                if (!head) {
+                    c += c_up;
+                    f[0] += f0;
+                    f[1] += f1;
+                    f[2] += f2;
+                }
+                head |= h_up;
             }
-        } else if (valid) {
-            atomicAdd(&cnt[lc], 1u);
+        }
+        if (valid && (lane == 63 || lc_dn != lc)) {
+            atomicAdd(&cnt[lc], c);
 #pragma unroll
             for (int d = 0; d < 3; ++d) atomicAdd(&sum[d][lc], f[d]);
         }
@@ -145,7 +158,13 @@ __global__ __launch_bounds__(kBlock) void vel_bulk_kernel(
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, m, 64));
-    if ((tid & 63) == 0) atomicMax(&amax[1], __float_as_uint(dmax));
+    if ((tid & 63) == 0) wmax[tid >> 6] = dmax;
+    __syncthreads();
+    if (tid == 0) {
+        float b = 0.0f;
+        for (int w = 0; w < kBlock / 64; ++w) b = fmaxf(b, wmax[w]);
+        tmax[blockIdx.x] = b;
+    }
 }
 
 // the global scale s = max |v - v_bulk| / 32767 (1 when every deviation is 0)
@@ -219,8 +238,13 @@ int launch_vel_encode(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, i
         vabsmax_kernel<<<gb, 256, 0, s>>>(vel, m3, amax);
         CUBE2_LAUNCH_CHECK();
     }
-    vel_bulk_kernel<<<blocks, kBlock, 0, s>>>(pos, cs, vel, (int)n, nt, shift, nb, amax, v_bulk,
+    // per-tile maxima in the (here unused) tile-order area of the work buffer
+    float *tmax = reinterpret_cast<float *>(work + L.tile_order);
+    vel_bulk_kernel<<<blocks, kBlock, 0, s>>>(pos, cs, vel, (int)n, nt, shift, nb, amax, v_bulk, tmax,
                                               status_word(ctx));
+    CUBE2_LAUNCH_CHECK();
+    vabsmax_kernel<<<(unsigned)std::min<int64_t>(1024, ((int64_t)blocks + 255) / 256), 256, 0, s>>>(
+        tmax, (int64_t)blocks, amax + 1);
     CUBE2_LAUNCH_CHECK();
     vel_code_kernel<true><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, nt, shift, nb, v_bulk, amax,
                                                     vel, vq, v_scale, nullptr, nullptr, nullptr);
