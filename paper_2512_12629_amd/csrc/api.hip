@@ -76,7 +76,6 @@ WorkLayout work_layout(const cube2_ctx *c, int64_t n) {
     size_t nblk = (std::max(nn, ntiles) + 4095) / 4096;
     L.hist = take(nblk * 256 * 4 + 1024);
     L.tile_order = take((ntiles * 4 + 64) * sizeof(uint32_t));  // + the tile work counter
-    L.counts = take((size_t)(c->n_cells + 1) * 4);
     const size_t scan_len = std::max((size_t)(c->n_cells + 1), nblk * 256);
     L.scan_tmp = take((scan_len / 1024 + 64) * 4 * 2 + 4096);
     L.offs_tmp = take(nn * 3 * sizeof(uint16_t));

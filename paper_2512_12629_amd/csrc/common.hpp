@@ -88,7 +88,7 @@ namespace cube2 {
 struct WorkLayout {
     size_t real_f, real_c, bar_f, bar_c, spec, coarse_acc;
     size_t real64_f, real64_c, spec64;  // FP64 form (zero-sized without it)
-    size_t keys, vals, keys2, vals2, hist, counts, scan_tmp, offs_tmp, red;
+    size_t keys, vals, keys2, vals2, hist, scan_tmp, offs_tmp, red;
     size_t tile_order;  // 4 x (tiles) + 64 uint32: PP tile order, its sort buffers, work counter
     size_t total;
 };

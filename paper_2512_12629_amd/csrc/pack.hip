@@ -8,7 +8,9 @@
 // histogram, one device-wide scan of the digit-major histogram, then a
 // scatter in which each key's rank among equal digits of its block comes
 // from wave ballots (a 64-lane match on the digit) plus per-wave counts in
-// LDS.  Ties keep their input order, so the result equals a stable argsort.
+// LDS; the block's keys are staged in LDS in digit order and written out in
+// runs.  Ties keep their input order, so the result equals a stable argsort.
+// cell_start is read off the sorted keys (no per-cell atomics).
 #include "common.hpp"
 
 namespace cube2 {
@@ -40,12 +42,6 @@ __global__ void quantize_kernel(const float *__restrict__ x, int n, int n_f, int
     }
     keys[i] = cell_key(c[0], c[1], c[2], nt);
     vals[i] = (uint32_t)i;
-}
-
-__global__ void histogram_kernel(const uint32_t *__restrict__ keys, int n,
-                                 uint32_t *__restrict__ counts) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicAdd(&counts[keys[i]], 1u);
 }
 
 // Exclusive scan, phase 1: scan each 1024-element tile, record tile sums.
@@ -112,24 +108,44 @@ __global__ void radix_count(const uint32_t *__restrict__ keys, int n, int shift,
     ghist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
+// Scatter of one 4096-key block.  The scanned digit-major histogram goff
+// gives each (digit, block) its global start; the difference of consecutive
+// entries is the block's own count of that digit.  Keys are first placed in
+// LDS in digit order (rank among equal digits from wave ballots plus per-wave
+// counts, so ties keep their input order), then written out in LDS order, so
+// that consecutive threads write consecutive addresses of one digit's run.
 __global__ void radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                               uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int n,
                               int shift, int nblk, const uint32_t *__restrict__ goff) {
-    __shared__ uint32_t base[256];
+    __shared__ uint32_t gbase[256];  // global start of each digit of this block
+    __shared__ uint32_t lpre[256];   // block-local start of each digit
+    __shared__ uint32_t run[256];    // next free block-local slot of each digit
     __shared__ uint32_t wcnt[kBlock / 64][256];
+    __shared__ uint32_t scan_sh[kBlock / 64 + 1];
+    __shared__ uint32_t sk[kSortTile], sv[kSortTile];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    base[tid] = goff[(int64_t)tid * nblk + blockIdx.x];
+    {
+        const int64_t e = (int64_t)tid * nblk + blockIdx.x;
+        const uint32_t g = goff[e];
+        const uint32_t next = (e + 1 < (int64_t)nblk * 256) ? goff[e + 1] : (uint32_t)n;
+        uint32_t total;
+        const uint32_t lp = block_exclusive_scan(next - g, scan_sh, total);
+        gbase[tid] = g;
+        lpre[tid] = lp;
+        run[tid] = lp;
+    }
     for (int k = 0; k < kBlock / 64; ++k) wcnt[k][tid] = 0;
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t blk0 = (int64_t)blockIdx.x * kSortTile;
+    const int cnt = (int)min((int64_t)kSortTile, (int64_t)n - blk0);
     for (int r = 0; r < kSortItems; ++r) {
-        const int64_t i = blk0 + r * kBlock + tid;
-        const bool valid = i < n;
+        const int li = r * kBlock + tid;
+        const bool valid = li < cnt;
         uint32_t key = 0, val = 0, dig = 0;
         if (valid) {
-            key = kin[i];
-            val = vin[i];
+            key = kin[blk0 + li];
+            val = vin[blk0 + li];
             dig = (key >> shift) & 255u;
         }
         uint64_t peers = __ballot(valid);
@@ -143,10 +159,10 @@ __global__ void radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *
         if (valid && rank == 0) wcnt[w][dig] = (uint32_t)__popcll(peers);
         __syncthreads();
         if (valid) {
-            uint32_t o = base[dig] + rank;
+            uint32_t o = run[dig] + rank;
             for (int k = 0; k < w; ++k) o += wcnt[k][dig];
-            kout[o] = key;
-            vout[o] = val;
+            sk[o] = key;
+            sv[o] = val;
         }
         __syncthreads();
         uint32_t add = 0;
@@ -154,8 +170,42 @@ __global__ void radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *
             add += wcnt[k][tid];
             wcnt[k][tid] = 0;
         }
-        base[tid] += add;
+        run[tid] += add;
         __syncthreads();
+    }
+    for (int j = tid; j < cnt; j += kBlock) {
+        const uint32_t key = sk[j];
+        const uint32_t dig = (key >> shift) & 255u;
+        const uint32_t o = gbase[dig] + ((uint32_t)j - lpre[dig]);
+        kout[o] = key;
+        vout[o] = sv[j];
+    }
+}
+
+// cell_start from the sorted keys: entry c is the first index whose key is
+// >= c, so index i (0..n) writes the entries (key[i-1], key[i]] (with key[-1]
+// = -1 and key[n] = n_cells).  Every entry has exactly one writer.  A run of
+// more than 64 entries (a stretch of empty cells) is written by the whole
+// wave, so that sparse inputs do not leave one lane writing most of the mesh.
+__global__ void cell_starts_kernel(const uint32_t *__restrict__ keys, int n, int64_t n_cells,
+                                   uint32_t *__restrict__ cell_start) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int64_t lo = 0, hi = -1;
+    if (i <= n) {
+        lo = i == 0 ? 0 : (int64_t)keys[i - 1] + 1;
+        hi = i == n ? n_cells : (int64_t)keys[i];
+    }
+    const bool wide = hi - lo >= 64;
+    if (!wide)
+        for (int64_t c = lo; c <= hi; ++c) cell_start[c] = (uint32_t)i;
+    uint64_t m = __ballot(wide);
+    while (m) {
+        const int l = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const long long a = __shfl((long long)lo, l, 64), b = __shfl((long long)hi, l, 64);
+        const uint32_t v = (uint32_t)__shfl((int)i, l, 64);
+        for (long long c = a + lane; c <= b; c += 64) cell_start[c] = v;
     }
 }
 
@@ -224,25 +274,18 @@ int launch_sort_by_cell(cube2_ctx *ctx, int64_t n64, const uint16_t *offs, uint1
                         uint32_t *cell_start, int32_t *perm, unsigned char *work,
                         const WorkLayout &L, hipStream_t s) {
     const int n = (int)n64;
-    uint32_t *counts = reinterpret_cast<uint32_t *>(work + L.counts);
     uint32_t *tmp = reinterpret_cast<uint32_t *>(work + L.scan_tmp);
     uint32_t *k0 = reinterpret_cast<uint32_t *>(work + L.keys);
     uint32_t *v0 = reinterpret_cast<uint32_t *>(work + L.vals);
     uint32_t *k1 = reinterpret_cast<uint32_t *>(work + L.keys2);
     uint32_t *v1 = reinterpret_cast<uint32_t *>(work + L.vals2);
     uint32_t *ghist = reinterpret_cast<uint32_t *>(work + L.hist);
-    const int64_t m = ctx->n_cells + 1;
-
-    // cell_start = exclusive scan of the per-cell counts (last entry = n)
-    fill_u32<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(counts, 0u, m);
-    CUBE2_LAUNCH_CHECK();
-    if (n > 0) {
-        histogram_kernel<<<(n + 255) / 256, 256, 0, s>>>(k0, n, counts);
+    int r = CUBE2_OK;
+    if (n == 0) {
+        cell_starts_kernel<<<1, 64, 0, s>>>(k0, 0, ctx->n_cells, cell_start);
         CUBE2_LAUNCH_CHECK();
+        return CUBE2_OK;
     }
-    int r = exclusive_scan(counts, cell_start, m, tmp, s);
-    if (r) return r;
-    if (n == 0) return CUBE2_OK;
 
     int bits = 0;
     while (((int64_t)1 << bits) < ctx->n_cells) ++bits;
@@ -257,6 +300,9 @@ int launch_sort_by_cell(cube2_ctx *ctx, int64_t n64, const uint16_t *offs, uint1
         uint32_t *t = k0; k0 = k1; k1 = t;
         t = v0; v0 = v1; v1 = t;
     }
+    // cell_start (n_cells + 1 entries, the last = n) from the sorted keys
+    cell_starts_kernel<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(k0, n, ctx->n_cells, cell_start);
+    CUBE2_LAUNCH_CHECK();
     gather_offsets<<<(n + 255) / 256, 256, 0, s>>>(v0, offs, n, pos, perm);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
