@@ -72,6 +72,25 @@ def test_pack_bit_exact(case):
     assert np.array_equal(q_gpu, case["q"][:, perm_or])
 
 
+@pytest.mark.parametrize("n_fine,npart", [(256, 0), (256, 5), (128, 4097)])
+def test_pack_sparse_bit_exact(n_fine, npart):
+    """Few particles on a large mesh (stretches of thousands of empty cells
+    between them), an empty input, and one key past a full 4096-key sort
+    block: cell_start, order and offsets against the oracle."""
+    rng = np.random.default_rng(110 + npart)
+    x = rng.random((3, npart)).astype(np.float32)
+    if npart >= 2:
+        x[:, 1] = x[:, 0]                    # two particles in one cell
+        x[:, -1] = np.float32(1.0 - 2.0 ** -24)  # the last cell of the box
+    c, p, pos, cs, perm = _setup(n_fine, 0, x)
+    torch.cuda.synchronize()
+    q = oracle.quantize(x, n_fine)
+    perm_or, cs_or, off_or = oracle.ios_order(q, n_fine)
+    assert np.array_equal(_np(cs).view(np.uint32), cs_or)
+    assert np.array_equal(_np(perm), perm_or.astype(np.int32))
+    assert np.array_equal(_np(pos).view(np.uint16).reshape(3, -1), off_or.reshape(3, -1))
+
+
 def test_green_table_within_one_ulp(case):
     c, p = case["c"], case["p"]
     for level, (H, n, b_a, b_prev) in enumerate(reversed(p.levels())):
