@@ -2,8 +2,9 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload clu512]
 
-Times K force evaluations (two-level PM + PP, inputs resident in HBM) with HIP
-events on the stream the library launches on, then the full step (force +
+Times K force evaluations (cube2_force: two-level PM + PP, the PP on the
+context's side stream beside the PM, inputs resident in HBM) with HIP events
+on the caller's stream, which waits for both, then the full step (force +
 kick-drift + IOS re-sort), the adjoint (PM + PP backward) and the stages, and
 prints one JSON line.  value = N / t_force (particles per second per force
 step).  A CPU baseline (the FP64 oracle, on a bounded sample of the same
@@ -329,8 +330,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def force():
-        m.cube2_pm_force(c.ctx, pos, cs, acc, c.work)
-        m.cube2_pp_force(c.ctx, pos, cs, acc, c.work, accumulate=True)
+        m.cube2_force(c.ctx, pos, cs, acc, c.work)
 
     def timed(fn, k):
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -386,8 +386,7 @@ def main():
         perm = torch.empty(N, dtype=torch.int32, device="cuda")
 
         def full_step():
-            m.cube2_pm_force(c.ctx, st[0], st[1], acc, c.work)
-            m.cube2_pp_force(c.ctx, st[0], st[1], acc, c.work, accumulate=True)
+            m.cube2_force(c.ctx, st[0], st[1], acc, c.work)
             m.cube2_kick_drift(c.ctx, st[0], st[1], st[2], acc, 1e-3, 1e-3, bufs[0], bufs[1],
                                bufs[2], perm, c.work)
             for i in range(3):
@@ -411,8 +410,7 @@ def main():
         xbar = torch.empty_like(abar)
 
         def backward():
-            m.cube2_pm_force_backward(c.ctx, st[0], st[1], abar, xbar, c.work)
-            m.cube2_pp_force_backward(c.ctx, st[0], st[1], abar, xbar, c.work, accumulate=True)
+            m.cube2_force_backward(c.ctx, st[0], st[1], abar, xbar, c.work)
 
         stages["kick_drift_resort"] = float(np.mean(t_full)) - ms
         stages["vel_encode_decode"] = float(np.mean(t_vel))

@@ -212,6 +212,27 @@ int cube2_pp_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_sta
                    float *acc, int accumulate, void *work, size_t work_bytes,
                    cube2_stream_t stream);
 
+/* The total force of eq. (4): the PM force of all levels plus the PP force,
+ * acc = PM + PP (device, 3*n FP32, overwritten), equal bit for bit to
+ * cube2_pm_force followed by cube2_pp_force with accumulate.  The PP part
+ * runs on a stream of the context (made on the first call, default
+ * priority) beside the PM part on `stream`, with its own tile queue and a
+ * 3*n FP32 staging area in `work`; `stream` waits for both before the sum,
+ * so the call is ordered on `stream` like every other.  Calls that share a
+ * context must not overlap (they share that stream and the work regions). */
+int cube2_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                float *acc, void *work, size_t work_bytes, cube2_stream_t stream);
+
+/* Adjoint of cube2_force: x_bar = PM adjoint + PP adjoint for the cotangents
+ * acc_bar (device, 3*n FP32 each; x_bar overwritten), the same as
+ * cube2_pm_force_backward followed by cube2_pp_force_backward with
+ * accumulate (to the rounding order of the PM adjoint's FP32 coarse-mesh
+ * atomics, which differs from run to run anyway), run the same way as cube2_force (PP adjoint on the context's
+ * stream beside the PM adjoint on `stream`, joined before the sum). */
+int cube2_force_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                         int64_t n, const float *acc_bar, float *x_bar, void *work,
+                         size_t work_bytes, cube2_stream_t stream);
+
 /* Leapfrog kick and drift (sections 2.2.3, 2.3): v' = v + kick*a and
  * q' = q + rint(drift * v' * 2^15) (round half even, FP64 arithmetic),
  * wrapped periodically, then a stable re-sort by IOS cell.  Inputs (device):

@@ -71,6 +71,8 @@ def _load():
         "cube2_interp": [P, P, P, I64, P, P, P, I, P],
         "cube2_pm_force": [P, P, P, I64, P, I, P, S, P],
         "cube2_pp_force": [P, P, P, I64, P, I, P, S, P],
+        "cube2_force": [P, P, P, I64, P, P, S, P],
+        "cube2_force_backward": [P, P, P, I64, P, P, P, S, P],
         "cube2_kick_drift": [P, P, P, P, P, I64, D, D, P, P, P, P, P, S, P],
         "cube2_reduce": [P, P, P, I64, ctypes.POINTER(D), P, S, P],
         "cube2_status": [P, P],
@@ -186,6 +188,17 @@ def cube2_pm_force(ctx, pos, cell_start, acc, work, accumulate=False, stream=Non
     _check(_lib.cube2_pm_force(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], _ptr(acc),
                                int(bool(accumulate)), _ptr(work), work.numel(), _stream(stream)),
            "cube2_pm_force")
+
+
+def cube2_force(ctx, pos, cell_start, acc, work, stream=None):
+    _check(_lib.cube2_force(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], _ptr(acc),
+                            _ptr(work), work.numel(), _stream(stream)), "cube2_force")
+
+
+def cube2_force_backward(ctx, pos, cell_start, acc_bar, x_bar, work, stream=None):
+    _check(_lib.cube2_force_backward(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1],
+                                     _ptr(acc_bar), _ptr(x_bar), _ptr(work), work.numel(),
+                                     _stream(stream)), "cube2_force_backward")
 
 
 def cube2_pp_force(ctx, pos, cell_start, acc, work, accumulate=False, stream=None):
@@ -417,8 +430,9 @@ class Cube2:
         return acc
 
     def force(self, pos, cs):
-        acc = self.pm_force(pos, cs)
-        return self.pp_force(pos, cs, acc)
+        acc = torch.empty((3, pos.shape[1]), dtype=torch.float32, device=self.device)
+        cube2_force(self.ctx, pos, cs, acc, self.work)
+        return acc
 
     def kick_drift(self, pos, cs, vel, acc, kick, drift):
         n = pos.shape[1]

@@ -1,6 +1,6 @@
 """Build libcube2.so (the gfx950 HIP library) in-tree with hipcc.
 
-    python -m paper_2512_12629_amd.build [--force]
+    python paper_2512_12629_amd/build.py [--force]
 
 Each csrc/*.hip is compiled to an object in parallel, then linked into
 paper_2512_12629_amd/_build/libcube2.so.  Packed FP32 instructions are

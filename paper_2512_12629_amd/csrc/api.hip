@@ -80,6 +80,13 @@ WorkLayout work_layout(const cube2_ctx *c, int64_t n) {
     L.scan_tmp = take((scan_len / 1024 + 64) * 4 * 2 + 4096);
     L.offs_tmp = take(nn * 3 * sizeof(uint16_t));
     L.red = take(8192 * 8 * sizeof(double));
+    {
+        const size_t tblk = (ntiles + 4095) / 4096;
+        L.pp_order = take((ntiles * 4 + 64) * sizeof(uint32_t));
+        L.pp_hist = take(tblk * 256 * 4 + 1024);
+        L.pp_scan = take((tblk * 256 / 1024 + 64) * 4 * 2 + 4096);
+        L.acc_pp = take(nn * 3 * sizeof(float));
+    }
     if (c->fp64) {
         L.real64_f = take(nf3 * sizeof(double));
         L.real64_c = take(nc3 * sizeof(double));
@@ -155,7 +162,13 @@ int cube2_create(const cube2_config *cfg, cube2_ctx **out) {
     return CUBE2_OK;
 }
 
-void cube2_destroy(cube2_ctx *ctx) { delete ctx; }
+void cube2_destroy(cube2_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    delete ctx;
+}
 
 int cube2_sizes(const cube2_ctx *ctx, int64_t n_max, size_t *table_bytes, size_t *work_bytes) {
     if (!ctx || n_max < 0 || n_max > INT32_MAX) return CUBE2_EINVAL;
@@ -286,6 +299,63 @@ int cube2_pp_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_sta
         return CUBE2_OK;
     }
     return launch_pp(ctx, pos, cell_start, n, acc, accumulate, work_, L_, s);
+}
+
+namespace {
+
+// The PM part on `stream` and the PP part on the context's side stream,
+// joined on `stream`, then out = PM + PP.  abar == nullptr: the force; else
+// the adjoint for the cotangents abar.
+int force_concurrent(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                     const float *abar, float *out, void *work, size_t work_bytes,
+                     cube2_stream_t stream, unsigned char *work_, const cube2::WorkLayout &L_) {
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (!ctx->side) {
+        CUBE2_CHECK_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        CUBE2_CHECK_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+        CUBE2_CHECK_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    }
+    float *acc_pp = reinterpret_cast<float *>(work_ + L_.acc_pp);
+    // PP first (it starts with a reduced persistent grid), the PM part beside it
+    CUBE2_CHECK_HIP(hipEventRecord(ctx->ev_fork, s));
+    CUBE2_CHECK_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+    int rcode = launch_pp_concurrent(ctx, pos, cell_start, n, abar, acc_pp, work_, L_, ctx->side);
+    if (rcode == CUBE2_OK)
+        rcode = abar ? cube2_pm_force_backward(ctx, pos, cell_start, n, abar, out, 0, work,
+                                               work_bytes, stream)
+                     : cube2_pm_force(ctx, pos, cell_start, n, out, 0, work, work_bytes, stream);
+    // the caller's stream waits for the side stream on every path
+    CUBE2_CHECK_HIP(hipEventRecord(ctx->ev_join, ctx->side));
+    CUBE2_CHECK_HIP(hipStreamWaitEvent(s, ctx->ev_join, 0));
+    if (rcode) return rcode;
+    return launch_add3(out, acc_pp, 3 * n, s);
+}
+
+}  // namespace
+
+int cube2_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                float *acc, void *work, size_t work_bytes, cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start || (n > 0 && (!pos || !acc))) return CUBE2_EINVAL;
+    CHECK_WORK(n);
+    if (n == 0 || (ctx->cfg.flags & CUBE2_PP_OFF))
+        return cube2_pm_force(ctx, pos, cell_start, n, acc, 0, work, work_bytes, stream);
+    return force_concurrent(ctx, pos, cell_start, n, nullptr, acc, work, work_bytes, stream, work_,
+                            L_);
+}
+
+int cube2_force_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                         int64_t n, const float *acc_bar, float *x_bar, void *work,
+                         size_t work_bytes, cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start || (n > 0 && (!pos || !acc_bar || !x_bar)))
+        return CUBE2_EINVAL;
+    CHECK_WORK(n);
+    if (n == 0 || (ctx->cfg.flags & CUBE2_PP_OFF))
+        return cube2_pm_force_backward(ctx, pos, cell_start, n, acc_bar, x_bar, 0, work,
+                                       work_bytes, stream);
+    return force_concurrent(ctx, pos, cell_start, n, acc_bar, x_bar, work, work_bytes, stream,
+                            work_, L_);
 }
 
 int cube2_kick_drift(cube2_ctx *ctx, const uint16_t *pos_in, const uint32_t *cell_start_in,

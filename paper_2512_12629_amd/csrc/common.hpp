@@ -80,6 +80,8 @@ struct cube2_ctx {
     cube2::Level lv[2];
     size_t table_bytes = 0;
     unsigned char *tables = nullptr;   // device; set by cube2_init_tables
+    hipStream_t side = nullptr;        // cube2_force's PP stream (default priority), made on first use
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace cube2 {
@@ -89,6 +91,7 @@ struct WorkLayout {
     size_t real_f, real_c, bar_f, bar_c, spec, coarse_acc;
     size_t real64_f, real64_c, spec64;  // FP64 form (zero-sized without it)
     size_t keys, vals, keys2, vals2, hist, scan_tmp, offs_tmp, red;
+    size_t pp_order, pp_hist, pp_scan, acc_pp;  // cube2_force's concurrent PP: own tile queue, output
     size_t tile_order;  // 4 x (tiles) + 64 uint32: PP tile order, its sort buffers, work counter
     size_t total;
 };
@@ -374,6 +377,10 @@ int launch_vel_encode(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, i
 int launch_vel_decode(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                       const int16_t *vq, const float *v_bulk, const float *v_scale, float *vel,
                       hipStream_t s);
+int launch_pp_concurrent(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                         const float *abar, float *acc_pp, unsigned char *work, const WorkLayout &L,
+                         hipStream_t s);
+int launch_add3(float *acc, const float *acc_pp, int64_t m, hipStream_t s);
 int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, float *acc,
               int accumulate, unsigned char *work, const WorkLayout &L, hipStream_t s);
 int build_pair_table(cube2_ctx *ctx);

@@ -627,7 +627,7 @@ namespace {
 template <bool ADJ, int H>
 int launch_pp_kernel_h(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                      const float *abar, float *out, int accumulate, unsigned char *work,
-                     const WorkLayout &L, hipStream_t s) {
+                     const WorkLayout &L, hipStream_t s, float grid_frac) {
     const float4 *table =
         reinterpret_cast<const float4 *>(ctx->tables + (ADJ ? ctx->pp_aoff : ctx->pp_soff));
     const int nt = ctx->nt;
@@ -637,7 +637,9 @@ int launch_pp_kernel_h(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, 
     const uint32_t *order = tile_order_ptr(work, L);
     uint32_t *queue = tile_queue_ptr(ctx, work, L);
     auto k = pp_kernel<ADJ, H>;
-    k<<<persistent_grid(k, PPGeo<ADJ, H>::BLOCK, ntiles), PPGeo<ADJ, H>::BLOCK, 0, s>>>(
+    const unsigned grid = std::max(
+        1u, (unsigned)((float)persistent_grid(k, PPGeo<ADJ, H>::BLOCK, ntiles) * grid_frac));
+    k<<<grid, PPGeo<ADJ, H>::BLOCK, 0, s>>>(
         pos, cs, (int)n, nt, table, ctx->pp_negc,
         (float)(ctx->cfg.g_newton * ctx->cfg.m_p), abar, out, accumulate, order, queue, ntiles);
     CUBE2_LAUNCH_CHECK();
@@ -647,13 +649,50 @@ int launch_pp_kernel_h(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, 
 template <bool ADJ>
 int launch_pp_kernel(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                      const float *abar, float *out, int accumulate, unsigned char *work,
-                     const WorkLayout &L, hipStream_t s) {
+                     const WorkLayout &L, hipStream_t s, float grid_frac = 1.0f) {
     if (ctx->pp_halo == 1)
-        return launch_pp_kernel_h<ADJ, 1>(ctx, pos, cs, n, abar, out, accumulate, work, L, s);
-    return launch_pp_kernel_h<ADJ, 2>(ctx, pos, cs, n, abar, out, accumulate, work, L, s);
+        return launch_pp_kernel_h<ADJ, 1>(ctx, pos, cs, n, abar, out, accumulate, work, L, s,
+                                          grid_frac);
+    return launch_pp_kernel_h<ADJ, 2>(ctx, pos, cs, n, abar, out, accumulate, work, L, s,
+                                      grid_frac);
 }
 
+__global__ void add3_kernel(float *__restrict__ acc, const float *__restrict__ b, int64_t m) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) acc[i] = acc[i] + b[i];
+}
+
+// Share of the persistent PP grid when the PM force runs beside it: the PM
+// kernels take the freed workgroup slots, and the memory-bound PM and the
+// VALU-bound PP then overlap on the same CUs.
+constexpr float kPPConcurrentFrac = 0.75f;
+
 }  // namespace
+
+// PP force (abar == nullptr) or its adjoint for the cotangents abar into
+// acc_pp (not accumulated) with its own tile order and work counter (the
+// pp_order / pp_hist / pp_scan regions), so that it can run on another stream
+// while the PM part uses the shared ones.
+int launch_pp_concurrent(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                         const float *abar, float *acc_pp, unsigned char *work, const WorkLayout &L,
+                         hipStream_t s) {
+    WorkLayout Lpp = L;
+    Lpp.tile_order = L.pp_order;
+    Lpp.hist = L.pp_hist;
+    Lpp.scan_tmp = L.pp_scan;
+    if (abar)
+        return launch_pp_kernel<true>(ctx, pos, cs, n, abar, acc_pp, 0, work, Lpp, s,
+                                      kPPConcurrentFrac);
+    return launch_pp_kernel<false>(ctx, pos, cs, n, nullptr, acc_pp, 0, work, Lpp, s,
+                                   kPPConcurrentFrac);
+}
+
+int launch_add3(float *acc, const float *acc_pp, int64_t m, hipStream_t s) {
+    if (m <= 0) return CUBE2_OK;
+    add3_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(acc, acc_pp, m);
+    CUBE2_LAUNCH_CHECK();
+    return CUBE2_OK;
+}
 
 int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, float *acc,
               int accumulate, unsigned char *work, const WorkLayout &L, hipStream_t s) {

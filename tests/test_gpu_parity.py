@@ -245,6 +245,40 @@ def test_total_force_against_oracle(case):
     assert med < MED and p99 < P99, (med, p99)
 
 
+def test_force_entry_equals_pm_then_pp(case):
+    """cube2_force (the PP on the context's side stream beside the PM force,
+    its own tile queue, summed after the join) against cube2_pm_force then
+    cube2_pp_force with accumulate: bit for bit, on two calls in a row."""
+    c = case["c"]
+    ref = c.pp_force(case["pos"], case["cs"], c.pm_force(case["pos"], case["cs"]))
+    for _ in range(2):
+        acc = c.force(case["pos"], case["cs"])
+        torch.cuda.synchronize()
+        assert torch.equal(acc, ref)
+
+
+def test_force_backward_entry_equals_pm_then_pp(case):
+    """cube2_force_backward (PP adjoint on the side stream beside the PM
+    adjoint) against the two adjoint entry points in sequence.  The PM
+    adjoint's coarse level adds FP32 values to its mesh with atomics, so two
+    runs agree to rounding order only: within 1e-5 of the largest entry."""
+    import paper_2512_12629_amd as m
+    c, pos, cs = case["c"], case["pos"], case["cs"]
+    n = pos.shape[1]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(211)
+    abar = torch.randn((3, n), device="cuda", generator=g)
+    ref = torch.empty_like(abar)
+    m.cube2_pm_force_backward(c.ctx, pos, cs, abar, ref, c.work)
+    m.cube2_pp_force_backward(c.ctx, pos, cs, abar, ref, c.work, accumulate=True)
+    for _ in range(2):
+        xb = torch.empty_like(abar)
+        m.cube2_force_backward(c.ctx, pos, cs, abar, xb, c.work)
+        torch.cuda.synchronize()
+        scale = float(ref.abs().max())
+        assert float((xb - ref).abs().max()) <= 1e-5 * scale
+
+
 def test_kick_drift_bit_exact(case):
     c, p = case["c"], case["p"]
     N = case["x"].shape[1]
