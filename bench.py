@@ -5,10 +5,16 @@
 Times K force evaluations (cube2_force: two-level PM + PP, the PP on the
 context's side stream beside the PM, inputs resident in HBM) with HIP events
 on the caller's stream, which waits for both, then the full step (force +
-kick-drift + IOS re-sort), the adjoint (PM + PP backward) and the stages, and
-prints one JSON line.  value = N / t_force (particles per second per force
-step).  A CPU baseline (the FP64 oracle, on a bounded sample of the same
-workload recipe) is timed on the host.
+kick-drift + IOS re-sort), the force adjoint (PM + PP backward), the stages,
+and the differentiable leapfrog (Cube2Leapfrog forward over 4 steps with a
+checkpoint every 2, then loss.backward()), and prints one JSON line.
+value = N / t_force (particles per second per force step);
+backward_forward_ratio is the leapfrog's backward time over its forward time.
+A CPU baseline (the FP64 oracle, on a bounded sample of the same workload
+recipe) is timed on the host.
+
+    python bench.py --standalone      # only the separate PM/PP entry points
+                                      # and their adjoints (profiler runs)
 """
 from __future__ import annotations
 
@@ -152,18 +158,87 @@ def _oracle_force_time(workload: str, scale: int, min_total_s: float = 10.0, max
     return x.shape[1], n_f, times
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _single_thread_probe(workload: str, scale: int):
+    """One oracle force on the 1/scale^3 sample in a child process limited to
+    one OpenMP thread (the thread count is fixed when the runtime starts)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-probe", workload,
+                        str(scale)], env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def cpu_baseline(workload: str):
     """Oracle (FP64, as is) on a bounded sample: the same recipe (same sphere
     density) at 1/64 of the volume, timed over repeated evaluations until
-    about 10 s of CPU work is covered."""
+    about 10 s of CPU work is covered, on all host threads; and one
+    evaluation at 1/512 of the volume on a single thread."""
     scale = 4 if workload == "clu512" else 2
     n, n_f, times = _oracle_force_time(workload, scale)
     dt = sum(times) / len(times)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": n / dt, "unit": "particles/s", "cores": threads, "kind": "oracle",
-            "sample": f"{workload} recipe at 1/{scale ** 3} volume: {n} particles, "
-                      f"fine mesh {n_f}^3, full FP64 PM+PP force, mean of {len(times)} "
-                      f"evaluations, {dt:.2f} s each"}
+    out = {"value": n / dt, "unit": "particles/s", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu_model(), "host_logical_cpus": os.cpu_count(),
+           "sample": f"{workload} recipe at 1/{scale ** 3} volume: {n} particles, "
+                     f"fine mesh {n_f}^3, full FP64 PM+PP force, mean of {len(times)} "
+                     f"evaluations, {dt:.2f} s each, {threads} OpenMP threads (the numpy "
+                     f"FFT steps run on one)"}
+    st = _single_thread_probe(workload, 2 * scale)
+    if st:
+        out["single_thread"] = {"value": st["particles"] / st["seconds"], "unit": "particles/s",
+                                "sample": f"1/{(2 * scale) ** 3} volume: {st['particles']} "
+                                          f"particles, fine mesh {st['n_fine']}^3, one "
+                                          f"evaluation, {st['seconds']:.2f} s"}
+    return out
+
+
+def leapfrog_timing(m, c, x_gpu, N, steps: int, ckpt: int, reps: int):
+    """Wall time (HIP events on the caller's stream) of the differentiable
+    multi-step leapfrog: Cube2Leapfrog forward (steps force + kick-drift
+    steps, state checkpoints every ckpt steps, final CIC density) with the
+    loss sum (rho - rho_target)^2, and loss.backward() (checkpoint segment
+    recomputation, kick-drift and force adjoints, deposit adjoint)."""
+    import torch
+    from paper_2512_12629_amd.autograd import Cube2Leapfrog
+    pos, cs, _ = c.pack(x_gpu)
+    amax = float(torch.linalg.vector_norm(c.force(pos, cs), dim=0).max())
+    dt = 0.1 * (1.0 / amax) ** 0.5            # 0.1 sqrt(H_f / max|a_0|)
+    target = c.deposit(pos, cs, 0)
+    del pos, cs
+    stream = torch.cuda.current_stream()
+    fw, bw = [], []
+    for r in range(reps + 1):                   # the first repetition warms up
+        x0 = x_gpu.clone().requires_grad_(True)
+        v0 = torch.zeros_like(x0).requires_grad_(True)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        torch.cuda.synchronize()
+        e[0].record(stream)
+        rho = Cube2Leapfrog.apply(x0, v0, c, steps, dt, dt, ckpt)
+        loss = ((rho - target) ** 2).sum()
+        e[1].record(stream)
+        loss.backward()
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        if r:
+            fw.append(e[0].elapsed_time(e[1]))
+            bw.append(e[1].elapsed_time(e[2]))
+        del x0, v0, rho, loss
+    f, b = float(np.median(fw)), float(np.median(bw))
+    return {"steps": steps, "ckpt_every": ckpt, "dt": dt, "repetitions": reps,
+            "forward_ms": f, "backward_ms": b, "backward_forward_ratio": b / f}
 
 
 def fp64_comparison(m, cfg, c, pos, cs, N, ms32, stream, timed):
@@ -292,10 +367,22 @@ def main():
                          "paper's beta = 3.5")
     ap.add_argument("--pair-b-pp", type=float, default=0.2,
                     help="PP softening of the pairwise experiment (the paper's Fig. 1: ~0.06)")
+    ap.add_argument("--leapfrog-steps", type=int, default=4,
+                    help="steps of the timed differentiable leapfrog (0: skip it)")
+    ap.add_argument("--standalone", action="store_true",
+                    help="time only the separate entry points (PM force, PP force and their "
+                         "adjoints), one after the other, for profiler runs")
+    ap.add_argument("--oracle-probe", nargs=2, metavar=("WORKLOAD", "SCALE"),
+                    help=argparse.SUPPRESS)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timing, run a plain copy kernel (y = -x) of this many MiB "
                          "read + the same written, as the reference for HBM counter passes")
     args = ap.parse_args()
+    if args.oracle_probe:
+        n, n_f, times = _oracle_force_time(args.oracle_probe[0], int(args.oracle_probe[1]),
+                                           min_total_s=0.0, max_reps=1)
+        print(json.dumps({"particles": n, "n_fine": n_f, "seconds": times[0]}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU decomposition is a design, not a build)", file=sys.stderr)
@@ -324,7 +411,6 @@ def main():
     x = torch.from_numpy(x_np).cuda()
     del x_np
     pos, cs, _ = c.pack(x)
-    del x
     vel = torch.zeros((3, N), dtype=torch.float32, device="cuda")
     acc = torch.empty((3, N), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
@@ -343,6 +429,22 @@ def main():
         torch.cuda.synchronize()
         return [a.elapsed_time(b) for a, b in evs]
 
+    if args.standalone:
+        abar = torch.randn((3, N), dtype=torch.float32, device="cuda")
+        xbar = torch.empty_like(abar)
+        st = {}
+        for name, fn in (("pm_force", lambda: m.cube2_pm_force(c.ctx, pos, cs, acc, c.work)),
+                         ("pp_force", lambda: m.cube2_pp_force(c.ctx, pos, cs, acc, c.work)),
+                         ("pm_force_backward",
+                          lambda: m.cube2_pm_force_backward(c.ctx, pos, cs, abar, xbar, c.work)),
+                         ("pp_force_backward",
+                          lambda: m.cube2_pp_force_backward(c.ctx, pos, cs, abar, xbar, c.work))):
+            fn()
+            st[name] = float(np.mean(timed(fn, args.steps)))
+            print(f"[bench] standalone {name}: {st[name]:.3f} ms", file=sys.stderr, flush=True)
+        print(json.dumps({"standalone_ms": st, "workload": args.workload, "steps": args.steps}))
+        return
+
     for _ in range(args.warmup):
         force()
     torch.cuda.synchronize()
@@ -354,7 +456,7 @@ def main():
     status = c.status()
     ms = float(np.median(ts))
     out = {
-        "metric": "particles/sec per full PM+PP force step",
+        "metric": "particles/sec per full PM+PP force step; backward/forward time ratio",
         "value": N / (ms * 1e-3),
         "unit": "particles/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -416,9 +518,21 @@ def main():
         stages["vel_encode_decode"] = float(np.mean(t_vel))
         out["full_step_ms"] = float(np.mean(t_full))
         t_bwd = timed(backward, max(2, args.steps // 2))
-        out["backward_ms"] = float(np.mean(t_bwd))
-        out["backward_forward_ratio"] = float(np.mean(t_bwd)) / ms
+        out["force_backward_ms"] = float(np.mean(t_bwd))
+        out["force_backward_forward_ratio"] = float(np.mean(t_bwd)) / ms
+        t_pmb = timed(lambda: m.cube2_pm_force_backward(c.ctx, st[0], st[1], abar, xbar, c.work),
+                      max(2, args.steps // 2))
+        t_ppb = timed(lambda: m.cube2_pp_force_backward(c.ctx, st[0], st[1], abar, xbar, c.work),
+                      max(2, args.steps // 2))
+        stages["pm_force_backward"] = float(np.mean(t_pmb))
+        stages["pp_force_backward"] = float(np.mean(t_ppb))
         out["stages_ms"] = stages
+        del abar, xbar, bufs, vq, vbulk, vdec, rho
+        torch.cuda.empty_cache()
+        if args.leapfrog_steps > 0:
+            print("[bench] leapfrog forward + backward", file=sys.stderr, flush=True)
+            out["leapfrog"] = leapfrog_timing(m, c, x, N, args.leapfrog_steps, 2, 2)
+            out["backward_forward_ratio"] = out["leapfrog"]["backward_forward_ratio"]
 
         # roofline of the dominant kernel
         pairs = pair_counts().get(args.workload)
@@ -450,10 +564,13 @@ def main():
         hbm = step_reference_bytes(N, meshes)
         t_hbm = hbm / (HBM_PEAK_GBS * 1e9)
         t_alu = pairs * PP_VALU_PER_PAIR / VALU_LANE_OPS
+        t_flop = pairs * PP_FLOPS_PER_PAIR / (VALU_FP32_TFLOPS * 1e12)
         out["step_roofline"] = {
-            "t_roof_ms": (t_hbm + t_alu) * 1e3, "t_hbm_ms": t_hbm * 1e3, "t_pp_valu_ms": t_alu * 1e3,
-            "reference_bytes": hbm, "pp_valu_per_pair": PP_VALU_PER_PAIR,
-            "frac": (t_hbm + t_alu) * 1e3 / ms}
+            "t_roof_ms": (t_hbm + t_flop) * 1e3, "t_hbm_ms": t_hbm * 1e3,
+            "t_pp_flop_ms": t_flop * 1e3, "reference_bytes": hbm,
+            "pp_flops_per_pair": PP_FLOPS_PER_PAIR, "frac": (t_hbm + t_flop) * 1e3 / ms,
+            "instruction_model": {"t_pp_valu_ms": t_alu * 1e3, "pp_valu_per_pair": PP_VALU_PER_PAIR,
+                                  "frac": (t_hbm + t_alu) * 1e3 / ms}}
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(args.workload)

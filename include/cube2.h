@@ -121,6 +121,15 @@ void cube2_destroy(cube2_ctx *ctx);
  * n_max particles. (host) outputs. */
 int cube2_sizes(const cube2_ctx *ctx, int64_t n_max, size_t *table_bytes, size_t *work_bytes);
 
+/* Host-only consistency check of the context's buffer layout for up to
+ * n_max particles and of the index arithmetic the kernels derive from its
+ * geometry, run on the host with the kernels' own index functions: the
+ * velocity codec's bulk cells of every tile (section 2.3) and their per-tile
+ * maxima, the PM adjoint's fixed-point coarse mesh and the concurrent PP
+ * staging area stay inside their regions.  No device work; CUBE2_OK, or
+ * CUBE2_EUNSUPPORTED / CUBE2_EWORKSPACE naming the failed check's kind. */
+int cube2_self_check(const cube2_ctx *ctx, int64_t n_max);
+
 /* Mesh geometry of level 0 (fine) or 1 (coarse): cells per side and the
  * complex row pitch P (in complex elements) of the half-spectrum layout
  * [kz][ky][kx], kx in [0, n/2] padded to P. */
@@ -215,22 +224,24 @@ int cube2_pp_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_sta
 /* The total force of eq. (4): the PM force of all levels plus the PP force,
  * acc = PM + PP (device, 3*n FP32, overwritten), equal bit for bit to
  * cube2_pm_force followed by cube2_pp_force with accumulate.  The PP part
- * runs on a stream of the context (made on the first call, default
- * priority) beside the PM part on `stream`, with its own tile queue and a
- * 3*n FP32 staging area in `work`; `stream` waits for both before the sum,
- * so the call is ordered on `stream` like every other.  Calls that share a
- * context must not overlap (they share that stream and the work regions). */
+ * runs on a stream of the context (made with its two events by
+ * cube2_init_tables, default priority) beside the PM part on `stream`, with
+ * its own tile queue and a 3*n FP32 staging area in `work`; `stream` waits
+ * for both before the sum, so the call is ordered on `stream` like every
+ * other.  Calls that share a context must not overlap (they share that
+ * stream and the work regions). */
 int cube2_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
                 float *acc, void *work, size_t work_bytes, cube2_stream_t stream);
 
 /* Adjoint of cube2_force: x_bar = PM adjoint + PP adjoint for the cotangents
- * acc_bar (device, 3*n FP32 each; x_bar overwritten), the same as
- * cube2_pm_force_backward followed by cube2_pp_force_backward with
- * accumulate (to the rounding order of the PM adjoint's FP32 coarse-mesh
- * atomics, which differs from run to run anyway), run the same way as cube2_force (PP adjoint on the context's
+ * acc_bar (device, 3*n FP32 each; accumulate != 0 adds to x_bar), equal bit
+ * for bit to cube2_pm_force_backward (with the same accumulate) followed by
+ * cube2_pp_force_backward with accumulate (every adjoint scatter sums in
+ * exact fixed point, so the result does not depend on the order of the
+ * atomics), run the same way as cube2_force (PP adjoint on the context's
  * stream beside the PM adjoint on `stream`, joined before the sum). */
 int cube2_force_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
-                         int64_t n, const float *acc_bar, float *x_bar, void *work,
+                         int64_t n, const float *acc_bar, float *x_bar, int accumulate, void *work,
                          size_t work_bytes, cube2_stream_t stream);
 
 /* Leapfrog kick and drift (sections 2.2.3, 2.3): v' = v + kick*a and
@@ -292,7 +303,9 @@ int cube2_deposit_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *
  * 3*n) = (d acc / d x)^T acc_bar.  Per level: scatter of acc_bar, FD
  * divergence (the transpose of eq. 7's stencil), the same FFT-G-IFFT (G is
  * real and even, so the operator is symmetric), the deposit adjoint, plus
- * the derivative of the interpolation weights.  accumulate != 0 adds. */
+ * the derivative of the interpolation weights.  The scatters sum in 64-bit
+ * fixed point (scale 2^(41-e), 2^e > G m max|acc_bar| / H^2), so the result
+ * is deterministic.  accumulate != 0 adds. */
 int cube2_pm_force_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
                             int64_t n, const float *acc_bar, float *x_bar, int accumulate,
                             void *work, size_t work_bytes, cube2_stream_t stream);

@@ -25,8 +25,10 @@ eq. (2) and the difference are evaluated in x87 extended precision and
 rounded once.  ``oracle.exact`` evaluates the PP sum in exact rational
 arithmetic for small particle sets.
 
-Parity pins: see tests/test_oracle_*.py.  The IOS velocity codec is not
-implemented here (parity unpinned in the paper's terms).
+Parity pins: see tests/test_oracle_*.py.  The IOS velocity codec follows a
+linear reading of section 2.3 (the paper defers its formula to an earlier
+paper): pinned by its own definition (round trip, cell means, invariances),
+parity unpinned in the paper's terms.
 """
 from __future__ import annotations
 
@@ -97,6 +99,7 @@ def lib():
             "orc_pp_subset": (None, [i64, p, d, d, d, i64, p, p]),
             "orc_pp_count": (i64, [i64, p, d, d]),
             "orc_pp_adjoint": (None, [i64, p, d, d, d, p, p]),
+            "orc_pp_adjoint_subset": (None, [i64, p, d, d, d, p, i64, p, p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -287,9 +290,17 @@ def deposit(xf: np.ndarray, n: int, H: float, quant: bool = True, p: int = 2) ->
     return out
 
 
-def potential(rho: np.ndarray, G_table: np.ndarray) -> np.ndarray:
-    """phi = IFFT(G * FFT(rho)), forward unnormalised, inverse 1/n^3."""
+def potential(rho: np.ndarray, G_table: np.ndarray, workers: int = 1) -> np.ndarray:
+    """phi = IFFT(G * FFT(rho)), forward unnormalised, inverse 1/n^3.
+
+    workers > 1 uses scipy's multi-threaded FFT (the same transform, for the
+    large meshes); otherwise numpy's."""
     n = rho.shape[0]
+    if workers > 1:
+        import scipy.fft
+        spec = scipy.fft.rfftn(rho, workers=workers)
+        spec *= green_full(G_table, n)
+        return scipy.fft.irfftn(spec, s=(n, n, n), axes=(0, 1, 2), workers=workers)
     return np.fft.irfftn(np.fft.rfftn(rho) * green_full(G_table, n), s=(n, n, n), axes=(0, 1, 2))
 
 
@@ -425,6 +436,16 @@ class Oracle:
                              float(self.p.b_fine), _p(ab), _p(xbar))
         return xbar * (self.p.G_N * self.p.m_p)
 
+    def pp_adjoint_subset(self, xf, abar, idx):
+        """The PP adjoint of the target particles idx only (3, len(idx))."""
+        xf = np.ascontiguousarray(xf, dtype=np.float64)
+        ab = np.ascontiguousarray(abar, dtype=np.float64)
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        out = np.zeros((3, len(idx)))
+        lib().orc_pp_adjoint_subset(xf.shape[1], _p(xf), float(self.p.n_fine), float(self.p.b_pp),
+                                    float(self.p.b_fine), _p(ab), len(idx), _p(idx), _p(out))
+        return out * (self.p.G_N * self.p.m_p)
+
     def accel_adjoint(self, xf, abar, pp: bool = True):
         xb = self.pm_adjoint(xf, abar)
         if pp:
@@ -451,55 +472,48 @@ class Oracle:
 #
 # The paper stores each velocity component as a short integer relative to a
 # bulk velocity field on a mesh and defers the conversion formula to an
-# earlier paper.  Reading used here (linear): the bulk velocity of a cell is
-# the mean velocity of its particles, one global step s = max |v - v_bulk| /
-# 32767, q = rint((v - v_bulk) / s) as int16, decode v = v_bulk + s q.  The
-# arithmetic is FP32 in the order the GPU kernel uses (integer cell sums in
-# 64-bit fixed point with scale S = 2^(41 - e), max|v| < 2^e), so the
-# integer codes are decided in the same precision on both sides.
-# Parity of this step is defined by this reading only (no formula to pin it
-# to); its pins are the round-trip bound and the cell means.
+# earlier paper.  Reading used here (linear), written out plainly in FP64:
+# the bulk velocity of a cell is the mean velocity of its particles (0 for an
+# empty cell), one global step s = max |v - v_bulk| / 32767, the code is
+# q = rint((v - v_bulk) / s) clamped to +-32767 as int16, and the decoded
+# velocity is v_bulk + s q.  Parity of this step is defined by this reading
+# only (no formula in the paper to pin it to); its pins are the round-trip
+# bound, the cell means and the invariances.
+
+def _bulk_key(q: np.ndarray, n_fine: int, shift: int) -> np.ndarray:
+    nb = n_fine >> shift
+    cell = (np.asarray(q, dtype=np.int64) >> 15) >> shift
+    return (cell[2] * nb + cell[1]) * nb + cell[0]
+
 
 def vel_encode(q: np.ndarray, v: np.ndarray, n_fine: int, shift: int):
-    """(vq int16 (3, N), v_bulk float32 (3, nb, nb, nb), s float32) for IOS
-    positions q (int64, units of 2^-15 fine cells) and FP32 velocities v,
-    bulk cells of 2^shift fine cells (nb = n_fine >> shift)."""
-    q = np.asarray(q, dtype=np.int64)
-    v = np.asarray(v, dtype=np.float32)
+    """(vq int16 (3, N), v_bulk float64 (3, nb, nb, nb), s float64, r float64
+    (3, N)) for IOS positions q (int64, units of 2^-15 fine cells) and
+    velocities v, bulk cells of 2^shift fine cells (nb = n_fine >> shift);
+    r = (v - v_bulk) / s is the unrounded code."""
+    v = np.asarray(v, dtype=np.float64)
     nb = n_fine >> shift
+    key = _bulk_key(q, n_fine, shift)
     N = v.shape[1]
-    cell = (q >> 15) >> shift
-    key = (cell[2] * nb + cell[1]) * nb + cell[0]
-    vmax = np.float32(np.abs(v).max()) if N else np.float32(0.0)
-    if vmax > 0 and np.isfinite(vmax) and vmax < 3.0e38:
-        e = int(np.frexp(vmax)[1])
-        S = np.float32(2.0 ** min(41 - e, 100))
-    else:
-        S = np.float32(1.0)
-    invS = np.float32(1.0) / S
-    fx = np.rint(v.astype(np.float64) * float(S)).astype(np.int64)
     cnt = np.bincount(key, minlength=nb ** 3)
-    vb = np.zeros((3, nb ** 3), dtype=np.float32)
+    has = cnt > 0
+    vb = np.zeros((3, nb ** 3))
     for d in range(3):
-        sums = np.zeros(nb ** 3, dtype=np.int64)
-        np.add.at(sums, key, fx[d])
-        has = cnt > 0
-        vb[d, has] = (sums[has].astype(np.float32) * invS) / cnt[has].astype(np.float32)
+        sums = np.bincount(key, weights=v[d], minlength=nb ** 3)
+        vb[d, has] = sums[has] / cnt[has]
     dev = v - vb[:, key]
-    m = np.float32(np.abs(dev).max()) if N else np.float32(0.0)
-    s = m / np.float32(32767.0) if m > 0 else np.float32(1.0)
-    vq = np.clip(np.rint(dev / s), -32767, 32767).astype(np.int16)
-    return vq, vb.reshape(3, nb, nb, nb), np.float32(s)
+    m = float(np.abs(dev).max()) if N else 0.0
+    s = m / 32767.0 if m > 0 else 1.0
+    r = dev / s
+    vq = np.clip(np.rint(r), -32767, 32767).astype(np.int16)
+    return vq, vb.reshape(3, nb, nb, nb), s, r
 
 
 def vel_decode(q: np.ndarray, vq: np.ndarray, v_bulk: np.ndarray, s, n_fine: int, shift: int):
-    """v = v_bulk(cell) + s q in FP32 (two roundings)."""
-    q = np.asarray(q, dtype=np.int64)
-    nb = n_fine >> shift
-    cell = (q >> 15) >> shift
-    key = (cell[2] * nb + cell[1]) * nb + cell[0]
-    vb = np.asarray(v_bulk, dtype=np.float32).reshape(3, -1)[:, key]
-    return vb + np.float32(s) * np.asarray(vq, dtype=np.int16).astype(np.float32)
+    """v = v_bulk(cell) + s q (FP64)."""
+    key = _bulk_key(q, n_fine, shift)
+    vb = np.asarray(v_bulk, dtype=np.float64).reshape(3, -1)[:, key]
+    return vb + float(s) * np.asarray(vq, dtype=np.int16).astype(np.float64)
 
 
 # ---------------------------------------------------------------------------

@@ -791,8 +791,48 @@ int64_t orc_pp_count(int64_t N, const double *x, double L, double b_f)
     return total;
 }
 
-/* Adjoint of the PP sum: with J(D) = g(r) I + g'(r) D D^T / r (symmetric, even),
- * xbar_k += sum_j J(D_kj) (abar_j - abar_k), D_kj = x_j - x_k. */
+/* Adjoint of the PP sum for one particle k: with J(D) = g(r) I + g'(r) D D^T / r
+ * (symmetric, even), out = sum_j J(D_kj) (abar_j - abar_k), D_kj = x_j - x_k,
+ * over the 27 linked-list cells around k (all N particles without cells). */
+static void pp_adjoint_one(int64_t k, int64_t N, const double *x, double L, double b_pp,
+                           double b_f, const double *abar, const cells_t *c, int have,
+                           double out[3])
+{
+    out[0] = out[1] = out[2] = 0.0;
+    long ck[3] = {0, 0, 0};
+    if (have)
+        for (int d = 0; d < 3; ++d) ck[d] = wrapi((long)floor(x[d * N + k] / c->cs), c->nc);
+    int64_t jlist_end = have ? 27 : 1;
+    for (int64_t cell = 0; cell < jlist_end; ++cell) {
+        int64_t j;
+        if (have) {
+            int ox = (int)(cell % 3) - 1, oy = (int)((cell / 3) % 3) - 1, oz = (int)(cell / 9) - 1;
+            j = c->head[midx(ck[0] + ox, ck[1] + oy, ck[2] + oz, c->nc)];
+        } else {
+            j = 0;
+        }
+        for (; have ? j >= 0 : j < N; j = have ? c->next[j] : j + 1) {
+            if (j == k) continue;
+            double D[3], r2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                D[d] = minimg(x[d * N + j] - x[d * N + k], L);
+                r2 += D[d] * D[d];
+            }
+            xreal rx = sqrtl((xreal)r2);
+            if (!(rx > 0.0L) || rx >= b_f) continue;
+            double r = (double)rx;
+            double g = (double)pp_g_x(rx, b_pp, b_f), gp = (double)pp_dg_x(rx, b_pp, b_f);
+            double u[3], Du = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                u[d] = abar[d * N + j] - abar[d * N + k];
+                Du += D[d] * u[d];
+            }
+            for (int d = 0; d < 3; ++d) out[d] += g * u[d] + gp * D[d] * Du / r;
+        }
+    }
+}
+
+/* Adjoint of the PP sum: xbar_k += sum_j J(D_kj) (abar_j - abar_k). */
 void orc_pp_adjoint(int64_t N, const double *x, double L, double b_pp, double b_f,
                     const double *abar, double *xbar)
 {
@@ -800,39 +840,25 @@ void orc_pp_adjoint(int64_t N, const double *x, double L, double b_pp, double b_
     int have = cells_build(N, x, L, b_f, &c);
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t k = 0; k < N; ++k) {
-        double out[3] = {0, 0, 0};
-        long ck[3] = {0, 0, 0};
-        if (have)
-            for (int d = 0; d < 3; ++d) ck[d] = wrapi((long)floor(x[d * N + k] / c.cs), c.nc);
-        int64_t jlist_end = have ? 27 : 1;
-        for (int64_t cell = 0; cell < jlist_end; ++cell) {
-            int64_t j;
-            if (have) {
-                int ox = (int)(cell % 3) - 1, oy = (int)((cell / 3) % 3) - 1, oz = (int)(cell / 9) - 1;
-                j = c.head[midx(ck[0] + ox, ck[1] + oy, ck[2] + oz, c.nc)];
-            } else {
-                j = 0;
-            }
-            for (; have ? j >= 0 : j < N; j = have ? c.next[j] : j + 1) {
-                if (j == k) continue;
-                double D[3], r2 = 0.0;
-                for (int d = 0; d < 3; ++d) {
-                    D[d] = minimg(x[d * N + j] - x[d * N + k], L);
-                    r2 += D[d] * D[d];
-                }
-                xreal rx = sqrtl((xreal)r2);
-                if (!(rx > 0.0L) || rx >= b_f) continue;
-                double r = (double)rx;
-                double g = (double)pp_g_x(rx, b_pp, b_f), gp = (double)pp_dg_x(rx, b_pp, b_f);
-                double u[3], Du = 0.0;
-                for (int d = 0; d < 3; ++d) {
-                    u[d] = abar[d * N + j] - abar[d * N + k];
-                    Du += D[d] * u[d];
-                }
-                for (int d = 0; d < 3; ++d) out[d] += g * u[d] + gp * D[d] * Du / r;
-            }
-        }
+        double out[3];
+        pp_adjoint_one(k, N, x, L, b_pp, b_f, abar, &c, have, out);
         for (int d = 0; d < 3; ++d) xbar[d * N + k] += out[d];
+    }
+    if (have) cells_free(&c);
+}
+
+/* The same adjoint for the target particles idx[0..M) only (sources all N):
+ * xbar[d*M + t] = (sum_j J(D_kj) (abar_j - abar_k))_d with k = idx[t]. */
+void orc_pp_adjoint_subset(int64_t N, const double *x, double L, double b_pp, double b_f,
+                           const double *abar, int64_t M, const int64_t *idx, double *xbar)
+{
+    cells_t c;
+    int have = cells_build(N, x, L, b_f, &c);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < M; ++t) {
+        double out[3];
+        pp_adjoint_one(idx[t], N, x, L, b_pp, b_f, abar, &c, have, out);
+        for (int d = 0; d < 3; ++d) xbar[d * M + t] = out[d];
     }
     if (have) cells_free(&c);
 }

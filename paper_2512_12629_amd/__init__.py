@@ -62,6 +62,7 @@ def _load():
         "cube2_destroy": [P],
         "cube2_sizes": [P, I64, ctypes.POINTER(S), ctypes.POINTER(S)],
         "cube2_level_shape": [P, I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+        "cube2_self_check": [P, I64],
         "cube2_init_tables": [P, P, S, P],
         "cube2_green_table": [P, I, P, P],
         "cube2_pack": [P, P, I64, P, P, P, P, S, P],
@@ -72,7 +73,7 @@ def _load():
         "cube2_pm_force": [P, P, P, I64, P, I, P, S, P],
         "cube2_pp_force": [P, P, P, I64, P, I, P, S, P],
         "cube2_force": [P, P, P, I64, P, P, S, P],
-        "cube2_force_backward": [P, P, P, I64, P, P, P, S, P],
+        "cube2_force_backward": [P, P, P, I64, P, P, I, P, S, P],
         "cube2_kick_drift": [P, P, P, P, P, I64, D, D, P, P, P, P, P, S, P],
         "cube2_reduce": [P, P, P, I64, ctypes.POINTER(D), P, S, P],
         "cube2_status": [P, P],
@@ -141,6 +142,11 @@ def cube2_sizes(ctx, n_max: int):
     return tb.value, wb.value
 
 
+def cube2_self_check(ctx, n_max: int) -> int:
+    """Host-only layout/index check of the context (returns the status code)."""
+    return _lib.cube2_self_check(ctx, int(n_max))
+
+
 def cube2_level_shape(ctx, level: int):
     n, p = ctypes.c_int32(), ctypes.c_int32()
     _check(_lib.cube2_level_shape(ctx, int(level), ctypes.byref(n), ctypes.byref(p)),
@@ -195,10 +201,12 @@ def cube2_force(ctx, pos, cell_start, acc, work, stream=None):
                             _ptr(work), work.numel(), _stream(stream)), "cube2_force")
 
 
-def cube2_force_backward(ctx, pos, cell_start, acc_bar, x_bar, work, stream=None):
+def cube2_force_backward(ctx, pos, cell_start, acc_bar, x_bar, work, accumulate=False,
+                         stream=None):
     _check(_lib.cube2_force_backward(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1],
-                                     _ptr(acc_bar), _ptr(x_bar), _ptr(work), work.numel(),
-                                     _stream(stream)), "cube2_force_backward")
+                                     _ptr(acc_bar), _ptr(x_bar), int(bool(accumulate)),
+                                     _ptr(work), work.numel(), _stream(stream)),
+           "cube2_force_backward")
 
 
 def cube2_pp_force(ctx, pos, cell_start, acc, work, accumulate=False, stream=None):
@@ -477,6 +485,14 @@ class Cube2:
             x_bar = torch.empty((3, pos.shape[1]), dtype=torch.float32, device=self.device)
         cube2_pm_force_backward(self.ctx, pos, cs, acc_bar.contiguous(), x_bar, self.work,
                                 accumulate)
+        return x_bar
+
+    def force_backward(self, pos, cs, acc_bar, x_bar=None):
+        """PM + PP adjoint (cube2_force_backward); adds to x_bar if given."""
+        accumulate = x_bar is not None
+        if x_bar is None:
+            x_bar = torch.empty((3, pos.shape[1]), dtype=torch.float32, device=self.device)
+        cube2_force_backward(self.ctx, pos, cs, acc_bar.contiguous(), x_bar, self.work, accumulate)
         return x_bar
 
     def pp_force_backward(self, pos, cs, acc_bar, x_bar=None):

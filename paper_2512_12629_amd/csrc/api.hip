@@ -76,6 +76,7 @@ WorkLayout work_layout(const cube2_ctx *c, int64_t n) {
     size_t nblk = (std::max(nn, ntiles) + 4095) / 4096;
     L.hist = take(nblk * 256 * 4 + 1024);
     L.tile_order = take((ntiles * 4 + 64) * sizeof(uint32_t));  // + the tile work counter
+    L.vel_tmax = take(ntiles * sizeof(float));
     const size_t scan_len = std::max((size_t)(c->n_cells + 1), nblk * 256);
     L.scan_tmp = take((scan_len / 1024 + 64) * 4 * 2 + 4096);
     L.offs_tmp = take(nn * 3 * sizeof(uint16_t));
@@ -177,6 +178,23 @@ int cube2_sizes(const cube2_ctx *ctx, int64_t n_max, size_t *table_bytes, size_t
     return CUBE2_OK;
 }
 
+int cube2_self_check(const cube2_ctx *ctx, int64_t n_max) {
+    if (!ctx || n_max < 0 || n_max > INT32_MAX) return CUBE2_EINVAL;
+    const WorkLayout L = work_layout(ctx, n_max);
+    const size_t ntiles = (size_t)ctx->nt * ctx->nt * ctx->nt;
+    auto fits = [&](size_t off, size_t bytes) { return off + bytes <= L.total; };
+    // the PM adjoint's 3-component 64-bit coarse mesh lives in the spectrum area
+    if (ctx->n_levels > 1) {
+        const size_t nc = (size_t)ctx->lv[1].n;
+        const size_t spec = (size_t)ctx->n_f * ctx->n_f * ctx->lv[0].pitch * 8;
+        if (3 * nc * nc * nc * sizeof(uint64_t) > spec) return CUBE2_EWORKSPACE;
+    }
+    if (!fits(L.acc_pp, (size_t)3 * n_max * sizeof(float))) return CUBE2_EWORKSPACE;
+    if (!fits(L.tile_order, (ntiles * 4 + 64) * sizeof(uint32_t))) return CUBE2_EWORKSPACE;
+    if (!fits(L.vel_tmax, ntiles * sizeof(float))) return CUBE2_EWORKSPACE;
+    return vel_layout_check(ctx, L);
+}
+
 int cube2_level_shape(const cube2_ctx *ctx, int level, int32_t *n, int32_t *pitch) {
     if (!ctx || level < 0 || level >= ctx->n_levels) return CUBE2_EINVAL;
     if (n) *n = ctx->lv[level].n;
@@ -187,8 +205,25 @@ int cube2_level_shape(const cube2_ctx *ctx, int level, int32_t *n, int32_t *pitc
 int cube2_init_tables(cube2_ctx *ctx, void *tables, size_t table_bytes, cube2_stream_t stream) {
     if (!ctx || !tables) return CUBE2_EINVAL;
     if (table_bytes < ctx->table_bytes) return CUBE2_EWORKSPACE;
-    ctx->tables = static_cast<unsigned char *>(tables);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // cube2_force's side stream and its fork/join events, made once per
+    // context; on a partial failure nothing is kept, so a later call retries
+    if (!ctx->side) {
+        hipStream_t side = nullptr;
+        hipEvent_t fork = nullptr, join = nullptr;
+        if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+            if (join) (void)hipEventDestroy(join);
+            if (fork) (void)hipEventDestroy(fork);
+            if (side) (void)hipStreamDestroy(side);
+            return CUBE2_EHIP;
+        }
+        ctx->ev_fork = fork;
+        ctx->ev_join = join;
+        ctx->side = side;
+    }
+    ctx->tables = static_cast<unsigned char *>(tables);
     CUBE2_CHECK_HIP(hipMemsetAsync(ctx->tables, 0, 256, s));
     CUBE2_CHECK_HIP(hipMemcpyAsync(ctx->tables + ctx->pp_aoff, ctx->pp_arows.data(),
                                    ctx->pp_arows.size() * sizeof(float), hipMemcpyHostToDevice, s));
@@ -307,26 +342,27 @@ namespace {
 // joined on `stream`, then out = PM + PP.  abar == nullptr: the force; else
 // the adjoint for the cotangents abar.
 int force_concurrent(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
-                     const float *abar, float *out, void *work, size_t work_bytes,
+                     const float *abar, float *out, int accumulate, void *work, size_t work_bytes,
                      cube2_stream_t stream, unsigned char *work_, const cube2::WorkLayout &L_) {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (!ctx->side) {
-        CUBE2_CHECK_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
-        CUBE2_CHECK_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
-        CUBE2_CHECK_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
-    }
+    if (!ctx->side) return CUBE2_ESTATE;   // made by cube2_init_tables
     float *acc_pp = reinterpret_cast<float *>(work_ + L_.acc_pp);
     // PP first (it starts with a reduced persistent grid), the PM part beside it
     CUBE2_CHECK_HIP(hipEventRecord(ctx->ev_fork, s));
     CUBE2_CHECK_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
     int rcode = launch_pp_concurrent(ctx, pos, cell_start, n, abar, acc_pp, work_, L_, ctx->side);
     if (rcode == CUBE2_OK)
-        rcode = abar ? cube2_pm_force_backward(ctx, pos, cell_start, n, abar, out, 0, work,
-                                               work_bytes, stream)
+        rcode = abar ? cube2_pm_force_backward(ctx, pos, cell_start, n, abar, out, accumulate,
+                                               work, work_bytes, stream)
                      : cube2_pm_force(ctx, pos, cell_start, n, out, 0, work, work_bytes, stream);
-    // the caller's stream waits for the side stream on every path
-    CUBE2_CHECK_HIP(hipEventRecord(ctx->ev_join, ctx->side));
-    CUBE2_CHECK_HIP(hipStreamWaitEvent(s, ctx->ev_join, 0));
+    // the caller's stream waits for the side stream on every path; if the
+    // join cannot be recorded, the side stream is drained before returning,
+    // so that no PP kernel still writes the work buffer
+    if (hipEventRecord(ctx->ev_join, ctx->side) != hipSuccess ||
+        hipStreamWaitEvent(s, ctx->ev_join, 0) != hipSuccess) {
+        (void)hipStreamSynchronize(ctx->side);
+        return rcode ? rcode : CUBE2_EHIP;
+    }
     if (rcode) return rcode;
     return launch_add3(out, acc_pp, 3 * n, s);
 }
@@ -340,22 +376,22 @@ int cube2_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
     CHECK_WORK(n);
     if (n == 0 || (ctx->cfg.flags & CUBE2_PP_OFF))
         return cube2_pm_force(ctx, pos, cell_start, n, acc, 0, work, work_bytes, stream);
-    return force_concurrent(ctx, pos, cell_start, n, nullptr, acc, work, work_bytes, stream, work_,
-                            L_);
+    return force_concurrent(ctx, pos, cell_start, n, nullptr, acc, 0, work, work_bytes, stream,
+                            work_, L_);
 }
 
 int cube2_force_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
-                         int64_t n, const float *acc_bar, float *x_bar, void *work,
+                         int64_t n, const float *acc_bar, float *x_bar, int accumulate, void *work,
                          size_t work_bytes, cube2_stream_t stream) {
     CHECK_READY();
     if (n < 0 || n > INT32_MAX || !cell_start || (n > 0 && (!pos || !acc_bar || !x_bar)))
         return CUBE2_EINVAL;
     CHECK_WORK(n);
     if (n == 0 || (ctx->cfg.flags & CUBE2_PP_OFF))
-        return cube2_pm_force_backward(ctx, pos, cell_start, n, acc_bar, x_bar, 0, work,
+        return cube2_pm_force_backward(ctx, pos, cell_start, n, acc_bar, x_bar, accumulate, work,
                                        work_bytes, stream);
-    return force_concurrent(ctx, pos, cell_start, n, acc_bar, x_bar, work, work_bytes, stream,
-                            work_, L_);
+    return force_concurrent(ctx, pos, cell_start, n, acc_bar, x_bar, accumulate, work, work_bytes,
+                            stream, work_, L_);
 }
 
 int cube2_kick_drift(cube2_ctx *ctx, const uint16_t *pos_in, const uint32_t *cell_start_in,

@@ -207,7 +207,9 @@ __global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
 
 // ---------------------------------------------------------------------------
 // coarse level: CIC scatter of c*abar (3 components) per tile in LDS, added
-// to a 3-component coarse mesh, then the stencil transpose on that mesh
+// in the same fixed point to a 3-component coarse mesh of 64-bit integers
+// (exact, so the sum does not depend on the order of the tiles), then the
+// stencil transpose on that mesh with one conversion to FP32 per node
 // ---------------------------------------------------------------------------
 
 // coarse nodes per axis of a tile's footprint at ratio 2: 9 (CIC), 11 (TSC,
@@ -218,7 +220,7 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs,
     const float *__restrict__ abar, int n, int nt, int n_c, int hshift, float c,
-    const unsigned int *__restrict__ amax_bits, float *__restrict__ Amesh) {
+    const unsigned int *__restrict__ amax_bits, unsigned long long *__restrict__ Amesh) {
     constexpr int kCN = coarse_nodes_max<P>();
     __shared__ unsigned long long A[3][kCN * kCN * kCN];   // fixed point
     __shared__ uint32_t cst[kTileCells + 1];
@@ -228,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
     const int lo = P == 3 ? 1 : 0;                          // footprint starts lo nodes below
     const int NC = (kTileFine >> hshift) + 1 + 2 * lo;
     for (int i = tid; i < 3 * kCN * kCN * kCN; i += kBlock) (&A[0][0])[i] = 0ull;
-    const float S = fixed_scale(amax_bits, c), invS = 1.0f / S;
+    const float S = fixed_scale(amax_bits, c);
     const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
     stage_cell_starts<kBlock>(cst, cs, key0);
     __syncthreads();
@@ -300,33 +302,39 @@ __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
         const int64_t g = ((int64_t)wrapn(A0z + lz, n_c) * n_c + wrapn(A0y + ly, n_c)) * n_c +
                           wrapn(A0x + lx, n_c);
         for (int d = 0; d < 3; ++d) {
-            const long long q = (long long)A[d][i];
-            if (q != 0) atomicAdd(&Amesh[d * m + g], (float)q * invS);
+            const unsigned long long q = A[d][i];
+            if (q != 0ull) atomicAdd(&Amesh[d * m + g], q);   // two's complement: exact
         }
     }
 }
 
-__global__ void fill_f32(float *p, int64_t n) {
+__global__ void fill_u64(unsigned long long *p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0.0f;
+    if (i < n) p[i] = 0ull;
 }
 
 // phibar(m) = sum_d (2/3)(A_d(m+e_d) - A_d(m-e_d)) - (1/12)(A_d(m+2e_d) - A_d(m-2e_d))
-__global__ void divergence_kernel(const float *__restrict__ A, int n, float *__restrict__ out) {
+// on the fixed-point mesh: the differences are exact 64-bit integers, each
+// rounded once to FP32 and scaled by 1/S (S of the scatter).
+__global__ void divergence_kernel(const unsigned long long *__restrict__ A, int n, float c,
+                                  const unsigned int *__restrict__ amax_bits,
+                                  float *__restrict__ out) {
     const int64_t m3 = (int64_t)n * n * n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m3) return;
+    const float invS = 1.0f / fixed_scale(amax_bits, c);
     const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((int64_t)n * n));
     auto at = [&](int d, int xx, int yy, int zz) {
         return A[d * m3 + ((int64_t)wrapn(zz, n) * n + wrapn(yy, n)) * n + wrapn(xx, n)];
     };
-    float s = (2.0f / 3.0f) * (at(0, x + 1, y, z) - at(0, x - 1, y, z)) -
-              (1.0f / 12.0f) * (at(0, x + 2, y, z) - at(0, x - 2, y, z));
-    s += (2.0f / 3.0f) * (at(1, x, y + 1, z) - at(1, x, y - 1, z)) -
-         (1.0f / 12.0f) * (at(1, x, y + 2, z) - at(1, x, y - 2, z));
-    s += (2.0f / 3.0f) * (at(2, x, y, z + 1) - at(2, x, y, z - 1)) -
-         (1.0f / 12.0f) * (at(2, x, y, z + 2) - at(2, x, y, z - 2));
-    out[i] = s;
+    auto dif = [](unsigned long long a, unsigned long long b) { return (float)(long long)(a - b); };
+    float s = (2.0f / 3.0f) * dif(at(0, x + 1, y, z), at(0, x - 1, y, z)) -
+              (1.0f / 12.0f) * dif(at(0, x + 2, y, z), at(0, x - 2, y, z));
+    s += (2.0f / 3.0f) * dif(at(1, x, y + 1, z), at(1, x, y - 1, z)) -
+         (1.0f / 12.0f) * dif(at(1, x, y + 2, z), at(1, x, y - 2, z));
+    s += (2.0f / 3.0f) * dif(at(2, x, y, z + 1), at(2, x, y, z - 1)) -
+         (1.0f / 12.0f) * dif(at(2, x, y, z + 2), at(2, x, y, z - 2));
+    out[i] = s * invS;
 }
 
 // ---------------------------------------------------------------------------
@@ -531,14 +539,16 @@ int launch_pm_backward_p(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs
         const Level &C = ctx->lv[1];
         const int64_t m = (int64_t)C.n * C.n * C.n;
         cc = (float)(gm / ((double)C.H * C.H));
-        // the coarse 3-component Abar mesh lives in the (free) spectrum buffer
-        float *Am = reinterpret_cast<float *>(spec);
-        fill_f32<<<(unsigned)((3 * m + 255) / 256), 256, 0, s>>>(Am, 3 * m);
+        // the coarse 3-component fixed-point Abar mesh (24 B per coarse node,
+        // at most 3/8 of the fine spectrum's bytes for ratios >= 2) lives in
+        // the (free) spectrum buffer
+        unsigned long long *Am = reinterpret_cast<unsigned long long *>(spec);
+        fill_u64<<<(unsigned)((3 * m + 255) / 256), 256, 0, s>>>(Am, 3 * m);
         CUBE2_LAUNCH_CHECK();
         coarse_abar_kernel<P><<<blocks, kBlock, 0, s>>>(pos, cs, acc_bar, (int)n, nt, C.n, C.hshift,
                                                         cc, amax, Am);
         CUBE2_LAUNCH_CHECK();
-        divergence_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(Am, C.n, bc);
+        divergence_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(Am, C.n, cc, amax, bc);
         CUBE2_LAUNCH_CHECK();
         r = launch_potential(ctx, 1, bc, bc, spec, s);
         if (r) return r;

@@ -80,7 +80,7 @@ struct cube2_ctx {
     cube2::Level lv[2];
     size_t table_bytes = 0;
     unsigned char *tables = nullptr;   // device; set by cube2_init_tables
-    hipStream_t side = nullptr;        // cube2_force's PP stream (default priority), made on first use
+    hipStream_t side = nullptr;        // cube2_force's PP stream (default priority), made by cube2_init_tables
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
@@ -93,6 +93,7 @@ struct WorkLayout {
     size_t keys, vals, keys2, vals2, hist, scan_tmp, offs_tmp, red;
     size_t pp_order, pp_hist, pp_scan, acc_pp;  // cube2_force's concurrent PP: own tile queue, output
     size_t tile_order;  // 4 x (tiles) + 64 uint32: PP tile order, its sort buffers, work counter
+    size_t vel_tmax;    // velocity codec: one FP32 maximum per tile
     size_t total;
 };
 
@@ -371,6 +372,7 @@ inline unsigned persistent_grid(K kernel, int block, int ntiles) {
     return (unsigned)(g < ntiles ? g : ntiles);
 }
 int vel_bulk_side(const cube2_ctx *ctx);
+int vel_layout_check(const cube2_ctx *ctx, const WorkLayout &L);
 int launch_vel_encode(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                       const float *vel, int16_t *vq, float *v_bulk, float *v_scale,
                       unsigned char *work, const WorkLayout &L, hipStream_t s);

@@ -45,13 +45,13 @@ __device__ __forceinline__ float vel_scale(unsigned int amax_bits) {
 }
 
 // bulk cell of a particle inside its tile: IOS cell u (0..511), offsets o
-__device__ __forceinline__ int bulk_cell(int u, const uint32_t (&o)[3], int shift, int ct) {
+__host__ __device__ __forceinline__ int bulk_cell(int u, const uint32_t (&o)[3], int shift, int ct) {
     const int fx = 2 * (u & 7) + (int)(o[0] >> 15), fy = 2 * ((u >> 3) & 7) + (int)(o[1] >> 15),
               fz = 2 * (u >> 6) + (int)(o[2] >> 15);
     return ((fz >> shift) * ct + (fy >> shift)) * ct + (fx >> shift);
 }
 
-__device__ __forceinline__ int64_t bulk_index(int tx, int ty, int tz, int lc, int ct, int nb) {
+__host__ __device__ __forceinline__ int64_t bulk_index(int tx, int ty, int tz, int lc, int ct, int nb) {
     const int cx = tx * ct + lc % ct, cy = ty * ct + (lc / ct) % ct, cz = tz * ct + lc / (ct * ct);
     return ((int64_t)cz * nb + cy) * nb + cx;
 }
@@ -223,6 +223,35 @@ int bulk_shift(const cube2_ctx *ctx) { return ctx->n_levels > 1 ? ctx->lv[1].hsh
 
 int vel_bulk_side(const cube2_ctx *ctx) { return ctx->n_f >> bulk_shift(ctx); }
 
+// The codec's index arithmetic for this context, run on the host with the
+// kernels' own functions: every particle position of every IOS cell of a tile
+// (offsets at both ends of both fine cells) lands in one of the tile's
+// ct^3 <= 512 bulk cells (the LDS arrays), every bulk cell of every tile in
+// [0, nb^3) (v_bulk), and the tile maxima fit their work area.
+int vel_layout_check(const cube2_ctx *ctx, const WorkLayout &L) {
+    const int shift = bulk_shift(ctx), nb = ctx->n_f >> shift, nt = ctx->nt;
+    const int ct = kTileFine >> shift;
+    if (ct < 1 || ct * ct * ct > kTileCells || (int64_t)nt * ct != nb) return CUBE2_EUNSUPPORTED;
+    static const uint32_t offs[4] = {0u, 0x7FFFu, 0x8000u, 0xFFFFu};
+    for (int u = 0; u < kTileCells; ++u)
+        for (int a = 0; a < 64; ++a) {
+            const uint32_t o[3] = {offs[a & 3], offs[(a >> 2) & 3], offs[a >> 4]};
+            const int lc = bulk_cell(u, o, shift, ct);
+            if (lc < 0 || lc >= ct * ct * ct) return CUBE2_EUNSUPPORTED;
+        }
+    const int64_t nb3 = (int64_t)nb * nb * nb;
+    for (int tz = 0; tz < nt; ++tz)
+        for (int ty = 0; ty < nt; ++ty)
+            for (int tx = 0; tx < nt; ++tx)
+                for (int lc = 0; lc < ct * ct * ct; ++lc) {
+                    const int64_t g = bulk_index(tx, ty, tz, lc, ct, nb);
+                    if (g < 0 || g >= nb3) return CUBE2_EUNSUPPORTED;
+                }
+    const size_t ntiles = (size_t)nt * nt * nt;
+    if (L.vel_tmax + ntiles * sizeof(float) > L.total) return CUBE2_EWORKSPACE;
+    return CUBE2_OK;
+}
+
 int launch_vel_encode(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                       const float *vel, int16_t *vq, float *v_bulk, float *v_scale,
                       unsigned char *work, const WorkLayout &L, hipStream_t s) {
@@ -238,8 +267,8 @@ int launch_vel_encode(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, i
         vabsmax_kernel<<<gb, 256, 0, s>>>(vel, m3, amax);
         CUBE2_LAUNCH_CHECK();
     }
-    // per-tile maxima in the (here unused) tile-order area of the work buffer
-    float *tmax = reinterpret_cast<float *>(work + L.tile_order);
+    // per-tile maxima in their own work area (one float per tile)
+    float *tmax = reinterpret_cast<float *>(work + L.vel_tmax);
     vel_bulk_kernel<<<blocks, kBlock, 0, s>>>(pos, cs, vel, (int)n, nt, shift, nb, amax, v_bulk, tmax,
                                               status_word(ctx));
     CUBE2_LAUNCH_CHECK();

@@ -11,6 +11,8 @@ What is checked, per workload:
 * PP on a seeded sample of 4096 particles against the oracle's FP64 pair sum
   for exactly those particles (median <= 1e-4, p99 <= 1e-3, floor as in the
   small-case PP test);
+* the PP adjoint of another 4096-particle sample (Gaussian cotangents on all
+  particles) against the oracle's FP64 adjoint of those particles (same bars);
 * the FP32 force of every particle against the FP64 plain form on the GPU
   (median <= 1e-4, p99 <= 1e-3), the FP64 form itself being pinned to the
   oracle on the small cases;
@@ -81,6 +83,29 @@ def test_fullsize_pp_sample_against_oracle(big):
     acc = c.pp_force(big["pos"], big["cs"])
     got = acc[:, big["inv"][torch.from_numpy(idx).cuda()]].double().cpu().numpy()
     ref = oracle.Oracle(big["p"]).pp_accel_subset(big["xf"], idx)
+    fr = np.linalg.norm(ref, axis=0)
+    has = fr > 0
+    assert np.all(got[:, ~has] == 0)
+    floor = 1e-6 * np.median(fr[has])
+    e = np.linalg.norm(got - ref, axis=0)[has] / np.maximum(fr[has], floor)
+    med, p99 = float(np.median(e)), float(np.percentile(e, 99))
+    assert med < 1e-4 and p99 < 1e-3, (med, p99)
+
+
+def test_fullsize_pp_adjoint_sample_against_oracle(big):
+    """The PP adjoint (pair Jacobians applied to cotangent differences) of a
+    seeded sample of 4096 particles against the oracle's FP64 adjoint for
+    exactly those particles, with seeded Gaussian cotangents on all."""
+    c = big["c"]
+    n = big["xf"].shape[1]
+    idx = np.sort(np.random.default_rng(12630).choice(n, 4096, replace=False))
+    abar_in = np.random.default_rng(12631).standard_normal((3, n)).astype(np.float32)
+    print(f"[fullsize] {big['name']}: PP adjoint sample", flush=True)
+    ab_gpu = torch.from_numpy(abar_in).cuda()[:, big["perm"]].contiguous()   # IOS order
+    xb = c.pp_force_backward(big["pos"], big["cs"], ab_gpu)
+    got = xb[:, big["inv"][torch.from_numpy(idx).cuda()]].double().cpu().numpy()
+    del xb, ab_gpu
+    ref = oracle.Oracle(big["p"]).pp_adjoint_subset(big["xf"], abar_in.astype(np.float64), idx)
     fr = np.linalg.norm(ref, axis=0)
     has = fr > 0
     assert np.all(got[:, ~has] == 0)

@@ -108,10 +108,10 @@ def test_leapfrog_gradient_matches_fp64_finite_differences():
 
 
 def test_checkpoint_interval_does_not_change_the_gradient():
-    # recomputation is bit-identical; the PM adjoint's FP32 atomic sums may
-    # differ in the last bits between runs
+    # recomputation is bit-identical and every adjoint kernel is
+    # deterministic (fixed-point scatters), so the gradient is too
     sim, x, rho_t, dt = _setup(12, 32, 302)
     gx1, gv1, _ = _grad(sim, x, rho_t, dt, 6, 1)
     gx3, gv3, _ = _grad(sim, x, rho_t, dt, 6, 3)
-    assert np.linalg.norm(gx1 - gx3) <= 1e-5 * np.linalg.norm(gx1)
-    assert np.linalg.norm(gv1 - gv3) <= 1e-5 * np.linalg.norm(gv1)
+    assert np.array_equal(gx1, gx3)
+    assert np.array_equal(gv1, gv3)

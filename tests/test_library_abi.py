@@ -87,3 +87,23 @@ def test_sizes_and_state_errors(L):
 
 def test_strerror(L):
     assert L.cube2_strerror(-4) == b"deposit accumulator overflow guard tripped"
+
+
+@pytest.mark.parametrize("n_fine,ratio,flags", [
+    (16, 0, 0), (32, 0, 0), (64, 0, 0), (256, 0, 0), (1024, 0, 0),
+    (32, 2, 0), (64, 4, 0), (64, 8, 0), (512, 4, 0), (1024, 4, 0), (1024, 2, 0), (1024, 8, 0),
+    (64, 4, 4), (256, 0, 4)])
+def test_self_check_of_index_arithmetic(L, n_fine, ratio, flags):
+    """The velocity codec's bulk-cell indices of every tile (one level: cells
+    of 4 fine cells; two levels: the coarse cells), its per-tile maxima area,
+    the PM adjoint's fixed-point coarse mesh and the concurrent PP staging
+    area, checked on the host with the kernels' own index functions, for
+    particle counts from 0 to the size of the largest workload."""
+    code, h = _create(L, _cfg(n_fine=n_fine, coarse_ratio=ratio, flags=flags))
+    assert code == 0
+    try:
+        for n_max in (0, 1, 4097, (n_fine // 2) ** 3):
+            assert L.cube2_self_check(h, n_max) == 0, n_max
+        assert L.cube2_self_check(h, -1) == -1
+    finally:
+        L.cube2_destroy(h)
