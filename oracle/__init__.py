@@ -73,6 +73,7 @@ def lib():
         sig = {
             "orc_profile": (d, [d, d]),
             "orc_refforce": (d, [d, d]),
+            "orc_refforce_many": (None, [i64, p, d, p]),
             "orc_refforce_dr": (d, [d, d]),
             "orc_profile_k": (d, [d, d]),
             "orc_green_point": (d, [i, i, i, i, d, d, i, i, d]),
@@ -159,6 +160,14 @@ def profile(r, b):
 
 def refforce(r, b):
     return lib().orc_refforce(float(r), float(b))
+
+
+def refforce_many(r, b):
+    """R(r, b) of eq. (2) for an array of r (same evaluation as refforce)."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    out = np.empty_like(r)
+    lib().orc_refforce_many(r.size, _p(r), float(b), _p(out))
+    return out
 
 
 def refforce_dr(r, b):

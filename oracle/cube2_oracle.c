@@ -70,6 +70,13 @@ static xreal refforce_dr_x(xreal r, xreal b)
 }
 
 double orc_refforce(double r, double b) { return (double)refforce_x(r, b); }
+
+/* R(r_i, b) for an array of separations (the same evaluation as orc_refforce). */
+void orc_refforce_many(int64_t N, const double *r, double b, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) out[i] = (double)refforce_x(r[i], b);
+}
 double orc_refforce_dr(double r, double b) { return (double)refforce_dr_x(r, b); }
 
 /* eq. (13): Fourier transform of eq.(1).  b <= 0 stands for b = infinity,

@@ -36,3 +36,21 @@ def force_stats(a, ref):
 def ulp32(x: np.ndarray) -> np.ndarray:
     x = np.asarray(x, dtype=np.float32)
     return np.spacing(np.abs(x)).astype(np.float64)
+
+
+def exact_sum_u64(a: np.ndarray) -> int:
+    """Exact sum of a uint64 array as a Python int (split into 32-bit halves,
+    each summed in int64 without overflow for up to 2^31 entries)."""
+    a = np.asarray(a, dtype=np.uint64).ravel()
+    hi = int((a >> np.uint64(32)).astype(np.int64).sum())
+    lo = int((a & np.uint64(0xFFFFFFFF)).astype(np.int64).sum())
+    return (hi << 32) + lo
+
+
+def zero_force_ok(acc: np.ndarray, has: np.ndarray, floor: float) -> bool:
+    """Particles with no pair inside the cutoff in exact arithmetic get an
+    exactly zero oracle force; in FP32 the squared separation of a pair
+    within a rounding of the cutoff may fall just inside it, where the pair
+    law is ~1e-30 of a typical force: such particles must stay below the
+    error floor."""
+    return bool(np.all(np.abs(acc[:, ~has]) <= floor))

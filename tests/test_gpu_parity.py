@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import synthetic
-from helpers import force_stats, ios_decode, rel_err, ulp32
+from helpers import exact_sum_u64, force_stats, ios_decode, rel_err, ulp32, zero_force_ok
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -111,7 +111,7 @@ def test_deposit_bit_exact(case):
         acc_or = oracle.deposit_fx(xf, n, H)
         assert np.array_equal(_np(fx).view(np.uint64), acc_or)
         assert np.array_equal(_np(rho), oracle.density_f32(acc_or))
-        assert int(acc_or.sum(dtype=np.uint64)) == xf.shape[1] * 2 ** 45
+        assert exact_sum_u64(acc_or) == xf.shape[1] * 2 ** 45
     assert c.status() == 0
 
 
@@ -168,13 +168,13 @@ def test_pp_force_against_oracle(case):
     ref = oracle.Oracle(p).pp_accel(xf)
     fr = np.linalg.norm(ref, axis=0)
     has = fr > 0
-    assert np.all(acc[:, ~has] == 0)
     # Particles whose only neighbours sit within ~1e-3 of the cutoff have
     # PP forces near 1e-16, where the oracle's FP64 difference
     # R(r, b_pp) - R(r, b_f) has lost every digit (the GPU evaluates the
     # exactly factored tail instead); errors are measured relative to
     # max(|F|, 1e-6 median |F|).
     floor = 1e-6 * np.median(fr[has])
+    assert zero_force_ok(acc, has, floor)
     e = np.linalg.norm(acc - ref, axis=0)[has] / np.maximum(fr[has], floor)
     med, p99 = float(np.median(e)), float(np.percentile(e, 99))
     assert med < MED and p99 < P99, (med, p99)
@@ -203,8 +203,8 @@ def test_pp_force_against_exact(name):
     acc[:, _np(perm).astype(np.int64)] = _np(c.pp_force(pos, cs))
     fr = np.linalg.norm(ref, axis=0)
     has = fr > 0
-    assert np.all(acc[:, ~has] == 0)
     floor = 1e-6 * np.median(fr[has])
+    assert zero_force_ok(acc, has, floor)
     e = np.linalg.norm(acc - ref, axis=0)[has] / np.maximum(fr[has], floor)
     med, p99 = float(np.median(e)), float(np.percentile(e, 99))
     assert med < MED and p99 < P99, (med, p99)

@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 import synthetic
-from helpers import force_stats, ulp32
+from helpers import exact_sum_u64, force_stats, ulp32
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -64,7 +64,7 @@ def test_tsc_deposit_bit_exact(case):
         acc_or = oracle.deposit_fx(xf, n, H, p=3)
         assert np.array_equal(_np(fx).view(np.uint64), acc_or)
         assert np.array_equal(_np(rho), oracle.density_f32(acc_or, p=3))
-        assert int(acc_or.sum(dtype=np.uint64)) == xf.shape[1] * 2 ** 48
+        assert exact_sum_u64(acc_or) == xf.shape[1] * 2 ** 48
     assert c.status() == 0
 
 
