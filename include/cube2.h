@@ -213,6 +213,49 @@ int cube2_pm_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_sta
                    float *acc, int accumulate, void *work, size_t work_bytes,
                    cube2_stream_t stream);
 
+/* The PM force of one level alone (section 2.1.2 steps 1-4 on that level):
+ * level 0 = the fine level (eq. 4b, truncated at b_coarse when the context
+ * has two levels), 1 = the coarse level (eq. 4a).  acc (device, 3*n FP32);
+ * accumulate != 0 adds.  cube2_pm_force is the sum over the levels. */
+int cube2_pm_level_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                         int64_t n, int level, float *acc, int accumulate, void *work,
+                         size_t work_bytes, cube2_stream_t stream);
+
+/* Tile+buffer mode (section 2.2.3, PM2 paragraph): the fine level and PP of
+ * a tile are computed on a local periodic box holding the tile and a buffer
+ * zone around it; the fine level's force is truncated at b_coarse, so a
+ * buffer of at least b_coarse + 3 fine cells keeps every particle that acts
+ * on the tile's own particles and puts the local box's periodic images
+ * beyond the truncation.  The coarse level stays global
+ * (cube2_pm_level_force, level 1).
+ *
+ * cube2_tile_gather: the particles of the global context's box of fine
+ * cells [origin - buffer, origin + tile + buffer)^3 (periodic; origin (host,
+ * 3 ints, fine cells), tile and buffer even; n_local = tile + 2 buffer a
+ * power of two in [32, 512], at most n_fine) are written as positions of the
+ * local box in its box units, x_local (device, (3, m) SoA at the front of a
+ * buffer of 3*m_max floats; exact in FP32), with their indices in the global
+ * particle order, idx (device, m int32).  The order is fixed (region cells
+ * z-major, x fastest, then the particle order within a cell), so the call is
+ * deterministic.  *m (host) receives the count; the call synchronises the
+ * stream to read it and returns CUBE2_EWORKSPACE, writing nothing, when it
+ * exceeds m_max.  Uses the fine-mesh area of `work`.
+ *
+ * cube2_tile_scatter_add: for the m gathered particles after a local
+ * cube2_pack (perm_local, device, m int32: gathered slot of local particle
+ * i) and a local force acc_local (device, (3, m) in the local particle
+ * order), adds acc_local to acc (device, (3, n), global order) at idx for
+ * the particles inside the tile proper (local coordinates in [buffer,
+ * buffer + tile) fine cells on every axis).  Each particle lies in exactly
+ * one tile of a tiling of the box, so the adds of one tile do not collide. */
+int cube2_tile_gather(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                      const int32_t origin[3], int32_t tile, int32_t buffer, float *x_local,
+                      int32_t *idx, int64_t m_max, int64_t *m, void *work, size_t work_bytes,
+                      cube2_stream_t stream);
+int cube2_tile_scatter_add(int64_t m, const int32_t *perm_local, const float *x_local,
+                           const int32_t *idx, int32_t tile, int32_t buffer,
+                           const float *acc_local, float *acc, int64_t n, cube2_stream_t stream);
+
 /* PP force (eq. 4d): a_i += G m_p sum_{j != i, 0 < r < b_fine}
  * [R(r,b_pp) - R(r,b_fine)] (x_j - x_i)/r with R of eq. (2) and the exact
  * minimum-image integer separation, in FP32 with compensated summation.

@@ -342,9 +342,10 @@ def interp(xf: np.ndarray, E: np.ndarray, H: float, quant: bool = True, p: int =
 class Oracle:
     """The force computation for one parameter set, with cached G tables."""
 
-    def __init__(self, params: Params, quant: bool = True):
+    def __init__(self, params: Params, quant: bool = True, workers: int = 1):
         self.p = params
         self.quant = quant
+        self.workers = workers       # threads of the library FFT (see potential)
         self._G = {}
 
     def green(self, level: int) -> np.ndarray:
@@ -360,7 +361,7 @@ class Oracle:
         """(rho, phi, E) of one level, unit particle mass."""
         H, n, _, _ = self.p.levels()[level]
         rho = deposit(xf, n, H, self.quant, self.p.assign)
-        phi = potential(rho, self.green(level))
+        phi = potential(rho, self.green(level), self.workers)
         return rho, phi, fd_force(phi)
 
     def pm_level_accel(self, xf, level):
@@ -473,6 +474,38 @@ class Oracle:
         dep_pos(xf.shape[1], _p(xf), int(n), float(H), int(self.quant),
                 _p(np.ascontiguousarray(rhobar, dtype=np.float64)), _p(xbar))
         return xbar
+
+
+# ---------------------------------------------------------------------------
+# Tile+buffer mode (section 2.2.3, PM2 paragraph)
+# ---------------------------------------------------------------------------
+
+def tile_local_accel(params: Params, xf: np.ndarray, origin, tile: int, buffer: int,
+                     workers: int = 1):
+    """Fine-level + PP acceleration of the particles of one tile computed on
+    the local periodic box of the tile and a buffer zone around it.
+
+    The box of fine cells [origin - buffer, origin + tile + buffer) (periodic
+    in the global box) holds the local particles; in their local coordinates
+    (shifted by origin - buffer) the finer level of the two-level split, whose
+    target force R(r, b_fine) - R(r, b_coarse) is truncated at b_coarse, and
+    the PP sum are evaluated with periodic boundaries on the local box of
+    tile + 2 buffer cells.  Returns (indices of the tile's own particles in
+    xf, their acceleration (3, k)); the coarse level is the global one."""
+    xf = np.asarray(xf, dtype=np.float64)
+    L = float(params.n_fine)
+    o = np.asarray(origin, dtype=np.float64).reshape(3, 1)
+    rel = np.mod(xf - (o - buffer), L)
+    n_local = tile + 2 * buffer
+    inb = np.all(rel < n_local, axis=0)
+    own = np.all((rel >= buffer) & (rel < buffer + tile), axis=0)
+    xl = np.ascontiguousarray(rel[:, inb])
+    pl = Params(n_fine=n_local, coarse_ratio=params.coarse_ratio, b_coarse=params.b_coarse,
+                b_fine=params.b_fine, b_pp=params.b_pp, m_p=params.m_p, G_N=params.G_N,
+                alias_nmax=params.alias_nmax, assign=params.assign)
+    ol = Oracle(pl, workers=workers)
+    a = ol.pm_level_accel(xl, 1) + ol.pp_accel(xl)
+    return np.nonzero(own)[0], a[:, own[inb]]
 
 
 # ---------------------------------------------------------------------------

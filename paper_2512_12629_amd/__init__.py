@@ -72,6 +72,10 @@ def _load():
         "cube2_interp": [P, P, P, I64, P, P, P, I, P],
         "cube2_pm_force": [P, P, P, I64, P, I, P, S, P],
         "cube2_pp_force": [P, P, P, I64, P, I, P, S, P],
+        "cube2_pm_level_force": [P, P, P, I64, I, P, I, P, S, P],
+        "cube2_tile_gather": [P, P, P, I64, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                              ctypes.c_int32, P, P, I64, ctypes.POINTER(I64), P, S, P],
+        "cube2_tile_scatter_add": [I64, P, P, P, ctypes.c_int32, ctypes.c_int32, P, P, I64, P],
         "cube2_force": [P, P, P, I64, P, P, S, P],
         "cube2_force_backward": [P, P, P, I64, P, P, I, P, S, P],
         "cube2_kick_drift": [P, P, P, P, P, I64, D, D, P, P, P, P, P, S, P],
@@ -194,6 +198,34 @@ def cube2_pm_force(ctx, pos, cell_start, acc, work, accumulate=False, stream=Non
     _check(_lib.cube2_pm_force(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], _ptr(acc),
                                int(bool(accumulate)), _ptr(work), work.numel(), _stream(stream)),
            "cube2_pm_force")
+
+
+def cube2_pm_level_force(ctx, pos, cell_start, level, acc, work, accumulate=False, stream=None):
+    _check(_lib.cube2_pm_level_force(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], int(level),
+                                     _ptr(acc), int(bool(accumulate)), _ptr(work), work.numel(),
+                                     _stream(stream)), "cube2_pm_level_force")
+
+
+def cube2_tile_gather(ctx, pos, cell_start, origin, tile, buffer, x_local, idx, work,
+                      stream=None):
+    """Returns the number m of particles of the tile and its buffer; x_local
+    holds (3, m) at its front and idx m entries, unless m > idx.numel(), when
+    nothing is written (the caller grows its buffers and calls again)."""
+    o = (ctypes.c_int32 * 3)(*[int(v) for v in origin])
+    m = ctypes.c_int64()
+    code = _lib.cube2_tile_gather(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], o, int(tile),
+                                  int(buffer), _ptr(x_local), _ptr(idx), idx.numel(),
+                                  ctypes.byref(m), _ptr(work), work.numel(), _stream(stream))
+    if code != -3:
+        _check(code, "cube2_tile_gather")
+    return m.value
+
+
+def cube2_tile_scatter_add(perm_local, x_local, idx, tile, buffer, acc_local, acc, stream=None):
+    m = perm_local.shape[0]
+    _check(_lib.cube2_tile_scatter_add(m, _ptr(perm_local), _ptr(x_local), _ptr(idx), int(tile),
+                                       int(buffer), _ptr(acc_local), _ptr(acc), acc.shape[1],
+                                       _stream(stream)), "cube2_tile_scatter_add")
 
 
 def cube2_force(ctx, pos, cell_start, acc, work, stream=None):
@@ -442,6 +474,13 @@ class Cube2:
         cube2_force(self.ctx, pos, cs, acc, self.work)
         return acc
 
+    def pm_level_force(self, pos, cs, level, acc=None):
+        accumulate = acc is not None
+        if acc is None:
+            acc = torch.empty((3, pos.shape[1]), dtype=torch.float32, device=self.device)
+        cube2_pm_level_force(self.ctx, pos, cs, level, acc, self.work, accumulate)
+        return acc
+
     def kick_drift(self, pos, cs, vel, acc, kick, drift):
         n = pos.shape[1]
         pos2 = torch.empty_like(pos)
@@ -534,3 +573,67 @@ class Cube2:
         cube2_kick_drift_backward(self.ctx, perm, xbar_out.contiguous(), vbar_out.contiguous(),
                                   kick, drift, xb, vb, ab)
         return xb, vb, ab
+
+
+class Cube2Tiled:
+    """Tile+buffer force of a two-level configuration (section 2.2.3, PM2
+    paragraph): the coarse level on the whole periodic box, the fine level and
+    PP of each tile on a local periodic box of the tile plus a buffer, the
+    results of the tile's own particles added in.  Every step is a C-ABI call;
+    this class only owns the two contexts and loops over the tiles.
+
+    tile, buffer: fine cells, even; tile divides n_fine and tile + 2 buffer is
+    a power of two in [32, 512].  The buffer should be at least b_coarse + 3
+    fine cells (the truncation plus the assignment and stencil reach)."""
+
+    def __init__(self, cfg: Config, tile: int, buffer: int, n_max: int, device="cuda"):
+        import dataclasses
+        if not cfg.coarse_ratio:
+            raise ValueError("the tile+buffer mode splits a two-level configuration")
+        if cfg.n_fine % tile:
+            raise ValueError("tiles must tile the box")
+        self.tile, self.buffer = int(tile), int(buffer)
+        self.n_local = self.tile + 2 * self.buffer
+        self.g = Cube2(cfg, n_max, device)
+        self.cfg_local = dataclasses.replace(cfg, n_fine=self.n_local)
+        self.device = self.g.device
+        self.local = None
+        self.m_cap = 0
+
+    def _local(self, m):
+        if self.local is None or m > self.m_cap:
+            self.m_cap = max(m, 1024)
+            self.local = Cube2(self.cfg_local, self.m_cap, self.device)
+            self.x_buf = torch.empty(3 * self.m_cap, dtype=torch.float32, device=self.device)
+            self.i_buf = torch.empty(self.m_cap, dtype=torch.int32, device=self.device)
+        return self.local
+
+    def origins(self):
+        k = self.g.cfg.n_fine // self.tile
+        return [(x * self.tile, y * self.tile, z * self.tile)
+                for z in range(k) for y in range(k) for x in range(k)]
+
+    def tile_force(self, pos, cs, origin, acc):
+        """Adds the fine-level + PP force of the particles of one tile to acc."""
+        loc = self._local(1024)
+        m = cube2_tile_gather(self.g.ctx, pos, cs, origin, self.tile, self.buffer, self.x_buf,
+                              self.i_buf, self.g.work)
+        if m > self.m_cap:
+            loc = self._local(m)
+            m = cube2_tile_gather(self.g.ctx, pos, cs, origin, self.tile, self.buffer, self.x_buf,
+                                  self.i_buf, self.g.work)
+        if m == 0:
+            return
+        xl = self.x_buf[:3 * m].view(3, m)
+        pos_l, cs_l, perm_l = loc.pack(xl)
+        a_l = loc.pm_level_force(pos_l, cs_l, 0)
+        loc.pp_force(pos_l, cs_l, a_l)
+        cube2_tile_scatter_add(perm_l, xl, self.i_buf[:m], self.tile, self.buffer, a_l, acc)
+
+    def force(self, pos, cs, origins=None):
+        """Coarse level for every particle plus, for the tiles at `origins`
+        (default: all), the fine level and PP of their own particles."""
+        acc = self.g.pm_level_force(pos, cs, 1)
+        for o in (self.origins() if origins is None else origins):
+            self.tile_force(pos, cs, o, acc)
+        return acc

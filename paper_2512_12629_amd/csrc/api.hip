@@ -320,6 +320,62 @@ int cube2_pm_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_sta
     return launch_interp(ctx, pos, cell_start, n, rf, rc, acc, accumulate, s);
 }
 
+int cube2_pm_level_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                         int64_t n, int level, float *acc, int accumulate, void *work,
+                         size_t work_bytes, cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start || (n > 0 && (!pos || !acc))) return CUBE2_EINVAL;
+    if (level < 0 || level >= ctx->n_levels) return CUBE2_EINVAL;
+    CHECK_WORK(n);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    float *m = reinterpret_cast<float *>(work_ + (level == 0 ? L_.real_f : L_.real_c));
+    float2 *spec = reinterpret_cast<float2 *>(work_ + L_.spec);
+    int rcode = level == 0
+                    ? launch_deposit(ctx, pos, cell_start, n, m, nullptr, nullptr, nullptr, work_, L_, s)
+                    : launch_deposit(ctx, pos, cell_start, n, nullptr, nullptr, m, nullptr, work_, L_, s);
+    if (rcode) return rcode;
+    rcode = launch_potential(ctx, level, m, m, spec, s);
+    if (rcode) return rcode;
+    if (n == 0) return CUBE2_OK;
+    return launch_interp_levels(ctx, pos, cell_start, n, level == 0 ? m : nullptr,
+                                level == 1 ? m : nullptr, acc, accumulate, level == 0 ? 1 : 2, s);
+}
+
+int cube2_tile_gather(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
+                      const int32_t origin[3], int32_t tile, int32_t buffer, float *x_local,
+                      int32_t *idx, int64_t m_max, int64_t *m, void *work, size_t work_bytes,
+                      cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start || !origin || !m || m_max < 0) return CUBE2_EINVAL;
+    if (n > 0 && !pos) return CUBE2_EINVAL;
+    if (m_max > 0 && (!x_local || !idx)) return CUBE2_EINVAL;
+    const int64_t n_local = (int64_t)tile + 2 * (int64_t)buffer;
+    if (tile < 2 || buffer < 0 || (tile & 1) || (buffer & 1)) return CUBE2_EINVAL;
+    if (n_local < 32 || n_local > 512 || (n_local & (n_local - 1)) || n_local > ctx->n_f)
+        return CUBE2_EUNSUPPORTED;
+    int r0[3];
+    for (int d = 0; d < 3; ++d) {
+        if (origin[d] < 0 || origin[d] >= ctx->n_f || (origin[d] & 1)) return CUBE2_EINVAL;
+        r0[d] = (int)(((origin[d] - buffer) / 2 % ctx->n_ios + ctx->n_ios) % ctx->n_ios);
+    }
+    CHECK_WORK(n);
+    *m = 0;
+    return launch_tile_gather(ctx, pos, cell_start, n, r0, (int)(n_local / 2), (int)n_local,
+                              x_local, idx, m_max, m, work_, L_,
+                              reinterpret_cast<hipStream_t>(stream));
+}
+
+int cube2_tile_scatter_add(int64_t m, const int32_t *perm_local, const float *x_local,
+                           const int32_t *idx, int32_t tile, int32_t buffer,
+                           const float *acc_local, float *acc, int64_t n, cube2_stream_t stream) {
+    if (m < 0 || n < 0 || m > INT32_MAX || n > INT32_MAX) return CUBE2_EINVAL;
+    if (m > 0 && (!perm_local || !x_local || !idx || !acc_local || !acc)) return CUBE2_EINVAL;
+    if (tile < 2 || buffer < 0) return CUBE2_EINVAL;
+    return launch_tile_scatter_add(m, perm_local, x_local, idx, buffer, buffer + tile,
+                                   tile + 2 * buffer, acc_local, acc, n,
+                                   reinterpret_cast<hipStream_t>(stream));
+}
+
 int cube2_pp_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
                    float *acc, int accumulate, void *work, size_t work_bytes,
                    cube2_stream_t stream) {

@@ -350,6 +350,20 @@ int launch_order_tiles(cube2_ctx *ctx, const uint32_t *cs, unsigned char *work,
                        const WorkLayout &L, hipStream_t s);
 int launch_reset_tile_queue(cube2_ctx *ctx, unsigned char *work, const WorkLayout &L,
                             hipStream_t s);
+// Device-wide exclusive scan of m uint32 (in may equal out); tmp: the
+// scan_tmp work region.
+int launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t m, uint32_t *tmp,
+                          hipStream_t s);
+int launch_interp_levels(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                         const float *phi_f, const float *phi_c, float *acc, int accumulate,
+                         int levels, hipStream_t s);
+int launch_tile_gather(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                       const int (&r0)[3], int R, int n_local, float *x_local, int32_t *idx,
+                       int64_t m_max, int64_t *m_out, unsigned char *work, const WorkLayout &L,
+                       hipStream_t s);
+int launch_tile_scatter_add(int64_t m, const int32_t *perm_local, const float *x_local,
+                            const int32_t *idx, int lo, int hi, int n_local,
+                            const float *acc_local, float *acc, int64_t n, hipStream_t s);
 
 // The tile order and work counter written by launch_order_tiles.
 inline const uint32_t *tile_order_ptr(unsigned char *work, const WorkLayout &L) {

@@ -92,14 +92,15 @@ __device__ __forceinline__ void gather3(const T *P, int S, int nx, int ny, int n
 }
 
 // At least two waves per SIMD: left alone, the compiler gives the two-level
-// TSC gather all 256 VGPRs and one wave per SIMD.
-template <bool TWO, int P, typename T>
+// TSC gather all 256 VGPRs and one wave per SIMD.  FINE = false gathers the
+// coarse level only (the tile+buffer mode computes the fine level per tile).
+template <bool TWO, int P, typename T, bool FINE = true>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void interp_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs, int n, int n_f, int nt,
     const T *__restrict__ phi_f, const T *__restrict__ phi_c, int n_c, int hshift, T scale_f,
     T scale_c, T *__restrict__ acc, int accumulate) {
     constexpr int FS = InterpGeo<P>::FS, HLO = InterpGeo<P>::HLO, CSM = InterpGeo<P>::CSMAX;
-    __shared__ T pf[FS * FS * FS];
+    __shared__ T pf[FINE ? FS * FS * FS : 1];
     __shared__ T pc[TWO ? CSM * CSM * CSM : 1];
     __shared__ uint32_t cst[kTileCells + 1];
 
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
     stage_cell_starts<kBlock>(cst, cs, key0);
     const int ax0 = tx * kTileFine, ay0 = ty * kTileFine, az0 = tz * kTileFine;
-    stage_block<FS, kBlock>(pf, phi_f, n_f, ax0 - HLO, ay0 - HLO, az0 - HLO);
+    if (FINE) stage_block<FS, kBlock>(pf, phi_f, n_f, ax0 - HLO, ay0 - HLO, az0 - HLO);
     const int CS = (kTileFine >> hshift) + FS - kTileFine;
     if (TWO) {
         const int cx0 = (ax0 >> hshift) - HLO, cy0 = (ay0 >> hshift) - HLO,
@@ -162,10 +163,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                         jc[d] = (int)(y >> kFracBits) + tsc_axis<T>((int)(y & 0x7FFFu), wc[d]) + HLO;
                     }
                 }
-                gather3(pf, FS, jf[0], jf[1], jf[2], wf[0], wf[1], wf[2], a[0], a[1], a[2]);
-                a[0] *= scale_f;
-                a[1] *= scale_f;
-                a[2] *= scale_f;
+                a[0] = a[1] = a[2] = T(0);
+                if (FINE) {
+                    gather3(pf, FS, jf[0], jf[1], jf[2], wf[0], wf[1], wf[2], a[0], a[1], a[2]);
+                    a[0] *= scale_f;
+                    a[1] *= scale_f;
+                    a[2] *= scale_f;
+                }
                 if (TWO) {
                     T c[3];
                     gather3(pc, CS, jc[0], jc[1], jc[2], wc[0], wc[1], wc[2], c[0], c[1], c[2]);
@@ -190,10 +194,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                         wc[d][0] = (T)(32768 - fc) * inv;
                     }
                 }
-                gather(pf, FS, jf[0], jf[1], jf[2], wf[0], wf[1], wf[2], a[0], a[1], a[2]);
-                a[0] *= scale_f;
-                a[1] *= scale_f;
-                a[2] *= scale_f;
+                a[0] = a[1] = a[2] = T(0);
+                if (FINE) {
+                    gather(pf, FS, jf[0], jf[1], jf[2], wf[0], wf[1], wf[2], a[0], a[1], a[2]);
+                    a[0] *= scale_f;
+                    a[1] *= scale_f;
+                    a[2] *= scale_f;
+                }
                 if (TWO) {
                     T c[3];
                     gather(pc, CS, jc[0], jc[1], jc[2], wc[0], wc[1], wc[2], c[0], c[1], c[2]);
@@ -213,12 +220,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 
 }  // namespace
 
+// levels: bit 0 the fine level, bit 1 the coarse level (if the context has one)
 template <int P, typename T>
 void launch_interp_kernel(cube2_ctx *ctx, unsigned blocks, const uint16_t *pos, const uint32_t *cs,
                           int64_t n, const T *phi_f, const T *phi_c, double gm, T *acc,
-                          int accumulate, hipStream_t s) {
+                          int accumulate, int levels, hipStream_t s) {
     const int nt = ctx->nt;
-    if (ctx->n_levels > 1) {
+    const bool fine = (levels & 1) != 0, coarse = ctx->n_levels > 1 && (levels & 2) != 0;
+    if (coarse && !fine) {
+        const Level &C = ctx->lv[1];
+        interp_kernel<true, P, T, false><<<blocks, kBlock, 0, s>>>(
+            pos, cs, (int)n, ctx->n_f, nt, nullptr, phi_c, C.n, C.hshift, T(0),
+            (T)(gm / ((double)C.H * C.H)), acc, accumulate);
+    } else if (coarse) {
         const Level &C = ctx->lv[1];
         interp_kernel<true, P, T><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, phi_f,
                                                             phi_c, C.n, C.hshift, (T)gm,
@@ -233,14 +247,17 @@ void launch_interp_kernel(cube2_ctx *ctx, unsigned blocks, const uint16_t *pos, 
 
 template <typename T>
 int interp_levels(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
-                  const T *phi_f, const T *phi_c, T *acc, int accumulate, hipStream_t s) {
+                  const T *phi_f, const T *phi_c, T *acc, int accumulate, int levels,
+                  hipStream_t s) {
     const int nt = ctx->nt;
     const unsigned blocks = (unsigned)(nt * nt * nt);
     const double gm = ctx->cfg.g_newton * ctx->cfg.m_p;
     if (ctx->tsc)
-        launch_interp_kernel<3, T>(ctx, blocks, pos, cs, n, phi_f, phi_c, gm, acc, accumulate, s);
+        launch_interp_kernel<3, T>(ctx, blocks, pos, cs, n, phi_f, phi_c, gm, acc, accumulate,
+                                   levels, s);
     else
-        launch_interp_kernel<2, T>(ctx, blocks, pos, cs, n, phi_f, phi_c, gm, acc, accumulate, s);
+        launch_interp_kernel<2, T>(ctx, blocks, pos, cs, n, phi_f, phi_c, gm, acc, accumulate,
+                                   levels, s);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }
@@ -248,13 +265,19 @@ int interp_levels(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64
 int launch_interp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                   const float *phi_f, const float *phi_c, float *acc, int accumulate,
                   hipStream_t s) {
-    return interp_levels<float>(ctx, pos, cs, n, phi_f, phi_c, acc, accumulate, s);
+    return interp_levels<float>(ctx, pos, cs, n, phi_f, phi_c, acc, accumulate, 3, s);
+}
+
+int launch_interp_levels(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
+                         const float *phi_f, const float *phi_c, float *acc, int accumulate,
+                         int levels, hipStream_t s) {
+    return interp_levels<float>(ctx, pos, cs, n, phi_f, phi_c, acc, accumulate, levels, s);
 }
 
 int launch_interp64(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                     const double *phi_f, const double *phi_c, double *acc, int accumulate,
                     hipStream_t s) {
-    return interp_levels<double>(ctx, pos, cs, n, phi_f, phi_c, acc, accumulate, s);
+    return interp_levels<double>(ctx, pos, cs, n, phi_f, phi_c, acc, accumulate, 3, s);
 }
 
 }  // namespace cube2

@@ -166,3 +166,15 @@ def make(name: str, seed: int | None = None, n_p: int | None = None) -> np.ndarr
     n_fine = w["n_fine"] * (w["n_p"] / WORKLOADS[name]["n_p"])
     return clustered(w["n_p"], w["rms"], w["n_spheres"], w["per_sphere"],
                      0.5 / n_fine, seed)
+
+
+def unit_directions(shape, count: int, seed: int) -> np.ndarray:
+    """`count` seeded directions of the given shape, each of unit Euclidean
+    norm (Gaussian, normalised): perturbation directions for directional
+    finite differences."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((count,) + tuple(shape))
+    for k in range(count):
+        v = rng.standard_normal(shape)
+        out[k] = v / np.linalg.norm(v)
+    return out
