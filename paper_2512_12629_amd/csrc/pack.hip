@@ -237,16 +237,16 @@ __global__ void tile_keys_kernel(const uint32_t *__restrict__ cs, int nt, uint32
 
 }  // namespace
 
-// Work order of the persistent per-tile kernels: the tiles sorted (stably,
-// one 8-bit radix pass) by their particle count in units of 1024, descending,
-// so that the heaviest tiles start first and the light ones keep the
-// XCD-slab order.  The tile indices land in the first ntiles words of the
-// tile_order region; the work counter (tile_queue_ptr) is reset to zero.
 int launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t m, uint32_t *tmp,
                           hipStream_t s) {
     return exclusive_scan(in, out, m, tmp, s);
 }
 
+// Work order of the persistent per-tile kernels: the tiles sorted (stably,
+// one 8-bit radix pass) by their particle count in units of 1024, descending,
+// so that the heaviest tiles start first and the light ones keep the
+// XCD-slab order.  The tile indices land in the first ntiles words of the
+// tile_order region; the work counter (tile_queue_ptr) is reset to zero.
 int launch_order_tiles(cube2_ctx *ctx, const uint32_t *cs, unsigned char *work,
                        const WorkLayout &L, hipStream_t s) {
     const int nt = ctx->nt;
