@@ -264,6 +264,19 @@ int cube2_pp_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_sta
                    float *acc, int accumulate, void *work, size_t work_bytes,
                    cube2_stream_t stream);
 
+/* cube2_pp_force without a work buffer, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the PP kernel's scratch (tile order, sort histogram and scan
+ * temporaries, work counter: 4.3 MB at n_fine = 1024) lives in a fixed 5 MiB
+ * device array of the library, one copy per device, held until the process
+ * ends.  Same arguments and result as cube2_pp_force (bit for bit); the call
+ * allocates nothing.  Every call on one device shares that array, so calls
+ * that overlap on one device (two streams, two threads) race; the work
+ * counter is cleared by a kernel at the start of each call.  CUBE2_EWORKSPACE
+ * if the scratch does not fit the array (no supported n_fine). */
+int cube2_pp_force_noalloc(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                           int64_t n, float *acc, int accumulate, cube2_stream_t stream);
+
 /* The total force of eq. (4): the PM force of all levels plus the PP force,
  * acc = PM + PP (device, 3*n FP32, overwritten), equal bit for bit to
  * cube2_pm_force followed by cube2_pp_force with accumulate.  The PP part

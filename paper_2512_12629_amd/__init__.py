@@ -73,6 +73,7 @@ def _load():
         "cube2_pm_force": [P, P, P, I64, P, I, P, S, P],
         "cube2_pp_force": [P, P, P, I64, P, I, P, S, P],
         "cube2_pm_level_force": [P, P, P, I64, I, P, I, P, S, P],
+        "cube2_pp_force_noalloc": [P, P, P, I64, P, I, P],
         "cube2_tile_gather": [P, P, P, I64, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                               ctypes.c_int32, P, P, I64, ctypes.POINTER(I64), P, S, P],
         "cube2_tile_scatter_add": [I64, P, P, P, ctypes.c_int32, ctypes.c_int32, P, P, I64, P],
@@ -245,6 +246,12 @@ def cube2_pp_force(ctx, pos, cell_start, acc, work, accumulate=False, stream=Non
     _check(_lib.cube2_pp_force(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], _ptr(acc),
                                int(bool(accumulate)), _ptr(work), work.numel(), _stream(stream)),
            "cube2_pp_force")
+
+
+def cube2_pp_force_noalloc(ctx, pos, cell_start, acc, accumulate=False, stream=None):
+    _check(_lib.cube2_pp_force_noalloc(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], _ptr(acc),
+                                       int(bool(accumulate)), _stream(stream)),
+           "cube2_pp_force_noalloc")
 
 
 def cube2_kick_drift(ctx, pos_in, cs_in, vel_in, acc, kick, drift, pos_out, cs_out, vel_out,

@@ -223,6 +223,9 @@ int cube2_init_tables(cube2_ctx *ctx, void *tables, size_t table_bytes, cube2_st
         ctx->ev_join = join;
         ctx->side = side;
     }
+    // the no-allocation PP entry point's scratch address on this device
+    const int sr = noalloc_setup(nullptr);
+    if (sr) return sr;
     ctx->tables = static_cast<unsigned char *>(tables);
     CUBE2_CHECK_HIP(hipMemsetAsync(ctx->tables, 0, 256, s));
     CUBE2_CHECK_HIP(hipMemcpyAsync(ctx->tables + ctx->pp_aoff, ctx->pp_arows.data(),

@@ -399,6 +399,9 @@ int launch_pp_concurrent(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs
 int launch_add3(float *acc, const float *acc_pp, int64_t m, hipStream_t s);
 int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, float *acc,
               int accumulate, unsigned char *work, const WorkLayout &L, hipStream_t s);
+// Address of the no-allocation entry point's scratch array on the current
+// device (taken once per device); out may be NULL.
+int noalloc_setup(unsigned char **out);
 int build_pair_table(cube2_ctx *ctx);
 int launch_kick_drift(cube2_ctx *ctx, const uint16_t *pos_in, const uint32_t *cs_in,
                       const float *vel_in, const float *acc, int64_t n, double kick,
