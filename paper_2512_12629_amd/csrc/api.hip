@@ -31,8 +31,6 @@ size_t table_layout(cube2_ctx *c) {
         L.gz_off = off;
         off = align_up(off + h * (size_t)pitch_of(L.n) * h * sizeof(float), 256);
     }
-    c->pp_aoff = off;
-    off = align_up(off + (size_t)kARows * kARowFloats * sizeof(float), 256);
     c->pp_soff = off;
     off = align_up(off + (size_t)kSRows * 4 * sizeof(float), 256);
     if (c->fp64) {
@@ -228,8 +226,6 @@ int cube2_init_tables(cube2_ctx *ctx, void *tables, size_t table_bytes, cube2_st
     if (sr) return sr;
     ctx->tables = static_cast<unsigned char *>(tables);
     CUBE2_CHECK_HIP(hipMemsetAsync(ctx->tables, 0, 256, s));
-    CUBE2_CHECK_HIP(hipMemcpyAsync(ctx->tables + ctx->pp_aoff, ctx->pp_arows.data(),
-                                   ctx->pp_arows.size() * sizeof(float), hipMemcpyHostToDevice, s));
     CUBE2_CHECK_HIP(hipMemcpyAsync(ctx->tables + ctx->pp_soff, ctx->pp_srows.data(),
                                    ctx->pp_srows.size() * sizeof(float), hipMemcpyHostToDevice, s));
     if (ctx->fp64)

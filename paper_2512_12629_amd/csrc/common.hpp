@@ -51,12 +51,6 @@ constexpr int kPairRow = 12;       // floats per interval: 9 coefficients, y map
 constexpr int kSMantBits = 4;
 constexpr int kSRow0 = (127 - 31) << kSMantBits;
 constexpr int kSRows = (7 + 31) << kSMantBits;  // 608
-// FP32 adjoint pair law (g and dg/ds), indexed the same way with 1/8 octave
-// pieces: one row of 6 quintic coefficients, padded to 8 floats.
-constexpr int kAMantBits = 3;
-constexpr int kARow0 = (127 - 31) << kAMantBits;
-constexpr int kARows = (7 + 31) << kAMantBits;  // 304
-constexpr int kARowFloats = 8;
 }  // namespace cube2
 
 struct cube2_ctx {
@@ -65,8 +59,6 @@ struct cube2_ctx {
     float pp_kinv = 0.f;               // K / b_f
     float pp_negc = 0.f;               // -1/b_f^2, rounded away from zero (FP32 pair law)
     int pp_halo = 1;                   // PP neighbour reach in IOS cells: 1 (b_f <= 2), 2 (b_f <= 4)
-    std::vector<float> pp_arows;       // kARows * kARowFloats: the FP32 adjoint pair law by s
-    size_t pp_aoff = 0;                // byte offset of pp_arows in `tables`
     std::vector<float> pp_srows;       // kSRows * 4 floats: the FP32 forward pair law by s = r^2
     size_t pp_soff = 0;                // byte offset of pp_srows in `tables`
     std::vector<double> pp_rows64;     // the same rows in FP64

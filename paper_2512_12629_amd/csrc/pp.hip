@@ -86,10 +86,9 @@ template <bool ADJ, int H> struct PPGeo {
 
 namespace {
 
-// The pair-law tables in LDS, declared at namespace scope so that every
-// access is a 32-bit LDS address (each kernel gets its own copy of the one it
-// uses): the adjoint's and the forward's, both indexed by s = r^2.
-__shared__ float4 pair_arows[kARows * kARowFloats / 4];
+// The pair-law table in LDS, declared at namespace scope so that every
+// access is a 32-bit LDS address, indexed by s = r^2 (the forward and the
+// adjoint kernel both read it).
 __shared__ float4 pair_srows[kSRows];
 
 __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
@@ -121,39 +120,36 @@ __device__ __forceinline__ void pair_accumulate(float dx, float dy, float dz, fl
 }
 
 // Adjoint of one pair for the cotangents: out += J(D) u with u = abar_j -
-// abar_i and J = d(g D)/dD = g I + 2 g_s D D^T, g_s = dg/ds.  The adjoint
-// table holds H = h b_f^10 = g / (1 - s/b_f^2)^5 as a quintic per 1/8 octave
-// of s, so that its derivative is accurate too; with w = 1 - s/b_f^2 clamped
-// to [0, 1] as in pair_accumulate: g = H w^5 and g_s = w^4 (H_s w - 5 H /
-// b_f^2), H_s = (dH/dz) 2^-e for s in [2^e, 2^(e+1)).
+// abar_i and J = d(g D)/dD = g I + 2 g_s D D^T, g_s = dg/ds.  It reads the
+// forward's table: H = h b_f^10 = g / (1 - s/b_f^2)^5 and, by synthetic
+// division of the same cubic, dH/dz, with z the local variable of the row
+// (s = 2^e (1 + z)), so H_s = (dH/dz) 2^-e; one 16-byte table read per pair
+// (the LDS reads, not the arithmetic, limit this kernel).  With w = 1 -
+// s/b_f^2 clamped to [0, 1] as in pair_accumulate: g = H w^5 and 2 g_s =
+// w^4 (2 H_s w + 10 negc H), negc = -1/b_f^2.  Every term enters the
+// accumulators through an FMA.
 __device__ __forceinline__ void pair_adjoint(float dx, float dy, float dz, float ux, float uy,
                                              float uz, float negc, float &ox, float &oy,
                                              float &oz) {
     const float s = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, 0x1p-31f)));
     const uint32_t b = __float_as_uint(s);
-    const int row = (int)(b >> (23 - kAMantBits)) - kARow0;
-    const float4 c0 = pair_arows[2 * row], c1 = pair_arows[2 * row + 1];
-    const float z = __uint_as_float((b & ((1u << (23 - kAMantBits)) - 1u)) | 0x3F800000u) - 1.0f;
-    const float inv2e = __uint_as_float(0x7F000000u - (b & 0x7F800000u));  // 2^-e
-    float h = fmaf(c1.y, z, c1.x);
-    float hz = c1.y;
+    const float4 c = pair_srows[(b >> (23 - kSMantBits)) - kSRow0];
+    const float z = __uint_as_float((b & ((1u << (23 - kSMantBits)) - 1u)) | 0x3F800000u) - 1.0f;
+    const float inv2e2 = __uint_as_float(0x7F800000u - (b & 0x7F800000u));  // 2^(1-e)
+    float h = fmaf(c.w, z, c.z);
+    float hz = fmaf(c.w, z, h);
+    h = fmaf(h, z, c.y);
     hz = fmaf(hz, z, h);
-    h = fmaf(h, z, c0.w);
-    hz = fmaf(hz, z, h);
-    h = fmaf(h, z, c0.z);
-    hz = fmaf(hz, z, h);
-    h = fmaf(h, z, c0.y);
-    hz = fmaf(hz, z, h);
-    h = fmaf(h, z, c0.x);
+    h = fmaf(h, z, c.x);
     const float w = unit_clamp(fmaf(s, negc, 1.0f));
     const float w2 = w * w;
     const float w4 = w2 * w2;
     const float g = (h * w) * w4;
-    const float gs2 = 2.0f * w4 * fmaf(hz * inv2e, w, (5.0f * negc) * h);  // 2 g_s
-    const float du = (dx * ux + dy * uy + dz * uz) * gs2;
-    ox += g * ux + du * dx;
-    oy += g * uy + du * dy;
-    oz += g * uz + du * dz;
+    const float gs2 = w4 * fmaf(hz * inv2e2, w, (10.0f * negc) * h);  // 2 g_s
+    const float du = fmaf(dz, uz, fmaf(dy, uy, dx * ux)) * gs2;
+    ox = fmaf(du, dx, fmaf(g, ux, ox));
+    oy = fmaf(du, dy, fmaf(g, uy, oy));
+    oz = fmaf(du, dz, fmaf(g, uz, oz));
 }
 
 // Heavy tiles are done in z-chunks: own cells are ordered z-major, so the own
@@ -189,11 +185,7 @@ __global__ __launch_bounds__((PPGeo<ADJ, H>::BLOCK)) void pp_kernel(const uint16
     const int tid = threadIdx.x;
     const int n_ios = nt * kTileIos;
     const float inv = 1.0f / 32768.0f;
-    if (ADJ) {
-        for (int i = tid; i < kARows * kARowFloats / 4; i += kPPBlock) pair_arows[i] = table[i];
-    } else {
-        for (int i = tid; i < kSRows; i += kPPBlock) pair_srows[i] = table[i];
-    }
+    for (int i = tid; i < kSRows; i += kPPBlock) pair_srows[i] = table[i];
 
     // Persistent workgroups: each takes the next tile of the heaviest-first
     // order (claim_slot) until all are taken (the exit test is
@@ -618,7 +610,6 @@ int build_pair_table(cube2_ctx *ctx) {
         row64[10] = yb;
     }
     fit_h_rows(ctx, kSMantBits, 4, kSRow0, kSRows, 4, ctx->pp_srows);
-    fit_h_rows(ctx, kAMantBits, 6, kARow0, kARows, kARowFloats, ctx->pp_arows);
     return 0;
 }
 
@@ -628,8 +619,7 @@ template <bool ADJ, int H>
 int launch_pp_kernel_h(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                      const float *abar, float *out, int accumulate, unsigned char *work,
                      const WorkLayout &L, hipStream_t s, float grid_frac) {
-    const float4 *table =
-        reinterpret_cast<const float4 *>(ctx->tables + (ADJ ? ctx->pp_aoff : ctx->pp_soff));
+    const float4 *table = reinterpret_cast<const float4 *>(ctx->tables + ctx->pp_soff);
     const int nt = ctx->nt;
     const int ntiles = nt * nt * nt;
     int r = launch_order_tiles(ctx, cs, work, L, s);
@@ -747,24 +737,23 @@ extern "C" int cube2_pair_jacobian_f32(const cube2_ctx *ctx, const float *d, flo
         const float s = std::fmaf(dz, dz, std::fmaf(dy, dy, std::fmaf(dx, dx, 0x1p-31f)));
         uint32_t b;
         std::memcpy(&b, &s, 4);
-        const float *c = &ctx->pp_arows[(size_t)((int)(b >> (23 - kAMantBits)) - kARow0) * kARowFloats];
-        const uint32_t zb = (b & ((1u << (23 - kAMantBits)) - 1u)) | 0x3F800000u;
-        const uint32_t eb = 0x7F000000u - (b & 0x7F800000u);
-        float z, inv2e;
+        const float *c = &ctx->pp_srows[(size_t)((b >> (23 - kSMantBits)) - kSRow0) * 4];
+        const uint32_t zb = (b & ((1u << (23 - kSMantBits)) - 1u)) | 0x3F800000u;
+        const uint32_t eb = 0x7F800000u - (b & 0x7F800000u);
+        float z, inv2e2;
         std::memcpy(&z, &zb, 4);
-        std::memcpy(&inv2e, &eb, 4);
+        std::memcpy(&inv2e2, &eb, 4);
         z -= 1.0f;
-        float h = std::fmaf(c[5], z, c[4]);
-        float hz = c[5];
-        for (int k = 3; k >= 0; --k) {
-            hz = std::fmaf(hz, z, h);
-            h = std::fmaf(h, z, c[k]);
-        }
+        float h = std::fmaf(c[3], z, c[2]);
+        float hz = std::fmaf(c[3], z, h);
+        h = std::fmaf(h, z, c[1]);
+        hz = std::fmaf(hz, z, h);
+        h = std::fmaf(h, z, c[0]);
         const float w = std::fmin(std::fmax(std::fmaf(s, ctx->pp_negc, 1.0f), 0.0f), 1.0f);
         const float w2 = w * w;
         const float w4 = w2 * w2;
         g[i] = (h * w) * w4;
-        gs[i] = 0.5f * (2.0f * w4 * std::fmaf(hz * inv2e, w, (5.0f * ctx->pp_negc) * h));
+        gs[i] = 0.5f * (w4 * std::fmaf(hz * inv2e2, w, (10.0f * ctx->pp_negc) * h));
     }
     return CUBE2_OK;
 }

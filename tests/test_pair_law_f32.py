@@ -109,9 +109,10 @@ def test_pair_law_f32_coincident_and_range():
 def test_pair_jacobian_f32_against_oracle(b_f, b_pp):
     """The adjoint kernel's (g, g_s = dg/ds) against the extended-precision
     oracle (g_s = (dg/dr) / 2r): g as above; the term 2 g_s D D^T of the pair
-    Jacobian g I + 2 g_s D D^T within (3e-5 + 5e-7/q) of the Jacobian's size
-    |g| + 2 |g_s| s (its table is a quintic per 1/8 octave, whose derivative
-    is good to a few 1e-6; g_s vanishes like q^4 at the cutoff)."""
+    Jacobian g I + 2 g_s D D^T within (1e-4 + 5e-7/q) of the Jacobian's size
+    |g| + 2 |g_s| s (g_s comes from the derivative of the forward table's
+    cubic, good to a few 1e-5 of the Jacobian, worst next to the breakpoints
+    of eq. 2 inside a row; g_s vanishes like q^4 at the cutoff)."""
     m, h = _ctx(b_f, b_pp)
     try:
         rng = np.random.default_rng(13)
@@ -133,7 +134,7 @@ def test_pair_jacobian_f32_against_oracle(b_f, b_pp):
         eg = np.abs(g - gref)[inside] / ((2e-6 + 1e-6 / q[inside]) * np.abs(gref[inside]))
         s2 = 2 * rr[inside] ** 2
         jac = np.abs(gref[inside]) + np.abs(gsref[inside]) * s2
-        es = np.abs(gs - gsref)[inside] * s2 / ((3e-5 + 5e-7 / q[inside]) * jac)
+        es = np.abs(gs - gsref)[inside] * s2 / ((1e-4 + 5e-7 / q[inside]) * jac)
         assert eg.max() <= 1.0, (eg.max(), rr[inside][np.argmax(eg)])
         assert es.max() <= 1.0, (es.max(), rr[inside][np.argmax(es)])
         assert np.all(g[q <= 0] == 0.0) and np.all(gs[q <= 0] == 0.0)
