@@ -221,40 +221,60 @@ int cube2_pm_level_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *ce
                          int64_t n, int level, float *acc, int accumulate, void *work,
                          size_t work_bytes, cube2_stream_t stream);
 
-/* Tile+buffer mode (section 2.2.3, PM2 paragraph): the fine level and PP of
- * a tile are computed on a local periodic box holding the tile and a buffer
- * zone around it; the fine level's force is truncated at b_coarse, so a
- * buffer of at least b_coarse + 3 fine cells keeps every particle that acts
- * on the tile's own particles and puts the local box's periodic images
- * beyond the truncation.  The coarse level stays global
- * (cube2_pm_level_force, level 1).
+/* Local boxes of tiles (section 2.2.3).  The tile+buffer mode of the PM2
+ * paragraph computes the fine level and PP of a tile on a local periodic box
+ * holding the tile and a buffer zone around it: the fine level's force is
+ * truncated at b_coarse, so a buffer of at least b_coarse + 3 fine cells
+ * keeps every particle that acts on the tile's own particles and puts the
+ * box's periodic images beyond the truncation; the coarse level stays global
+ * (cube2_pm_level_force, level 1).  The PM3 level of the PM3 paragraph uses
+ * the same boxes for subtiles, several of them packed into one box.
  *
- * cube2_tile_gather: the particles of the global context's box of fine
- * cells [origin - buffer, origin + tile + buffer)^3 (periodic; origin (host,
- * 3 ints, fine cells), tile and buffer even; n_local = tile + 2 buffer a
- * power of two in [32, 512], at most n_fine) are written as positions of the
- * local box in its box units, x_local (device, (3, m) SoA at the front of a
- * buffer of 3*m_max floats; exact in FP32), with their indices in the global
- * particle order, idx (device, m int32).  The order is fixed (region cells
+ * cube2_tile_gather: for n_tiles tiles (origins, host, 3 ints per tile, x y
+ * z, fine cells, even; 1 <= n_tiles <= 4096), the particles of the global
+ * context's boxes of fine cells [origin - buffer, origin + tile + buffer)^3
+ * (periodic; tile and buffer even; the slot side n_slot = tile + 2 buffer a
+ * power of two, 32 <= n_slot <= n_fine).  Tile t is placed in slot t of a
+ * k^3 grid of slots (k the smallest power of two with k^3 >= n_tiles, slot
+ * t at (t mod k, (t / k) mod k, t / k^2) n_slot), and the packed box of
+ * n_box = k n_slot <= 512 fine cells receives the positions in its box
+ * units, x_local (device, (3, m) SoA at the front of a buffer of 3*m_max
+ * floats; exact in FP32), with the particles' indices in the global order,
+ * idx (device, m int32).  The order is fixed (tile by tile, region cells
  * z-major, x fastest, then the particle order within a cell), so the call is
  * deterministic.  *m (host) receives the count; the call synchronises the
  * stream to read it and returns CUBE2_EWORKSPACE, writing nothing, when it
- * exceeds m_max.  Uses the fine-mesh area of `work`.
+ * exceeds m_max (or when n_tiles (n_slot/2)^3 exceeds the IOS cells of the
+ * context).  Uses the fine-mesh and reduction areas of `work`.
  *
- * cube2_tile_scatter_add: for the m gathered particles after a local
- * cube2_pack (perm_local, device, m int32: gathered slot of local particle
- * i) and a local force acc_local (device, (3, m) in the local particle
- * order), adds acc_local to acc (device, (3, n), global order) at idx for
- * the particles inside the tile proper (local coordinates in [buffer,
- * buffer + tile) fine cells on every axis).  Each particle lies in exactly
- * one tile of a tiling of the box, so the adds of one tile do not collide. */
+ * cube2_tile_scatter_add: for the m gathered particles after a cube2_pack on
+ * the packed box's context (perm_local, device, m int32: gathered slot of
+ * local particle i) and a force on it, acc_local (device, (3, m) in the
+ * local particle order), adds scale * acc_local to acc (device, (3, n),
+ * global order) at idx for the particles inside their tile proper (position
+ * within the slot in [buffer, buffer + tile) fine cells on every axis).  A
+ * box in units of H fine cells gives forces H^2 times those in fine units
+ * (eq. 2 is homogeneous of degree -2), so scale = 1/H^2 there.  Each
+ * particle lies in one tile of a tiling of the box, so the adds of one call
+ * do not collide. */
 int cube2_tile_gather(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
-                      const int32_t origin[3], int32_t tile, int32_t buffer, float *x_local,
-                      int32_t *idx, int64_t m_max, int64_t *m, void *work, size_t work_bytes,
-                      cube2_stream_t stream);
+                      const int32_t *origins, int32_t n_tiles, int32_t tile, int32_t buffer,
+                      float *x_local, int32_t *idx, int64_t m_max, int64_t *m, void *work,
+                      size_t work_bytes, cube2_stream_t stream);
 int cube2_tile_scatter_add(int64_t m, const int32_t *perm_local, const float *x_local,
-                           const int32_t *idx, int32_t tile, int32_t buffer,
-                           const float *acc_local, float *acc, int64_t n, cube2_stream_t stream);
+                           const int32_t *idx, int32_t n_tiles, int32_t tile, int32_t buffer,
+                           float scale, const float *acc_local, float *acc, int64_t n,
+                           cube2_stream_t stream);
+
+/* cube2_pp_force restricted to the tiles (8^3 IOS cells) with skip_tiles[t]
+ * == 0 (device, one byte per tile, t = (tz nt + ty) nt + tx with nt =
+ * n_fine/16 tiles per side, may be NULL): the pair sums of the particles of a
+ * skipped tile are neither computed nor written (their acc entries are left
+ * as they are), as when the PM3 level of section 2.2.3 takes those
+ * particles' short-range force with a shorter PP range. */
+int cube2_pp_force_skip(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                        int64_t n, const uint8_t *skip_tiles, float *acc, int accumulate,
+                        void *work, size_t work_bytes, cube2_stream_t stream);
 
 /* PP force (eq. 4d): a_i += G m_p sum_{j != i, 0 < r < b_fine}
  * [R(r,b_pp) - R(r,b_fine)] (x_j - x_i)/r with R of eq. (2) and the exact

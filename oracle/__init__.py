@@ -508,6 +508,29 @@ def tile_local_accel(params: Params, xf: np.ndarray, origin, tile: int, buffer: 
     return np.nonzero(own)[0], a[:, own[inb]]
 
 
+def pm3_local_accel(params: Params, xf: np.ndarray, origin, tile: int, buffer: int, h3: float,
+                    beta3: float = 3.5, workers: int = 1):
+    """PM3 level and its PP of the particles of one subtile (section 2.2.3,
+    PM3 paragraph; eqs. 4c and 4d with three levels).
+
+    On the local periodic box of the subtile and a buffer, a mesh of spacing
+    H3 = h3 fine cells carries the level whose target force is R(r, b3) -
+    R(r, b2), softening b3 = beta3 H3 truncated at the fine level's softening
+    b2 = params.b_fine, and the PP sum with softening b_pp is cut at b3.  It
+    is the tile computation of tile_local_accel in units of H3 cells (eq. 2
+    is homogeneous of degree -2: R(r / H, b / H) = H^2 R(r, b)), scaled back
+    to fine-cell units.  Returns (indices of the subtile's own particles,
+    their PM3 + PP acceleration)."""
+    scaled = Params(n_fine=int(round(params.n_fine / h3)), coarse_ratio=params.coarse_ratio,
+                    b_coarse=params.b_fine / h3, b_fine=beta3, b_pp=params.b_pp / h3,
+                    m_p=params.m_p, G_N=params.G_N, alias_nmax=params.alias_nmax,
+                    assign=params.assign)
+    o = [int(round(v / h3)) for v in origin]
+    idx, a = tile_local_accel(scaled, np.asarray(xf, dtype=np.float64) / h3, o,
+                              int(round(tile / h3)), int(round(buffer / h3)), workers)
+    return idx, a / (h3 * h3)
+
+
 # ---------------------------------------------------------------------------
 # IOS velocities (section 2.3)
 # ---------------------------------------------------------------------------

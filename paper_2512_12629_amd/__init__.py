@@ -75,8 +75,11 @@ def _load():
         "cube2_pm_level_force": [P, P, P, I64, I, P, I, P, S, P],
         "cube2_pp_force_noalloc": [P, P, P, I64, P, I, P],
         "cube2_tile_gather": [P, P, P, I64, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
-                              ctypes.c_int32, P, P, I64, ctypes.POINTER(I64), P, S, P],
-        "cube2_tile_scatter_add": [I64, P, P, P, ctypes.c_int32, ctypes.c_int32, P, P, I64, P],
+                              ctypes.c_int32, ctypes.c_int32, P, P, I64, ctypes.POINTER(I64), P,
+                              S, P],
+        "cube2_tile_scatter_add": [I64, P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_float, P, P, I64, P],
+        "cube2_pp_force_skip": [P, P, P, I64, P, P, I, P, S, P],
         "cube2_force": [P, P, P, I64, P, P, S, P],
         "cube2_force_backward": [P, P, P, I64, P, P, I, P, S, P],
         "cube2_kick_drift": [P, P, P, P, P, I64, D, D, P, P, P, P, P, S, P],
@@ -207,26 +210,40 @@ def cube2_pm_level_force(ctx, pos, cell_start, level, acc, work, accumulate=Fals
                                      _stream(stream)), "cube2_pm_level_force")
 
 
-def cube2_tile_gather(ctx, pos, cell_start, origin, tile, buffer, x_local, idx, work,
+def cube2_tile_gather(ctx, pos, cell_start, origins, tile, buffer, x_local, idx, work,
                       stream=None):
-    """Returns the number m of particles of the tile and its buffer; x_local
-    holds (3, m) at its front and idx m entries, unless m > idx.numel(), when
-    nothing is written (the caller grows its buffers and calls again)."""
-    o = (ctypes.c_int32 * 3)(*[int(v) for v in origin])
+    """Gathers the particles of the tiles at `origins` (a list of (x, y, z)
+    fine-cell origins) with their buffers into one packed box; returns their
+    number m.  x_local holds (3, m) at its front and idx m entries, unless
+    m > idx.numel(), when nothing is written (the caller grows its buffers
+    and calls again)."""
+    flat = [int(v) for o in origins for v in o]
+    o = (ctypes.c_int32 * len(flat))(*flat)
     m = ctypes.c_int64()
-    code = _lib.cube2_tile_gather(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], o, int(tile),
-                                  int(buffer), _ptr(x_local), _ptr(idx), idx.numel(),
-                                  ctypes.byref(m), _ptr(work), work.numel(), _stream(stream))
+    code = _lib.cube2_tile_gather(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1], o,
+                                  len(flat) // 3, int(tile), int(buffer), _ptr(x_local),
+                                  _ptr(idx), idx.numel(), ctypes.byref(m), _ptr(work),
+                                  work.numel(), _stream(stream))
     if code != -3:
         _check(code, "cube2_tile_gather")
     return m.value
 
 
-def cube2_tile_scatter_add(perm_local, x_local, idx, tile, buffer, acc_local, acc, stream=None):
+def cube2_tile_scatter_add(perm_local, x_local, idx, n_tiles, tile, buffer, acc_local, acc,
+                           scale=1.0, stream=None):
     m = perm_local.shape[0]
-    _check(_lib.cube2_tile_scatter_add(m, _ptr(perm_local), _ptr(x_local), _ptr(idx), int(tile),
-                                       int(buffer), _ptr(acc_local), _ptr(acc), acc.shape[1],
+    _check(_lib.cube2_tile_scatter_add(m, _ptr(perm_local), _ptr(x_local), _ptr(idx),
+                                       int(n_tiles), int(tile), int(buffer), float(scale),
+                                       _ptr(acc_local), _ptr(acc), acc.shape[1],
                                        _stream(stream)), "cube2_tile_scatter_add")
+
+
+def cube2_pp_force_skip(ctx, pos, cell_start, skip_tiles, acc, work, accumulate=False,
+                        stream=None):
+    _check(_lib.cube2_pp_force_skip(ctx, _ptr(pos), _ptr(cell_start), pos.shape[1],
+                                    _ptr(skip_tiles), _ptr(acc), int(bool(accumulate)),
+                                    _ptr(work), work.numel(), _stream(stream)),
+           "cube2_pp_force_skip")
 
 
 def cube2_force(ctx, pos, cell_start, acc, work, stream=None):
@@ -623,19 +640,19 @@ class Cube2Tiled:
     def tile_force(self, pos, cs, origin, acc):
         """Adds the fine-level + PP force of the particles of one tile to acc."""
         loc = self._local(1024)
-        m = cube2_tile_gather(self.g.ctx, pos, cs, origin, self.tile, self.buffer, self.x_buf,
+        m = cube2_tile_gather(self.g.ctx, pos, cs, [origin], self.tile, self.buffer, self.x_buf,
                               self.i_buf, self.g.work)
         if m > self.m_cap:
             loc = self._local(m)
-            m = cube2_tile_gather(self.g.ctx, pos, cs, origin, self.tile, self.buffer, self.x_buf,
-                                  self.i_buf, self.g.work)
+            m = cube2_tile_gather(self.g.ctx, pos, cs, [origin], self.tile, self.buffer,
+                                  self.x_buf, self.i_buf, self.g.work)
         if m == 0:
             return
         xl = self.x_buf[:3 * m].view(3, m)
         pos_l, cs_l, perm_l = loc.pack(xl)
         a_l = loc.pm_level_force(pos_l, cs_l, 0)
         loc.pp_force(pos_l, cs_l, a_l)
-        cube2_tile_scatter_add(perm_l, xl, self.i_buf[:m], self.tile, self.buffer, a_l, acc)
+        cube2_tile_scatter_add(perm_l, xl, self.i_buf[:m], 1, self.tile, self.buffer, a_l, acc)
 
     def force(self, pos, cs, origins=None):
         """Coarse level for every particle plus, for the tiles at `origins`
@@ -644,3 +661,176 @@ class Cube2Tiled:
         for o in (self.origins() if origins is None else origins):
             self.tile_force(pos, cs, o, acc)
         return acc
+
+
+class Cube2PM3:
+    """Three-level force with an adaptive PM3 level on subtiles (section
+    2.2.3, PM3 paragraph; eq. 4 with three levels): the coarse and fine PM
+    levels on the whole box; for the selected tiles (the PP kernel's 16^3
+    fine-cell tiles) a PM3 level of spacing H3 = h3 fine cells with softening
+    b3 = beta3 H3, truncated at the fine softening b2, plus a PP sum cut at
+    b3, computed on local boxes of the tile and a buffer (several tiles packed
+    into one box); for the other tiles the PP sum cut at b2.  Every step is a
+    C-ABI call (cube2_pm_force, cube2_pp_force_skip, cube2_tile_gather,
+    cube2_pack / cube2_pm_level_force / cube2_pp_force on the PM3 context,
+    cube2_tile_scatter_add with scale 1/H3^2).
+
+    Which tiles get a PM3 level follows the paper's rule: the one that
+    minimises t_PM3 + t_PP, from a cost model measured on the device
+    (calibrate): the PP time per candidate pair of the b2 range, and the PM3
+    time per particle of a packed box."""
+
+    TILE = 16
+
+    def __init__(self, cfg: Config, n_max: int, h3: float = 0.5, beta3: float = 3.5,
+                 device="cuda", max_batch: int | None = None):
+        import dataclasses
+        self.max_batch = max_batch
+        if not cfg.coarse_ratio:
+            raise ValueError("the PM3 level sits below a two-level configuration")
+        self.g = Cube2(cfg, n_max, device)
+        self.device = self.g.device
+        self.h3, self.beta3 = float(h3), float(beta3)
+        self.scale = 1.0 / (self.h3 * self.h3)
+        b2 = cfg.b_fine
+        # buffer: at least b2 + 3 H3 (truncation plus assignment and stencil
+        # reach), even, with a power-of-two slot of 32 fine cells or more
+        self.buffer = 8
+        while self.buffer < b2 + 3 * self.h3 or (self.TILE + 2 * self.buffer) & (
+                self.TILE + 2 * self.buffer - 1):
+            self.buffer += 2
+        self.n_slot = self.TILE + 2 * self.buffer
+        self.cfg3 = dataclasses.replace(cfg, n_fine=0, b_coarse=b2 / self.h3, b_fine=self.beta3,
+                                        b_pp=cfg.b_pp / self.h3)
+        self.nt = cfg.n_fine // self.TILE
+        self._ctx3 = {}
+        self.model = None
+
+    def _pm3_ctx(self, k, m):
+        key = k
+        c, cap = self._ctx3.get(key, (None, 0))
+        if c is None or m > cap:
+            import dataclasses
+            cap = max(m, 4096)
+            n3 = int(round(k * self.n_slot / self.h3))
+            c = Cube2(dataclasses.replace(self.cfg3, n_fine=n3), cap, self.device)
+            self._ctx3[key] = (c, cap)
+        return c
+
+    def origins(self, tiles):
+        nt = self.nt
+        return [((t % nt) * self.TILE, (t // nt % nt) * self.TILE, (t // (nt * nt)) * self.TILE)
+                for t in tiles]
+
+    def tile_stats(self, cs):
+        """Per tile (index (tz nt + ty) nt + tx): particle count and the
+        candidate pairs of the PP sum at the b2 range (particles of each IOS
+        cell times those of its 27 neighbour cells), from the cell starts."""
+        n_ios = 8 * self.nt
+        cnt = (cs[1:].long() - cs[:-1].long()).view(self.nt, self.nt, self.nt, 8, 8, 8)
+        grid = cnt.permute(0, 3, 1, 4, 2, 5).reshape(n_ios, n_ios, n_ios).float()
+        nb = grid.clone()
+        reach = 1 if self.g.cfg.b_fine <= 2.0 else 2
+        for ax in range(3):   # (2 reach + 1)-cell box sum along each axis, periodic
+            acc = nb.clone()
+            for r in range(1, reach + 1):
+                acc += nb.roll(r, ax) + nb.roll(-r, ax)
+            nb = acc
+        cand = (grid * nb).view(self.nt, 8, self.nt, 8, self.nt, 8).sum((1, 3, 5))
+        return cnt.sum((3, 4, 5)).reshape(-1), cand.reshape(-1)
+
+    def pm3_tiles(self, pos, cs, tiles, acc):
+        """Adds the PM3 level + PP of the given tiles' particles to acc."""
+        tiles = list(tiles)
+        n = pos.shape[1]
+        kmax = 1
+        while kmax * 2 * self.n_slot <= 512 and (kmax * 2) ** 3 * (self.n_slot // 2) ** 3 <= \
+                (self.nt * 8) ** 3:
+            kmax *= 2
+        per = kmax ** 3 if self.max_batch is None else max(1, min(kmax ** 3, self.max_batch))
+        for b in range(0, len(tiles), per):
+            batch = tiles[b:b + per]
+            k = 1
+            while k ** 3 < len(batch):
+                k *= 2
+            cap = max(4096, int(n))
+            while True:   # buffers overlap, so a batch can hold more than n particles
+                x_buf = torch.empty(3 * cap, dtype=torch.float32, device=self.device)
+                i_buf = torch.empty(cap, dtype=torch.int32, device=self.device)
+                m = cube2_tile_gather(self.g.ctx, pos, cs, self.origins(batch), self.TILE,
+                                      self.buffer, x_buf, i_buf, self.g.work)
+                if m <= cap:
+                    break
+                cap = m
+            if m == 0:
+                continue
+            c3 = self._pm3_ctx(k, m)
+            xl = x_buf[:3 * m].view(3, m)
+            p3, cs3, perm3 = c3.pack(xl)
+            a3 = c3.pm_level_force(p3, cs3, 0)
+            c3.pp_force(p3, cs3, a3)
+            cube2_tile_scatter_add(perm3, xl, i_buf[:m], len(batch), self.TILE, self.buffer, a3,
+                                   acc, self.scale)
+
+    def force(self, pos, cs, tiles=None):
+        """Coarse + fine PM of every particle; PP cut at b2 for the tiles not
+        in `tiles`; PM3 + PP cut at b3 for those in it (default: the model's
+        choice, none before calibrate())."""
+        if tiles is None:
+            tiles = self.select(cs) if self.model else []
+        acc = self.g.pm_force(pos, cs)
+        skip = torch.zeros(self.nt ** 3, dtype=torch.uint8, device=self.device)
+        if len(tiles):
+            skip[torch.as_tensor(list(tiles), dtype=torch.long, device=self.device)] = 1
+        cube2_pp_force_skip(self.g.ctx, pos, cs, skip, acc, self.g.work, accumulate=True)
+        if len(tiles):
+            self.pm3_tiles(pos, cs, tiles, acc)
+        return acc
+
+    def calibrate(self, pos, cs, trial=64, reps=3):
+        """Measures the cost model on the device: the b2-range PP time per
+        candidate pair (the whole PP sum) and the PM3 time per particle of a
+        packed box (the `trial` heaviest tiles), and keeps it for select()."""
+        import numpy as np
+        count, cand = self.tile_stats(cs)
+        stream = torch.cuda.current_stream()
+
+        def timed(fn):
+            ts = []
+            for _ in range(reps + 1):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                a.record(stream)
+                fn()
+                b.record(stream)
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(b))
+            return float(np.median(ts[1:])) * 1e-3
+
+        acc = torch.zeros((3, pos.shape[1]), dtype=torch.float32, device=self.device)
+        t_pp = timed(lambda: self.g.pp_force(pos, cs, acc))
+        heavy = torch.argsort(count, descending=True)[:trial].tolist()
+        m_trial = float(count[heavy].sum())
+        t_pm3 = timed(lambda: self.pm3_tiles(pos, cs, heavy, acc))
+        self.model = {"pp_s_per_candidate": t_pp / max(float(cand.sum()), 1.0),
+                      "pm3_s_per_particle": t_pm3 / max(m_trial, 1.0),
+                      "pp_b3_candidate_fraction": self._cand_fraction(),
+                      "t_pp_s": t_pp, "t_pm3_trial_s": t_pm3, "trial_tiles": len(heavy)}
+        return self.model
+
+    def _cand_fraction(self):
+        # candidate volume of the PM3 box's PP, (2 reach + 1) IOS cells of
+        # 2 H3 fine cells per axis, over that of the b2 range's PP, (2 reach
+        # + 1) IOS cells of 2 fine cells
+        r3 = 1 if self.beta3 <= 2.0 else 2
+        r2 = 1 if self.g.cfg.b_fine <= 2.0 else 2
+        return ((2 * r3 + 1) * 2 * self.h3) ** 3 / ((2 * r2 + 1) * 2.0) ** 3
+
+    def select(self, cs):
+        """Tiles whose predicted PP saving exceeds their predicted PM3 time:
+        t_pp_per_cand * cand * (1 - f3) > t_pm3_per_particle * count."""
+        count, cand = self.tile_stats(cs)
+        md = self.model
+        save = md["pp_s_per_candidate"] * cand * (1.0 - md["pp_b3_candidate_fraction"])
+        cost = md["pm3_s_per_particle"] * count
+        return torch.nonzero(save > cost).flatten().tolist()

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "common.hpp"
 
@@ -341,37 +342,44 @@ int cube2_pm_level_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *ce
 }
 
 int cube2_tile_gather(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start, int64_t n,
-                      const int32_t origin[3], int32_t tile, int32_t buffer, float *x_local,
-                      int32_t *idx, int64_t m_max, int64_t *m, void *work, size_t work_bytes,
-                      cube2_stream_t stream) {
+                      const int32_t *origins, int32_t n_tiles, int32_t tile, int32_t buffer,
+                      float *x_local, int32_t *idx, int64_t m_max, int64_t *m, void *work,
+                      size_t work_bytes, cube2_stream_t stream) {
     CHECK_READY();
-    if (n < 0 || n > INT32_MAX || !cell_start || !origin || !m || m_max < 0) return CUBE2_EINVAL;
+    if (n < 0 || n > INT32_MAX || !cell_start || !origins || !m || m_max < 0) return CUBE2_EINVAL;
     if (n > 0 && !pos) return CUBE2_EINVAL;
     if (m_max > 0 && (!x_local || !idx)) return CUBE2_EINVAL;
-    const int64_t n_local = (int64_t)tile + 2 * (int64_t)buffer;
+    if (n_tiles < 1 || n_tiles > 4096) return CUBE2_EINVAL;
+    const int64_t n_slot = (int64_t)tile + 2 * (int64_t)buffer;
     if (tile < 2 || buffer < 0 || (tile & 1) || (buffer & 1)) return CUBE2_EINVAL;
-    if (n_local < 32 || n_local > 512 || (n_local & (n_local - 1)) || n_local > ctx->n_f)
-        return CUBE2_EUNSUPPORTED;
-    int r0[3];
-    for (int d = 0; d < 3; ++d) {
-        if (origin[d] < 0 || origin[d] >= ctx->n_f || (origin[d] & 1)) return CUBE2_EINVAL;
-        r0[d] = (int)(((origin[d] - buffer) / 2 % ctx->n_ios + ctx->n_ios) % ctx->n_ios);
-    }
+    if (n_slot < 32 || (n_slot & (n_slot - 1)) || n_slot > ctx->n_f) return CUBE2_EUNSUPPORTED;
+    const int k = tile_slots(n_tiles);
+    if (n_slot * k > 512) return CUBE2_EUNSUPPORTED;   // exact FP32 box-unit positions
+    const int R = (int)(n_slot / 2);
+    // the per-cell scan must fit the scan area sized for the IOS cells
+    if ((int64_t)n_tiles * R * R * R > ctx->n_cells) return CUBE2_EWORKSPACE;
+    std::vector<int32_t> r0((size_t)3 * n_tiles);
+    for (int t = 0; t < n_tiles; ++t)
+        for (int d = 0; d < 3; ++d) {
+            const int32_t o = origins[3 * t + d];
+            if (o < 0 || o >= ctx->n_f || (o & 1)) return CUBE2_EINVAL;
+            r0[3 * t + d] = (int32_t)((((o - buffer) / 2) % ctx->n_ios + ctx->n_ios) % ctx->n_ios);
+        }
     CHECK_WORK(n);
     *m = 0;
-    return launch_tile_gather(ctx, pos, cell_start, n, r0, (int)(n_local / 2), (int)n_local,
-                              x_local, idx, m_max, m, work_, L_,
-                              reinterpret_cast<hipStream_t>(stream));
+    return launch_tile_gather(ctx, pos, cell_start, n, r0.data(), n_tiles, R, x_local, idx, m_max,
+                              m, work_, L_, reinterpret_cast<hipStream_t>(stream));
 }
 
 int cube2_tile_scatter_add(int64_t m, const int32_t *perm_local, const float *x_local,
-                           const int32_t *idx, int32_t tile, int32_t buffer,
-                           const float *acc_local, float *acc, int64_t n, cube2_stream_t stream) {
+                           const int32_t *idx, int32_t n_tiles, int32_t tile, int32_t buffer,
+                           float scale, const float *acc_local, float *acc, int64_t n,
+                           cube2_stream_t stream) {
     if (m < 0 || n < 0 || m > INT32_MAX || n > INT32_MAX) return CUBE2_EINVAL;
     if (m > 0 && (!perm_local || !x_local || !idx || !acc_local || !acc)) return CUBE2_EINVAL;
-    if (tile < 2 || buffer < 0) return CUBE2_EINVAL;
-    return launch_tile_scatter_add(m, perm_local, x_local, idx, buffer, buffer + tile,
-                                   tile + 2 * buffer, acc_local, acc, n,
+    if (tile < 2 || buffer < 0 || n_tiles < 1 || n_tiles > 4096) return CUBE2_EINVAL;
+    return launch_tile_scatter_add(m, perm_local, x_local, idx, n_tiles, buffer, buffer + tile,
+                                   tile + 2 * buffer, scale, acc_local, acc, n,
                                    reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -389,6 +397,17 @@ int cube2_pp_force(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_sta
         return CUBE2_OK;
     }
     return launch_pp(ctx, pos, cell_start, n, acc, accumulate, work_, L_, s);
+}
+
+int cube2_pp_force_skip(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
+                        int64_t n, const uint8_t *skip_tiles, float *acc, int accumulate,
+                        void *work, size_t work_bytes, cube2_stream_t stream) {
+    CHECK_READY();
+    if (n < 0 || n > INT32_MAX || !cell_start || (n > 0 && (!pos || !acc))) return CUBE2_EINVAL;
+    CHECK_WORK(n);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (n == 0 || (ctx->cfg.flags & CUBE2_PP_OFF)) return CUBE2_OK;
+    return launch_pp(ctx, pos, cell_start, n, acc, accumulate, work_, L_, s, skip_tiles);
 }
 
 namespace {

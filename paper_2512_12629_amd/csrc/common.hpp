@@ -350,11 +350,13 @@ int launch_interp_levels(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs
                          const float *phi_f, const float *phi_c, float *acc, int accumulate,
                          int levels, hipStream_t s);
 int launch_tile_gather(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
-                       const int (&r0)[3], int R, int n_local, float *x_local, int32_t *idx,
+                       const int32_t *r0_host, int T, int R, float *x_local, int32_t *idx,
                        int64_t m_max, int64_t *m_out, unsigned char *work, const WorkLayout &L,
                        hipStream_t s);
+// side k of the k^3 grid of slots that holds T tiles (a power of two)
+int tile_slots(int T);
 int launch_tile_scatter_add(int64_t m, const int32_t *perm_local, const float *x_local,
-                            const int32_t *idx, int lo, int hi, int n_local,
+                            const int32_t *idx, int T, int lo, int hi, int n_slot, float scale,
                             const float *acc_local, float *acc, int64_t n, hipStream_t s);
 
 // The tile order and work counter written by launch_order_tiles.
@@ -389,8 +391,11 @@ int launch_pp_concurrent(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs
                          const float *abar, float *acc_pp, unsigned char *work, const WorkLayout &L,
                          hipStream_t s);
 int launch_add3(float *acc, const float *acc_pp, int64_t m, hipStream_t s);
+// skip (device, one byte per tile, index (tz nt + ty) nt + tx, may be NULL):
+// tiles whose own particles the kernel leaves alone
 int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, float *acc,
-              int accumulate, unsigned char *work, const WorkLayout &L, hipStream_t s);
+              int accumulate, unsigned char *work, const WorkLayout &L, hipStream_t s,
+              const uint8_t *skip = nullptr);
 // Address of the no-allocation entry point's scratch array on the current
 // device (taken once per device); out may be NULL.
 int noalloc_setup(unsigned char **out);

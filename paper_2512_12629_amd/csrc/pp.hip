@@ -168,7 +168,8 @@ __global__ __launch_bounds__((PPGeo<ADJ, H>::BLOCK)) void pp_kernel(const uint16
                                                      const float *__restrict__ abar,
                                                      float *__restrict__ acc, int accumulate,
                                                      const uint32_t *__restrict__ order,
-                                                     uint32_t *__restrict__ queue, int ntiles) {
+                                                     uint32_t *__restrict__ queue, int ntiles,
+                                                     const uint8_t *__restrict__ skip) {
     constexpr int CAP = PPGeo<ADJ, H>::CAP;
     constexpr int kPPBlock = PPGeo<ADJ, H>::BLOCK;
     constexpr int kPSegPerThread = PPGeo<ADJ, H>::SEG_PER_THREAD;
@@ -203,6 +204,10 @@ __global__ __launch_bounds__((PPGeo<ADJ, H>::BLOCK)) void pp_kernel(const uint16
         if (ti >= ntiles) break;
         if (tid == 0) next = claim_slot(queue, ntiles);
         const int t = (int)order[ti];
+        if (skip && skip[t]) {   // a tile whose pairs another level handles
+            __syncthreads();     // every thread has read tile_sh
+            continue;
+        }
         const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
         const int c0x = tx * kTileIos, c0y = ty * kTileIos, c0z = tz * kTileIos;
 
@@ -618,7 +623,8 @@ namespace {
 template <bool ADJ, int H>
 int launch_pp_kernel_h(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                      const float *abar, float *out, int accumulate, unsigned char *work,
-                     const WorkLayout &L, hipStream_t s, float grid_frac) {
+                     const WorkLayout &L, hipStream_t s, float grid_frac,
+                     const uint8_t *skip) {
     const float4 *table = reinterpret_cast<const float4 *>(ctx->tables + ctx->pp_soff);
     const int nt = ctx->nt;
     const int ntiles = nt * nt * nt;
@@ -631,7 +637,8 @@ int launch_pp_kernel_h(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, 
         1u, (unsigned)((float)persistent_grid(k, PPGeo<ADJ, H>::BLOCK, ntiles) * grid_frac));
     k<<<grid, PPGeo<ADJ, H>::BLOCK, 0, s>>>(
         pos, cs, (int)n, nt, table, ctx->pp_negc,
-        (float)(ctx->cfg.g_newton * ctx->cfg.m_p), abar, out, accumulate, order, queue, ntiles);
+        (float)(ctx->cfg.g_newton * ctx->cfg.m_p), abar, out, accumulate, order, queue, ntiles,
+        skip);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }
@@ -639,12 +646,13 @@ int launch_pp_kernel_h(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, 
 template <bool ADJ>
 int launch_pp_kernel(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                      const float *abar, float *out, int accumulate, unsigned char *work,
-                     const WorkLayout &L, hipStream_t s, float grid_frac = 1.0f) {
+                     const WorkLayout &L, hipStream_t s, float grid_frac = 1.0f,
+                     const uint8_t *skip = nullptr) {
     if (ctx->pp_halo == 1)
         return launch_pp_kernel_h<ADJ, 1>(ctx, pos, cs, n, abar, out, accumulate, work, L, s,
-                                          grid_frac);
+                                          grid_frac, skip);
     return launch_pp_kernel_h<ADJ, 2>(ctx, pos, cs, n, abar, out, accumulate, work, L, s,
-                                      grid_frac);
+                                      grid_frac, skip);
 }
 
 __global__ void add3_kernel(float *__restrict__ acc, const float *__restrict__ b, int64_t m) {
@@ -685,8 +693,10 @@ int launch_add3(float *acc, const float *acc_pp, int64_t m, hipStream_t s) {
 }
 
 int launch_pp(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n, float *acc,
-              int accumulate, unsigned char *work, const WorkLayout &L, hipStream_t s) {
-    return launch_pp_kernel<false>(ctx, pos, cs, n, nullptr, acc, accumulate, work, L, s);
+              int accumulate, unsigned char *work, const WorkLayout &L, hipStream_t s,
+              const uint8_t *skip) {
+    return launch_pp_kernel<false>(ctx, pos, cs, n, nullptr, acc, accumulate, work, L, s, 1.0f,
+                                   skip);
 }
 
 int launch_pp_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,

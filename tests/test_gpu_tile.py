@@ -74,15 +74,15 @@ def test_tile_pp_part_is_the_periodic_pp(setup):
     n = pos.shape[1]
     o = (48, 16, 112)
     loc = t._local(1024)
-    mcount = m.cube2_tile_gather(t.g.ctx, pos, cs, o, TILE, BUF, t.x_buf, t.i_buf, t.g.work)
+    mcount = m.cube2_tile_gather(t.g.ctx, pos, cs, [o], TILE, BUF, t.x_buf, t.i_buf, t.g.work)
     if mcount > t.m_cap:
         loc = t._local(mcount)
-        mcount = m.cube2_tile_gather(t.g.ctx, pos, cs, o, TILE, BUF, t.x_buf, t.i_buf, t.g.work)
+        mcount = m.cube2_tile_gather(t.g.ctx, pos, cs, [o], TILE, BUF, t.x_buf, t.i_buf, t.g.work)
     xl = t.x_buf[:3 * mcount].view(3, mcount)
     pos_l, cs_l, perm_l = loc.pack(xl)
     a_l = loc.pp_force(pos_l, cs_l)
     acc = torch.zeros((3, n), dtype=torch.float32, device="cuda")
-    m.cube2_tile_scatter_add(perm_l, xl, t.i_buf[:mcount], TILE, BUF, a_l, acc)
+    m.cube2_tile_scatter_add(perm_l, xl, t.i_buf[:mcount], 1, TILE, BUF, a_l, acc)
     ref = t.g.pp_force(pos, cs).cpu().numpy().astype(np.float64)
     got = acc.cpu().numpy().astype(np.float64)
     idx, _ = oracle.tile_local_accel(setup["p"], setup["xf"], o, TILE, BUF)
