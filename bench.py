@@ -345,6 +345,58 @@ def pairwise_experiment(args):
     print(json.dumps(out))
 
 
+def pm3_experiment(args):
+    """The adaptive PM3 level (section 2.2.3, PM3 paragraph) at the paper's
+    softenings (beta = 3.5 on the fine level: b_f = 3.5 fine cells, the PP
+    range of 125 neighbour cells; b_pp = 1/16): the two-level force against
+    the three-level force with PM3 (H3 = 1/2 fine cell, b3 = 3.5 H3) on the
+    tiles that the measured t_PM3 + t_PP model selects, on the same
+    particles; and the difference of the two forces."""
+    import torch
+    import paper_2512_12629_amd as m
+    torch.cuda.set_device(0)
+    w = WORKLOADS[args.workload]
+    x_np = synthetic.make(args.workload)
+    N = x_np.shape[1]
+    cfg = m.Config(n_fine=w["n_fine"], coarse_ratio=w["coarse_ratio"], b_fine=args.pair_b_fine,
+                   b_pp=args.pair_b_pp)
+    p3 = m.Cube2PM3(cfg, N)
+    pos, cs, _ = p3.g.pack(torch.from_numpy(x_np).cuda())
+    del x_np
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, k):
+        ts = []
+        for _ in range(k + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts[1:]))
+
+    t_two = timed(lambda: p3.g.force(pos, cs), args.steps)
+    print(f"[bench] two-level force {t_two:.2f} ms", file=sys.stderr, flush=True)
+    model = p3.calibrate(pos, cs, trial=args.pm3_trial)
+    tiles = p3.select(cs)
+    print(f"[bench] model {model}; {len(tiles)} PM3 tiles", file=sys.stderr, flush=True)
+    t_three = timed(lambda: p3.force(pos, cs, tiles), args.steps)
+    a2 = p3.g.force(pos, cs).double()
+    a3 = p3.force(pos, cs, tiles).double()
+    num = torch.linalg.vector_norm(a3 - a2, dim=0)
+    den = torch.linalg.vector_norm(a2, dim=0).clamp_min(1e-300)
+    e = (num / den).cpu().numpy()
+    out = {"experiment": "adaptive PM3 level (section 2.2.3) at the paper's softenings",
+           "workload": args.workload, "particles": N, "b_fine": cfg.b_fine, "b_pp": cfg.b_pp,
+           "h3": p3.h3, "beta3": p3.beta3, "pm3_tiles": len(tiles), "tiles": p3.nt ** 3,
+           "two_level_force_ms": t_two, "three_level_force_ms": t_three,
+           "speedup": t_two / t_three, "model": model,
+           "rel_diff_median": float(np.median(e)), "rel_diff_p99": float(np.percentile(e, 99))}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -367,6 +419,11 @@ def main():
                          "paper's beta = 3.5")
     ap.add_argument("--pair-b-pp", type=float, default=0.2,
                     help="PP softening of the pairwise experiment (the paper's Fig. 1: ~0.06)")
+    ap.add_argument("--pm3", action="store_true",
+                    help="run the adaptive PM3 experiment (softenings from --pair-b-fine / "
+                         "--pair-b-pp, default 3.5 and 1/16 here) instead of the benchmark")
+    ap.add_argument("--pm3-trial", type=int, default=512,
+                    help="tiles of the PM3 cost-model calibration")
     ap.add_argument("--leapfrog-steps", type=int, default=4,
                     help="steps of the timed differentiable leapfrog (0: skip it)")
     ap.add_argument("--standalone", action="store_true",
@@ -390,6 +447,11 @@ def main():
 
     if args.pairwise:
         pairwise_experiment(args)
+        return
+    if args.pm3:
+        if args.pair_b_fine == 2.0 and args.pair_b_pp == 0.2:
+            args.pair_b_fine, args.pair_b_pp = 3.5, 0.0625
+        pm3_experiment(args)
         return
 
     import torch

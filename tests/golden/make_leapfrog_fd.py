@@ -28,7 +28,9 @@ large sums.
     python tests/golden/make_leapfrog_fd.py --merge --parts P [--tmp DIR]
 
 Each part (run them in parallel processes) evaluates its share of the
-perturbed forwards into DIR; --merge writes the JSON beside this script.
+perturbed forwards into DIR; --merge adds the oracle's own reverse-mode
+derivatives (oracle.leapfrog_loss_grad on the same trajectory) and writes the
+JSON beside this script.
 """
 import argparse
 import json
@@ -124,9 +126,17 @@ def merge(parts, tmp):
     missing = [j for j in todo if "%s:%s:%s" % j not in vals]
     if missing:
         raise SystemExit(f"{len(missing)} derivatives missing")
+    # the oracle's own reverse mode on the same continuous trajectory, for a
+    # three-way comparison (finite differences, oracle adjoint, GPU adjoint)
+    o, _, x0f, rho_t = setup(8)
+    _, gx, _ = oracle.leapfrog_loss_grad(o, x0f, np.zeros_like(x0f), base["dt"], base["dt"], STEPS,
+                                         rho_t)
+    dirs = synthetic.unit_directions(x0f.shape, N_DIRS, DIR_SEED)
     out = {
         "workload": "zel128_grad: 128^3 particles, Zel'dovich k^-2 rms 0.1 H_p, 256^3 mesh, "
                     "b_f = 2, b_pp = 0.2, one PM level + PP",
+        "oracle_adjoint_dirs": [float(np.sum(gx * dirs[k])) for k in range(N_DIRS)],
+        "oracle_adjoint_comps": [float(gx[j[2], j[1]]) for j in todo if j[0] == "comp"],
         "steps": STEPS, "dt": base["dt"], "loss": base["loss"], "n_fine": N_FINE,
         "dir_seed": DIR_SEED, "n_dirs": N_DIRS, "h_dirs": list(H_DIRS),
         "dirs": [[vals["dir:%d:%s" % (k, h)] for h in H_DIRS] for k in range(N_DIRS)],
