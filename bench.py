@@ -45,6 +45,9 @@ WORKLOADS = {
     "clu256": dict(n_fine=512, coarse_ratio=4,
                    desc="256^3 particles, Zel'dovich + 1000 Plummer spheres x 2048; fine 512^3, "
                         "coarse 128^3"),
+    "clu256_halos": dict(n_fine=512, coarse_ratio=4,
+                         desc="256^3 particles, Zel'dovich + 125 Plummer spheres x 16384; fine "
+                              "512^3, coarse 128^3"),
     "zel128": dict(n_fine=256, coarse_ratio=0,
                    desc="128^3 particles, Zel'dovich k^-2; single-level 256^3 mesh"),
 }
@@ -351,7 +354,9 @@ def pm3_experiment(args):
     range of 125 neighbour cells; b_pp = 1/16): the two-level force against
     the three-level force with PM3 (H3 = 1/2 fine cell, b3 = 3.5 H3) on the
     tiles that the measured t_PM3 + t_PP model selects, on the same
-    particles; and the difference of the two forces."""
+    particles; the same with PM3 forced on the heaviest tiles, against the
+    model's prediction of that change; and the difference of the two- and
+    three-level forces (on the forced tiles when the model selects none)."""
     import torch
     import paper_2512_12629_amd as m
     torch.cuda.set_device(0)
@@ -380,9 +385,17 @@ def pm3_experiment(args):
     t_two = timed(lambda: p3.g.force(pos, cs), args.steps)
     print(f"[bench] two-level force {t_two:.2f} ms", file=sys.stderr, flush=True)
     model = p3.calibrate(pos, cs, trial=args.pm3_trial)
-    tiles = p3.select(cs)
+    tiles = p3.select(pos, cs)
     print(f"[bench] model {model}; {len(tiles)} PM3 tiles", file=sys.stderr, flush=True)
     t_three = timed(lambda: p3.force(pos, cs, tiles), args.steps)
+    # the model against a forced choice: PM3 on the heaviest tiles
+    count, _, _ = p3.tile_stats(pos, cs)
+    forced = torch.argsort(count, descending=True)[:args.pm3_trial].tolist()
+    t_forced = timed(lambda: p3.force(pos, cs, forced), args.steps)
+    pred = p3.predicted_change(pos, cs, forced) * 1e3
+    pred_sel = p3.predicted_change(pos, cs, tiles) * 1e3 if tiles else 0.0
+    if not tiles:
+        tiles = forced        # report the difference of the forced choice
     a2 = p3.g.force(pos, cs).double()
     a3 = p3.force(pos, cs, tiles).double()
     num = torch.linalg.vector_norm(a3 - a2, dim=0)
@@ -393,6 +406,9 @@ def pm3_experiment(args):
            "h3": p3.h3, "beta3": p3.beta3, "pm3_tiles": len(tiles), "tiles": p3.nt ** 3,
            "two_level_force_ms": t_two, "three_level_force_ms": t_three,
            "speedup": t_two / t_three, "model": model,
+           "selected_delta_ms_measured": t_three - t_two, "selected_delta_ms_predicted": pred_sel,
+           "forced_heaviest_tiles": len(forced), "forced_force_ms": t_forced,
+           "forced_delta_ms_measured": t_forced - t_two, "forced_delta_ms_predicted": pred,
            "rel_diff_median": float(np.median(e)), "rel_diff_p99": float(np.percentile(e, 99))}
     print(json.dumps(out))
 

@@ -722,22 +722,46 @@ class Cube2PM3:
         return [((t % nt) * self.TILE, (t // nt % nt) * self.TILE, (t // (nt * nt)) * self.TILE)
                 for t in tiles]
 
-    def tile_stats(self, cs):
-        """Per tile (index (tz nt + ty) nt + tx): particle count and the
-        candidate pairs of the PP sum at the b2 range (particles of each IOS
-        cell times those of its 27 neighbour cells), from the cell starts."""
-        n_ios = 8 * self.nt
-        cnt = (cs[1:].long() - cs[:-1].long()).view(self.nt, self.nt, self.nt, 8, 8, 8)
-        grid = cnt.permute(0, 3, 1, 4, 2, 5).reshape(n_ios, n_ios, n_ios).float()
-        nb = grid.clone()
-        reach = 1 if self.g.cfg.b_fine <= 2.0 else 2
-        for ax in range(3):   # (2 reach + 1)-cell box sum along each axis, periodic
-            acc = nb.clone()
+    @staticmethod
+    def _box_sum(grid, reach):
+        """Sum over the (2 reach + 1)^3 box around every cell (periodic)."""
+        for ax in range(3):
+            acc = grid.clone()
             for r in range(1, reach + 1):
-                acc += nb.roll(r, ax) + nb.roll(-r, ax)
-            nb = acc
-        cand = (grid * nb).view(self.nt, 8, self.nt, 8, self.nt, 8).sum((1, 3, 5))
-        return cnt.sum((3, 4, 5)).reshape(-1), cand.reshape(-1)
+                acc += grid.roll(r, ax) + grid.roll(-r, ax)
+            grid = acc
+        return grid
+
+    def tile_stats(self, pos, cs):
+        """Per tile (index (tz nt + ty) nt + tx): particle count, candidate
+        pairs of the PP sum at the b2 range (particles of each IOS cell times
+        those of the IOS cells within its reach), and candidate pairs of the
+        PM3 boxes' PP sum at the b3 range (the same on cells of 2 H3 fine
+        cells, the PM3 box's IOS cells)."""
+        nt, n_ios = self.nt, 8 * self.nt
+        counts = cs[1:].long() - cs[:-1].long()
+        cnt = counts.view(nt, nt, nt, 8, 8, 8)
+        grid = cnt.permute(0, 3, 1, 4, 2, 5).reshape(n_ios, n_ios, n_ios).float()
+        r2 = 1 if self.g.cfg.b_fine <= 2.0 else 2
+        cand2 = (grid * self._box_sum(grid, r2)).view(nt, 8, nt, 8, nt, 8).sum((1, 3, 5))
+        # cells of 2 H3 fine cells: the particle's fine position from its IOS
+        # cell (tile-major key) and its offset, in units of 2 H3
+        per = int(round(1.0 / (2.0 * self.h3)))          # PM3 IOS cells per fine cell
+        nc3 = self.g.cfg.n_fine * per
+        key = torch.repeat_interleave(torch.arange(counts.numel(), device=cs.device), counts)
+        t, u = key // 512, key % 512
+        cx = (t % nt) * 8 + u % 8
+        cy = (t // nt % nt) * 8 + u // 8 % 8
+        cz = (t // (nt * nt)) * 8 + u // 64
+        off = pos.long() & 0xFFFF
+        f = [((2 * c + (off[d] >> 15)) * per + ((off[d] & 0x7FFF) * per >> 15))
+             for d, c in enumerate((cx, cy, cz))]
+        g3 = torch.bincount((f[2] * nc3 + f[1]) * nc3 + f[0], minlength=nc3 ** 3).float()
+        g3 = g3.view(nc3, nc3, nc3)
+        r3 = 1 if self.beta3 <= 2.0 else 2
+        c3 = 16 * per
+        cand3 = (g3 * self._box_sum(g3, r3)).view(nt, c3, nt, c3, nt, c3).sum((1, 3, 5))
+        return cnt.sum((3, 4, 5)).reshape(-1), cand2.reshape(-1), cand3.reshape(-1)
 
     def pm3_tiles(self, pos, cs, tiles, acc):
         """Adds the PM3 level + PP of the given tiles' particles to acc."""
@@ -777,7 +801,7 @@ class Cube2PM3:
         in `tiles`; PM3 + PP cut at b3 for those in it (default: the model's
         choice, none before calibrate())."""
         if tiles is None:
-            tiles = self.select(cs) if self.model else []
+            tiles = self.select(pos, cs) if self.model else []
         acc = self.g.pm_force(pos, cs)
         skip = torch.zeros(self.nt ** 3, dtype=torch.uint8, device=self.device)
         if len(tiles):
@@ -789,10 +813,13 @@ class Cube2PM3:
 
     def calibrate(self, pos, cs, trial=64, reps=3):
         """Measures the cost model on the device: the b2-range PP time per
-        candidate pair (the whole PP sum) and the PM3 time per particle of a
-        packed box (the `trial` heaviest tiles), and keeps it for select()."""
+        candidate pair (the whole PP sum), and the PM3 time of two packed
+        batches of `trial` tiles each (the heaviest tiles, and tiles from the
+        middle of the occupied ones), fitted as t = c_tile n_tiles + c_pp3
+        (their b3-range candidates): the mesh time per tile and the PM3 box's
+        PP time per candidate.  Kept for select()."""
         import numpy as np
-        count, cand = self.tile_stats(cs)
+        count, cand2, cand3 = self.tile_stats(pos, cs)
         stream = torch.cuda.current_stream()
 
         def timed(fn):
@@ -809,28 +836,43 @@ class Cube2PM3:
 
         acc = torch.zeros((3, pos.shape[1]), dtype=torch.float32, device=self.device)
         t_pp = timed(lambda: self.g.pp_force(pos, cs, acc))
-        heavy = torch.argsort(count, descending=True)[:trial].tolist()
-        m_trial = float(count[heavy].sum())
-        t_pm3 = timed(lambda: self.pm3_tiles(pos, cs, heavy, acc))
-        self.model = {"pp_s_per_candidate": t_pp / max(float(cand.sum()), 1.0),
-                      "pm3_s_per_particle": t_pm3 / max(m_trial, 1.0),
-                      "pp_b3_candidate_fraction": self._cand_fraction(),
-                      "t_pp_s": t_pp, "t_pm3_trial_s": t_pm3, "trial_tiles": len(heavy)}
+        c_pp = t_pp / max(float(cand2.sum()), 1.0)
+        order = torch.argsort(count, descending=True)
+        occupied = int((count > 0).sum())
+        sets = [order[:trial], order[max(0, occupied // 2 - trial // 2):][:trial]]
+        rows, ts = [], []
+        for sset in sets:
+            tl = sset.tolist()
+            ts.append(timed(lambda: self.pm3_tiles(pos, cs, tl, acc)))
+            rows.append([float(len(tl)), float(cand3[sset].sum())])
+        A, t = np.array(rows), np.array(ts)
+        try:
+            c_tile, c_pp3 = np.linalg.solve(A, t)
+        except np.linalg.LinAlgError:
+            c_tile, c_pp3 = -1.0, -1.0
+        if not (c_tile > 0 and c_pp3 > 0):       # ill-conditioned: the PP rate of the sum
+            c_pp3 = c_pp
+            c_tile = max((t[0] - c_pp3 * A[0, 1]) / A[0, 0], t[1] / A[1, 0], 1e-9)
+        self.model = {"pp_s_per_candidate": c_pp, "pm3_pp_s_per_candidate": float(c_pp3),
+                      "pm3_s_per_tile": float(c_tile), "t_pp_s": t_pp,
+                      "t_pm3_trials_s": ts, "trial_tiles": trial}
         return self.model
 
-    def _cand_fraction(self):
-        # candidate volume of the PM3 box's PP, (2 reach + 1) IOS cells of
-        # 2 H3 fine cells per axis, over that of the b2 range's PP, (2 reach
-        # + 1) IOS cells of 2 fine cells
-        r3 = 1 if self.beta3 <= 2.0 else 2
-        r2 = 1 if self.g.cfg.b_fine <= 2.0 else 2
-        return ((2 * r3 + 1) * 2 * self.h3) ** 3 / ((2 * r2 + 1) * 2.0) ** 3
-
-    def select(self, cs):
-        """Tiles whose predicted PP saving exceeds their predicted PM3 time:
-        t_pp_per_cand * cand * (1 - f3) > t_pm3_per_particle * count."""
-        count, cand = self.tile_stats(cs)
+    def predicted_change(self, pos, cs, tiles):
+        """The model's change of the force time (s) when `tiles` get PM3."""
+        _, cand2, cand3 = self.tile_stats(pos, cs)
+        t = torch.as_tensor(list(tiles), dtype=torch.long, device=cand2.device)
         md = self.model
-        save = md["pp_s_per_candidate"] * cand * (1.0 - md["pp_b3_candidate_fraction"])
-        cost = md["pm3_s_per_particle"] * count
-        return torch.nonzero(save > cost).flatten().tolist()
+        return (md["pm3_s_per_tile"] * len(tiles) + md["pm3_pp_s_per_candidate"] * float(
+            cand3[t].sum()) - md["pp_s_per_candidate"] * float(cand2[t].sum()))
+
+    def select(self, pos, cs):
+        """Tiles whose predicted b2-range PP time exceeds their predicted
+        PM3 time (mesh time per tile plus the PP at the b3 range): the rule
+        of the paper (minimal t_PM3 + t_PP per subtile), with the costs
+        measured by calibrate()."""
+        _, cand2, cand3 = self.tile_stats(pos, cs)
+        md = self.model
+        gain = (md["pp_s_per_candidate"] * cand2 - md["pm3_pp_s_per_candidate"] * cand3
+                - md["pm3_s_per_tile"])
+        return torch.nonzero(gain > 0).flatten().tolist()

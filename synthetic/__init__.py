@@ -144,6 +144,10 @@ WORKLOADS = {
     "zel128_grad": dict(n_p=128, n_fine=256, coarse_ratio=0, kind="zeldovich", rms=0.1),
     "clu512": dict(n_p=512, n_fine=1024, coarse_ratio=4, kind="clustered", rms=0.25,
                    n_spheres=8000, per_sphere=2048),
+    # the same sphere mass fraction in 8x heavier spheres (denser halos, the
+    # regime where the paper's adaptive PM3 level pays)
+    "clu256_halos": dict(n_p=256, n_fine=512, coarse_ratio=4, kind="clustered", rms=0.25,
+                         n_spheres=125, per_sphere=16384),
 }
 
 SEED_BASE = 12629

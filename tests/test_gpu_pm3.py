@@ -45,7 +45,7 @@ def field():
     pos, cs, perm = pm3.g.pack(torch.from_numpy(x).cuda())
     q = oracle.quantize(x, NG)
     xf = oracle.q_to_fine(q[:, perm.cpu().numpy().astype(np.int64)])     # GPU order
-    count, _ = pm3.tile_stats(cs)
+    count, _, _ = pm3.tile_stats(pos, cs)
     dense = torch.argsort(count, descending=True)[:5].tolist()
     return dict(m=m, cfg=cfg, pm3=pm3, pos=pos, cs=cs, xf=xf, dense=dense,
                 p=oracle.Params(n_fine=NG, coarse_ratio=4))
@@ -136,8 +136,14 @@ def test_pm3_against_two_level(field):
 def test_pm3_cost_model(field):
     pm3, pos, cs = field["pm3"], field["pos"], field["cs"]
     model = pm3.calibrate(pos, cs, trial=8, reps=2)
-    assert model["pp_s_per_candidate"] > 0 and model["pm3_s_per_particle"] > 0
-    tiles = pm3.select(cs)
+    assert model["pp_s_per_candidate"] > 0 and model["pm3_s_per_tile"] >= 0
+    tiles = pm3.select(pos, cs)
+    # the candidate counts: every particle of a tile is a candidate of
+    # itself at least, and the b3 range (5 cells of 1 fine cell) sees fewer
+    # than the b2 range (3 IOS cells of 2 fine cells) on average
+    count, cand2, cand3 = pm3.tile_stats(pos, cs)
+    assert torch.all(cand2 >= count) and torch.all(cand3 >= count)
+    assert float(cand3.sum()) < float(cand2.sum())
     a = pm3.force(pos, cs)
     assert torch.isfinite(a).all()
     assert all(0 <= t < pm3.nt ** 3 for t in tiles)
