@@ -81,6 +81,21 @@ def step_reference_bytes(n_particles: int, meshes) -> float:
     return b
 
 
+def step_compulsory_bytes(n_particles: int, meshes) -> float:
+    """HBM bytes of one force evaluation in the compulsory traffic model:
+    per level of n^3 cells, the density write (4 B/cell), one read and one
+    write per transform (the real mesh, 4 B/cell, and the half spectrum,
+    8 B per complex value, for the forward and the inverse FFT), one read of
+    the octant Green's table and one of the potential; per particle as in the
+    reference model.  No per-axis FFT reaches it (a 1024^2 plane does not fit
+    a CU's LDS), so it is a bound, not a target."""
+    b = 32.0 * n_particles
+    for n in meshes:
+        h = n // 2 + 1
+        b += 4.0 * n ** 3 + 2 * (4.0 * n ** 3 + 8.0 * h * n * n) + 4.0 * h ** 3 + 4.0 * n ** 3
+    return b
+
+
 def pair_counts():
     path = os.path.join(ROOT, "tests", "golden", "pair_counts.json")
     if os.path.exists(path):
@@ -641,6 +656,8 @@ def main():
         meshes = [w["n_fine"]] + ([w["n_fine"] // w["coarse_ratio"]] if w["coarse_ratio"] else [])
         hbm = step_reference_bytes(N, meshes)
         t_hbm = hbm / (HBM_PEAK_GBS * 1e9)
+        hbm_c = step_compulsory_bytes(N, meshes)
+        t_hbm_c = hbm_c / (HBM_PEAK_GBS * 1e9)
         t_alu = pairs * PP_VALU_PER_PAIR / VALU_LANE_OPS
         t_flop = pairs * PP_FLOPS_PER_PAIR / (VALU_FP32_TFLOPS * 1e12)
         out["step_roofline"] = {
@@ -648,7 +665,9 @@ def main():
             "t_pp_flop_ms": t_flop * 1e3, "reference_bytes": hbm,
             "pp_flops_per_pair": PP_FLOPS_PER_PAIR, "frac": (t_hbm + t_flop) * 1e3 / ms,
             "instruction_model": {"t_pp_valu_ms": t_alu * 1e3, "pp_valu_per_pair": PP_VALU_PER_PAIR,
-                                  "frac": (t_hbm + t_alu) * 1e3 / ms}}
+                                  "frac": (t_hbm + t_alu) * 1e3 / ms},
+            "compulsory_model": {"bytes": hbm_c, "t_hbm_ms": t_hbm_c * 1e3,
+                                 "frac": (t_hbm_c + t_flop) * 1e3 / ms}}
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(args.workload)
