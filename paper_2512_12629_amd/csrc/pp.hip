@@ -176,8 +176,11 @@ __global__ __launch_bounds__((PPGeo<ADJ, H>::BLOCK)) void pp_kernel(const uint16
     constexpr int kPB = PPBox<H>::PB, kPSegs = PPBox<H>::SEGS, kW = PPBox<H>::W;
     __shared__ uint32_t seg_pre[kPSegs + 1];
     __shared__ uint32_t seg_src[kPSegs];
-    __shared__ float4 xs[CAP];
-    __shared__ float4 as_[ADJ ? CAP : 1];
+    // staged particles; the adjoint interleaves each position with its
+    // cotangent (xs[2 v], xs[2 v + 1]), so that both reads of a pair share one
+    // address register
+    constexpr int XS = ADJ ? 2 : 1;
+    __shared__ float4 xs[XS * CAP];
     __shared__ uint32_t cst[kTileCells + 1];     // own cells: particle starts (tile-relative)
     __shared__ uint32_t scan_sh[kPPBlock / 64 + 1];
     __shared__ int chunk_sh, tile_sh;
@@ -305,11 +308,11 @@ __global__ __launch_bounds__((PPGeo<ADJ, H>::BLOCK)) void pp_kernel(const uint16
                         q.y = (float)(2 * (by - H)) + (float)o[i][1] * inv;
                         q.z = (float)(2 * (bz - H)) + (float)o[i][2] * inv;
                         q.w = 0.0f;
-                        xs[pre_k[k] + i] = q;
+                        xs[XS * (pre_k[k] + i)] = q;
                         if (ADJ) {
                             const uint32_t p = src[k] + i;
-                            as_[pre_k[k] + i] = make_float4(abar[p], abar[(int64_t)n + p],
-                                                            abar[2 * (int64_t)n + p], 0.f);
+                            xs[XS * (pre_k[k] + i) + 1] = make_float4(abar[p], abar[(int64_t)n + p],
+                                                                      abar[2 * (int64_t)n + p], 0.f);
                         }
                     }
                 }
@@ -350,8 +353,8 @@ __global__ __launch_bounds__((PPGeo<ADJ, H>::BLOCK)) void pp_kernel(const uint16
                         q.z = (float)(2 * (bz - H)) + (float)o[k][2] * inv;
                         q.w = 0.0f;
                         const uint32_t v = v0 + k * kPPBlock;
-                        xs[v - vb] = q;
-                        if (ADJ) as_[v - vb] = ab[k];
+                        xs[XS * (v - vb)] = q;
+                        if (ADJ) xs[XS * (v - vb) + 1] = ab[k];
                     }
                 }
             }
@@ -366,7 +369,7 @@ __global__ __launch_bounds__((PPGeo<ADJ, H>::BLOCK)) void pp_kernel(const uint16
                 if (staged) {
                     // the particle itself is staged: same exact floats, no HBM read
                     const int su = (bz * kPB + by) * kPB + bx;
-                    const float4 qi = xs[seg_pre[su] + (lp - cst[u]) - vb];
+                    const float4 qi = xs[XS * (seg_pre[su] + (lp - cst[u]) - vb)];
                     xi = qi.x;
                     yi = qi.y;
                     zi = qi.z;
@@ -392,15 +395,22 @@ __global__ __launch_bounds__((PPGeo<ADJ, H>::BLOCK)) void pp_kernel(const uint16
                         float fx = 0.f, fy = 0.f, fz = 0.f;
                         uint32_t v = v0;
                         if (ADJ) {
-                            for (; v + 1 < v1; v += 2) {
-                                const float4 qa = xs[v], aa = as_[v], qb = xs[v + 1], ab = as_[v + 1];
-                                pair_adjoint(qa.x - xi, qa.y - yi, qa.z - zi, aa.x - aix, aa.y - aiy,
-                                             aa.z - aiz, negc, fx, fy, fz);
-                                pair_adjoint(qb.x - xi, qb.y - yi, qb.z - zi, ab.x - aix, ab.y - aiy,
-                                             ab.z - aiz, negc, fx, fy, fz);
+                            // four pairs per iteration: the loop control and the LDS
+                            // latency spread over more work
+                            for (; v + 3 < v1; v += 4) {
+                                float4 q[4], a[4];
+#pragma unroll
+                                for (int t = 0; t < 4; ++t) {
+                                    q[t] = xs[2 * (v + t)];
+                                    a[t] = xs[2 * (v + t) + 1];
+                                }
+#pragma unroll
+                                for (int t = 0; t < 4; ++t)
+                                    pair_adjoint(q[t].x - xi, q[t].y - yi, q[t].z - zi, a[t].x - aix,
+                                                 a[t].y - aiy, a[t].z - aiz, negc, fx, fy, fz);
                             }
-                            if (v < v1) {
-                                const float4 qa = xs[v], aa = as_[v];
+                            for (; v < v1; ++v) {
+                                const float4 qa = xs[2 * v], aa = xs[2 * v + 1];
                                 pair_adjoint(qa.x - xi, qa.y - yi, qa.z - zi, aa.x - aix, aa.y - aiy,
                                              aa.z - aiz, negc, fx, fy, fz);
                             }
