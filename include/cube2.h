@@ -65,7 +65,8 @@ enum cube2_status_code {
     CUBE2_EWORKSPACE = -3,    /* tables or work buffer too small */
     CUBE2_EOVERFLOW = -4,     /* deposit accumulator could overflow (status) */
     CUBE2_EHIP = -5,          /* a HIP runtime call failed */
-    CUBE2_ESTATE = -6         /* tables not initialised */
+    CUBE2_ESTATE = -6,        /* tables not initialised */
+    CUBE2_ENONFINITE = -7     /* kick-drift met a non-finite velocity (status) */
 };
 
 enum cube2_flags {
@@ -325,7 +326,10 @@ int cube2_force_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *ce
  * wrapped periodically, then a stable re-sort by IOS cell.  Inputs (device):
  * pos_in, cell_start_in, vel_in (3*n), acc (3*n).  Outputs (device, must not
  * alias the inputs): pos_out, cell_start_out, vel_out, perm_out (perm_out[i] =
- * input slot of output particle i). */
+ * input slot of output particle i).  A component whose v' is not finite, or
+ * whose displacement exceeds 2^62 position units, is not moved (its v' is
+ * still stored) and the device status records CUBE2_ENONFINITE for
+ * cube2_status; the call itself returns CUBE2_OK. */
 int cube2_kick_drift(cube2_ctx *ctx, const uint16_t *pos_in, const uint32_t *cell_start_in,
                      const float *vel_in, const float *acc, int64_t n, double kick, double drift,
                      uint16_t *pos_out, uint32_t *cell_start_out, float *vel_out,
@@ -360,8 +364,9 @@ int cube2_vel_decode(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_s
                      const int16_t *vq, const float *v_bulk, const float *v_scale, float *vel,
                      cube2_stream_t stream);
 
-/* Synchronise the stream and return the device status (CUBE2_OK or
- * CUBE2_EOVERFLOW), clearing it. */
+/* Synchronise the stream and return the device status, clearing it:
+ * CUBE2_OK, CUBE2_ENONFINITE (a kick-drift met a non-finite kicked velocity
+ * or displacement; it has priority) or CUBE2_EOVERFLOW. */
 int cube2_status(cube2_ctx *ctx, cube2_stream_t stream);
 
 /* ---- adjoints ---------------------------------------------------------- */

@@ -34,7 +34,8 @@ CUBE2_ASSIGN_TSC = 4
 CUBE2_ISOLATED = 8
 _ERRORS = {0: "ok", -1: "invalid argument", -2: "unsupported configuration",
            -3: "tables or work buffer too small", -4: "deposit overflow guard",
-           -5: "HIP runtime error", -6: "tables not initialised"}
+           -5: "HIP runtime error", -6: "tables not initialised",
+           -7: "non-finite kick-drift"}
 
 
 class Cube2Error(RuntimeError):

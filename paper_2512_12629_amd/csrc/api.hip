@@ -532,6 +532,7 @@ int cube2_status(cube2_ctx *ctx, cube2_stream_t stream) {
     CUBE2_CHECK_HIP(hipStreamSynchronize(s));
     CUBE2_CHECK_HIP(hipMemsetAsync(status_word(ctx), 0, 4, s));
     CUBE2_CHECK_HIP(hipStreamSynchronize(s));
+    if (word & kStatusNonFinite) return CUBE2_ENONFINITE;
     return word ? CUBE2_EOVERFLOW : CUBE2_OK;
 }
 
@@ -658,6 +659,7 @@ const char *cube2_strerror(int code) {
         case CUBE2_EUNSUPPORTED: return "unsupported configuration";
         case CUBE2_EWORKSPACE: return "tables or work buffer too small";
         case CUBE2_EOVERFLOW: return "deposit accumulator overflow guard tripped";
+        case CUBE2_ENONFINITE: return "kick-drift met a non-finite velocity or displacement";
         case CUBE2_EHIP: return "HIP runtime error";
         case CUBE2_ESTATE: return "tables not initialised";
         default: return "unknown status code";

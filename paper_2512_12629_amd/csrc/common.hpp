@@ -93,6 +93,10 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 WorkLayout work_layout(const cube2_ctx *ctx, int64_t n);
 
+// bits of the device status word
+constexpr uint32_t kStatusOverflow = 1u;    // a deposit or codec accumulator could overflow
+constexpr uint32_t kStatusNonFinite = 2u;   // a kick-drift met a non-finite velocity or step
+
 inline uint32_t *status_word(const cube2_ctx *ctx) {
     return reinterpret_cast<uint32_t *>(ctx->tables);
 }

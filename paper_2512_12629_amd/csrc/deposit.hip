@@ -302,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
                 seg_src[s_last] + (seg_pre[s_last + 1] - seg_pre[s_last]) - seg_src[s_first];
             const uint32_t fine_max = P == 3 ? (1u << 17) : (1u << 19);
             const uint32_t own_max = P == 3 ? (1u << 14) : (1u << 16);
-            if ((FINE && total >= fine_max) || (COARSE && own >= own_max)) atomicOr(status, 1u);
+            if ((FINE && total >= fine_max) || (COARSE && own >= own_max)) atomicOr(status, kStatusOverflow);
         }
 
         // The loop runs wave-uniformly (every lane of a wave takes the same

@@ -7,7 +7,10 @@
 // v' = v + kick * a and dq = rint(drift * v' * 2^15) are evaluated in FP64
 // with separately rounded operations (FMA contraction is switched off in
 // these kernels), so the integer displacement and the stored velocity are
-// deterministic functions of the FP32 inputs.
+// deterministic functions of the FP32 inputs.  A particle whose v' or
+// displacement is not finite (a non-finite acceleration or velocity, or a
+// displacement beyond 2^62 units) is not moved, and the status word records
+// it (cube2_status then returns CUBE2_ENONFINITE).
 #include "common.hpp"
 
 namespace cube2 {
@@ -17,7 +20,7 @@ __global__ __launch_bounds__(kBlock) void kick_drift_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs,
     const float *__restrict__ vel, const float *__restrict__ acc, int n, int nt, int n_f,
     double kick, double drift, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-    uint16_t *__restrict__ offs) {
+    uint16_t *__restrict__ offs, uint32_t *__restrict__ status) {
 #pragma clang fp contract(off)
     __shared__ uint32_t cst[kTileCells + 1];
     int tx, ty, tz;
@@ -28,6 +31,7 @@ __global__ __launch_bounds__(kBlock) void kick_drift_kernel(
     __syncthreads();
     const int64_t span = (int64_t)n_f << kFracBits;
     const int cbase[3] = {tx * kTileIos, ty * kTileIos, tz * kTileIos};
+    bool bad = false;
     for (uint32_t p = cst[0] + tid; p < cst[kTileCells]; p += kBlock) {
         const int u = seg_search(cst, kTileCells, p);
         const int uc[3] = {u & 7, (u >> 3) & 7, u >> 6};
@@ -37,7 +41,11 @@ __global__ __launch_bounds__(kBlock) void kick_drift_kernel(
             const int64_t i = (int64_t)d * n + p;
             const double kv = kick * (double)acc[i];
             const double v1 = (double)vel[i] + kv;
-            const double dq = rint((drift * v1) * 32768.0);
+            double dq = rint((drift * v1) * 32768.0);
+            if (!(fabs(dq) < 0x1p62)) {   // also NaN: the particle stays where it is
+                dq = 0.0;
+                bad = true;
+            }
             int64_t q = ((int64_t)(cbase[d] + uc[d]) << 16) + pos[i];
             q = (q + (int64_t)dq) % span;
             if (q < 0) q += span;
@@ -47,6 +55,7 @@ __global__ __launch_bounds__(kBlock) void kick_drift_kernel(
         keys[p] = cell_key(c[0], c[1], c[2], nt);
         vals[p] = p;
     }
+    if (bad) atomicOr(status, kStatusNonFinite);
 }
 
 __global__ void kick_gather(const int32_t *__restrict__ perm, const float *__restrict__ vel,
@@ -144,7 +153,7 @@ int launch_kick_drift(cube2_ctx *ctx, const uint16_t *pos_in, const uint32_t *cs
         kick_drift_kernel<<<(unsigned)(nt * nt * nt), kBlock, 0, s>>>(
             pos_in, cs_in, vel_in, acc, n, nt, ctx->n_f, kick, drift,
             reinterpret_cast<uint32_t *>(work + L.keys), reinterpret_cast<uint32_t *>(work + L.vals),
-            offs);
+            offs, status_word(ctx));
         CUBE2_LAUNCH_CHECK();
     }
     int r = launch_sort_by_cell(ctx, n, offs, pos_out, cs_out, perm_out, work, L, s);

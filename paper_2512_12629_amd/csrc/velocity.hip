@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void vel_bulk_kernel(
     for (int i = tid; i < ncell; i += kBlock) {
         const uint32_t c = cnt[i];
         // 2^22 values below 2^41 each keep the sum within 63 bits
-        if (c >= (1u << 22)) atomicOr(status, 1u);
+        if (c >= (1u << 22)) atomicOr(status, kStatusOverflow);
         const int64_t g = bulk_index(tx, ty, tz, i, ct, nb);
         const int64_t m3 = (int64_t)nb * nb * nb;
 #pragma unroll

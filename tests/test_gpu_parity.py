@@ -338,6 +338,38 @@ def test_overflow_guard_sets_status():
     assert c.status() == 0           # cleared by the read
 
 
+def test_nonfinite_kick_sets_status():
+    import paper_2512_12629_amd as m
+    # A NaN and an infinite acceleration: those two particles keep their
+    # positions, every other particle moves exactly as in a run where the two
+    # accelerations are zero, and the status reports it once.
+    rng = np.random.default_rng(11)
+    n = 5000
+    x = rng.random((3, n)).astype(np.float32)
+    c = m.Cube2(m.Config(n_fine=32), n_max=n)
+    pos, cs, _ = c.pack(torch.from_numpy(x).cuda())
+    vel = (0.2 * rng.standard_normal((3, n))).astype(np.float32)
+    acc = rng.standard_normal((3, n)).astype(np.float32)
+    acc[:, 17] = 0.0
+    acc[:, 2500] = 0.0
+    vel[:, 17] = 0.0
+    vel[:, 2500] = 0.0
+    ok = c.kick_drift(pos, cs, torch.from_numpy(vel).cuda(), torch.from_numpy(acc).cuda(), 0.05, 0.3)
+    assert c.status() == 0
+    acc[1, 17] = np.nan
+    acc[2, 2500] = np.inf
+    bad = c.kick_drift(pos, cs, torch.from_numpy(vel).cuda(), torch.from_numpy(acc).cuda(), 0.05, 0.3)
+    assert c.status() == -7          # CUBE2_ENONFINITE
+    assert c.status() == 0           # cleared by the read
+    for a, b in zip(ok[:2], bad[:2]):
+        assert torch.equal(a, b)
+    assert torch.equal(ok[3], bad[3])
+    v_ok, v_bad, perm = _np(ok[2]), _np(bad[2]), _np(ok[3])
+    keep = (perm != 17) & (perm != 2500)
+    assert np.array_equal(v_ok[:, keep], v_bad[:, keep])
+    assert not np.isfinite(v_bad[:, ~keep]).all()
+
+
 def test_empty_input():
     import paper_2512_12629_amd as m
     c = m.Cube2(m.Config(n_fine=32), n_max=1)
