@@ -61,9 +61,9 @@ PP_FLOPS_PER_PAIR = 28
 
 
 # VALU instructions per candidate pair of the compiled forward PP inner loop
-# (gfx950 ISA: 47 per iteration of the two-pair unrolled loop), and the
+# (gfx950 ISA: 42 per iteration of the two-pair unrolled loop), and the
 # unpacked FP32 VALU issue rate (lane-ops per second).
-PP_VALU_PER_PAIR = 23.5
+PP_VALU_PER_PAIR = 21.0
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 

@@ -66,14 +66,18 @@ template <bool ADJ, int H> struct PPGeo {
 // The FP32 forward kernel evaluates g as a function of s = r^2 instead, which
 // needs neither a square root nor r^-3.  Since g vanishes like (b_f - r)^5 at
 // the cutoff, and sparse particles often have all their neighbours close to
-// it, the table holds h = g / (b_f^2 - s)^5, smooth and nonzero up to and
-// beyond the cutoff (there the factorised form gives h = Q(1 - r/b_f) /
-// (r^3 (b_f (b_f + r))^5), continued analytically past b_f), scaled by
-// b_f^10, and the kernel forms g = (h b_f^10) w^5 with w = 1 - s/b_f^2
-// clamped to [0, 1]: exact zero beyond the cutoff and the same relative
-// accuracy near it as elsewhere.  s is cut at its float exponent and
-// top 4 mantissa bits (1/16 of an octave, s in [2^-31, 64)); on each piece h
-// is the cubic through its values at the 4 Chebyshev nodes (fitted in FP64
+// it, the table does not hold g itself: with h = g / (b_f^2 - s)^5, smooth and
+// nonzero up to and beyond the cutoff (there the factorised form gives h =
+// Q(1 - r/b_f) / (r^3 (b_f (b_f + r))^5), continued analytically past b_f),
+// it holds H = h b_f^10 w = g / w^4 with w = 1 - s/b_f^2, still smooth (one
+// simple zero at the cutoff, continued linearly past it), and the kernel
+// forms g = H w^4 with w clamped to [0, 1]: exact zero beyond the cutoff.
+// Near the cutoff the fit of H errs like 1/w relative (7e-7 at w = 1/32 on
+// the row s in [3.75, 3.875) for b_f = 2), as the FP32 rounding of s does
+// anyway (b_f^2 - s turns it into 6e-8 / w per power of w); with more powers
+// of w in the table the cubic would have to follow a multiple zero.  s is cut
+// at its float exponent and top 4 mantissa bits (1/16 of an octave, s in
+// [2^-31, 2^7)); on each piece H is the cubic through its values at the 4 Chebyshev nodes (fitted in FP64
 // on the host from eq. (2) evaluated in extended precision).  For exact s the
 // table's g is within 8e-7 of the true g, relative; FP32 rounding of s adds
 // its own part near the cutoff, as rounding of r does in any evaluation.  The
@@ -99,7 +103,7 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
 }
 
 // g(r) * D accumulated into (fx, fy, fz) from the s-indexed table (LDS).
-// The table holds h b_f^10, and w = 1 - s/b_f^2 is formed as one FMA with
+// The table holds H = g / w^4, and w = 1 - s/b_f^2 is formed as one FMA with
 // the result clamped to [0, 1] (negc = -1/b_f^2 rounded away from zero, so
 // that w = 0 for every s >= b_f^2).
 __device__ __forceinline__ float unit_clamp(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
@@ -113,7 +117,7 @@ __device__ __forceinline__ void pair_accumulate(float dx, float dy, float dz, fl
     const float h = fmaf(fmaf(fmaf(c.w, z, c.z), z, c.y), z, c.x);
     const float w = unit_clamp(fmaf(s, negc, 1.0f));
     const float w2 = w * w;
-    const float g = (h * w) * (w2 * w2);
+    const float g = h * (w2 * w2);
     fx = fmaf(g, dx, fx);
     fy = fmaf(g, dy, fy);
     fz = fmaf(g, dz, fz);
@@ -121,13 +125,12 @@ __device__ __forceinline__ void pair_accumulate(float dx, float dy, float dz, fl
 
 // Adjoint of one pair for the cotangents: out += J(D) u with u = abar_j -
 // abar_i and J = d(g D)/dD = g I + 2 g_s D D^T, g_s = dg/ds.  It reads the
-// forward's table: H = h b_f^10 = g / (1 - s/b_f^2)^5 and, by synthetic
+// forward's table: H = g / w^4, w = 1 - s/b_f^2, and, by synthetic
 // division of the same cubic, dH/dz, with z the local variable of the row
 // (s = 2^e (1 + z)), so H_s = (dH/dz) 2^-e; one 16-byte table read per pair
-// (the LDS reads, not the arithmetic, limit this kernel).  With w = 1 -
-// s/b_f^2 clamped to [0, 1] as in pair_accumulate: g = H w^5 and 2 g_s =
-// w^4 (2 H_s w + 10 negc H), negc = -1/b_f^2.  Every term enters the
-// accumulators through an FMA.
+// (the LDS reads, not the arithmetic, limit this kernel).  With w clamped to
+// [0, 1] as in pair_accumulate: g = H w^4 and 2 g_s = w^3 (2 H_s w + 8 negc
+// H), negc = -1/b_f^2.  Every term enters the accumulators through an FMA.
 __device__ __forceinline__ void pair_adjoint(float dx, float dy, float dz, float ux, float uy,
                                              float uz, float negc, float &ox, float &oy,
                                              float &oz) {
@@ -143,9 +146,8 @@ __device__ __forceinline__ void pair_adjoint(float dx, float dy, float dz, float
     h = fmaf(h, z, c.x);
     const float w = unit_clamp(fmaf(s, negc, 1.0f));
     const float w2 = w * w;
-    const float w4 = w2 * w2;
-    const float g = (h * w) * w4;
-    const float gs2 = w4 * fmaf(hz * inv2e2, w, (10.0f * negc) * h);  // 2 g_s
+    const float g = h * (w2 * w2);
+    const float gs2 = (w2 * w) * fmaf(hz * inv2e2, w, (8.0f * negc) * h);  // 2 g_s
     const float du = fmaf(dz, uz, fmaf(dy, uy, dx * ux)) * gs2;
     ox = fmaf(du, dx, fmaf(g, ux, ox));
     oy = fmaf(du, dy, fmaf(g, uy, oy));
@@ -393,35 +395,45 @@ __global__ __launch_bounds__((PPGeo<ADJ, H>::BLOCK)) void pp_kernel(const uint16
                         const int sm = ((bz + oz) * kPB + (by + oy)) * kPB + bx;
                         const uint32_t v0 = seg_pre[sm - H] - vb, v1 = seg_pre[sm + H + 1] - vb;
                         float fx = 0.f, fy = 0.f, fz = 0.f;
-                        uint32_t v = v0;
                         if (ADJ) {
                             // four pairs per iteration: the loop control and the LDS
-                            // latency spread over more work
-                            for (; v + 3 < v1; v += 4) {
-                                float4 q[4], a[4];
+                            // latency spread over more work.  The loops run on the
+                            // LDS address against precomputed bounds, never below xs
+                            // (LDS addresses compare unsigned).
+                            const float4 *q = xs + 2 * v0;
+                            const float4 *const qe = xs + 2 * v1;
+                            const float4 *const qe4 = xs + 2 * (v1 >= v0 + 3 ? v1 - 3 : v0);
+                            for (; q < qe4; q += 8) {
+                                float4 x[4], a[4];
 #pragma unroll
                                 for (int t = 0; t < 4; ++t) {
-                                    q[t] = xs[2 * (v + t)];
-                                    a[t] = xs[2 * (v + t) + 1];
+                                    x[t] = q[2 * t];
+                                    a[t] = q[2 * t + 1];
                                 }
 #pragma unroll
                                 for (int t = 0; t < 4; ++t)
-                                    pair_adjoint(q[t].x - xi, q[t].y - yi, q[t].z - zi, a[t].x - aix,
+                                    pair_adjoint(x[t].x - xi, x[t].y - yi, x[t].z - zi, a[t].x - aix,
                                                  a[t].y - aiy, a[t].z - aiz, negc, fx, fy, fz);
                             }
-                            for (; v < v1; ++v) {
-                                const float4 qa = xs[2 * v], aa = xs[2 * v + 1];
+                            for (; q < qe; q += 2) {
+                                const float4 qa = q[0], aa = q[1];
                                 pair_adjoint(qa.x - xi, qa.y - yi, qa.z - zi, aa.x - aix, aa.y - aiy,
                                              aa.z - aiz, negc, fx, fy, fz);
                             }
                         } else {
-                            for (; v + 1 < v1; v += 2) {
-                                const float4 qa = xs[v], qb = xs[v + 1];
+                            // two pairs per iteration.  The loop runs on the LDS
+                            // address against a precomputed bound, never below xs
+                            // (one add and one compare per trip).
+                            const float4 *q = xs + v0;
+                            const float4 *const qend = xs + v1;
+                            const float4 *const qe = xs + (v1 > v0 ? v1 - 1 : v0);
+                            for (; q < qe; q += 2) {
+                                const float4 qa = q[0], qb = q[1];
                                 pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, negc, fx, fy, fz);
                                 pair_accumulate(qb.x - xi, qb.y - yi, qb.z - zi, negc, fx, fy, fz);
                             }
-                            if (v < v1) {
-                                const float4 qa = xs[v];
+                            if (q < qend) {
+                                const float4 qa = q[0];
                                 pair_accumulate(qa.x - xi, qa.y - yi, qa.z - zi, negc, fx, fy, fz);
                             }
                         }
@@ -514,17 +526,17 @@ long double pair_h_direct(double b_pp, double b_f, double rd) {
     return (r_over_r(b_pp) - r_over_r(bf)) / (w * w * w * w * w);
 }
 
-// A table of H = h b_f^10 = g / (1 - s/b_f^2)^5 by s = r^2 (see the comments above
-// pair_accumulate and pair_adjoint): row t covers s in [2^e (1 + i/2^mb),
-// 2^e (1 + (i+1)/2^mb)) with (e + 127) 2^mb + i = t + row0, and holds the
-// polynomial of degree D-1 in z in [0, 2^-mb) through h at the D Chebyshev
-// nodes, solved in FP64 in the variable y = 2^mb z and rescaled.  Built from
+// A table of H = g / w^4 = h b_f^10 w, w = 1 - s/b_f^2, by s = r^2 (see the
+// comments above pair_accumulate and pair_adjoint): row t covers s in
+// [2^e (1 + i/2^mb), 2^e (1 + (i+1)/2^mb)) with (e + 127) 2^mb + i = t + row0,
+// and holds the polynomial of degree D-1 in z in [0, 2^-mb) through H at the
+// D Chebyshev nodes, solved in FP64 in the variable y = 2^mb z and rescaled.  Built from
 // eq. (2) directly (extended precision), independent of the r grid; rows
 // beyond the cutoff are zero.
 void fit_h_rows(const cube2_ctx *ctx, int mb, int D, int row0, int nrows, int row_floats,
                 std::vector<float> &out) {
     const double pi = 3.14159265358979323846, bf = ctx->cfg.b_fine;
-    const long double bf10 = std::pow((long double)bf, 10);  // rows hold H = h b_f^10
+    const long double bf10 = std::pow((long double)bf, 10);  // rows hold H = h b_f^10 w
     std::vector<double> yn(D);
     for (int j = 0; j < D; ++j) yn[j] = 0.5 + 0.5 * std::cos(pi * (j + 0.5) / D);
     out.assign((size_t)nrows * row_floats, 0.0f);
@@ -537,7 +549,8 @@ void fit_h_rows(const cube2_ctx *ctx, int mb, int D, int row0, int nrows, int ro
             const double sv = scale * (1.0 + (i + yn[j]) * inv);
             double p = 1.0;
             for (int k = 0; k < D; ++k, p *= yn[j]) A[j][k] = p;
-            A[j][D] = (double)(pair_h_direct(ctx->cfg.b_pp, bf, std::sqrt(sv)) * bf10);
+            const long double w = 1.0L - (long double)sv / ((long double)bf * bf);
+            A[j][D] = (double)(pair_h_direct(ctx->cfg.b_pp, bf, std::sqrt(sv)) * bf10 * w);
         }
         for (int c = 0; c < D; ++c) {  // Gauss-Jordan, partial pivoting
             int pv = c;
@@ -738,7 +751,7 @@ extern "C" int cube2_pair_law_f32(const cube2_ctx *ctx, const float *d, float *g
         const float h = std::fmaf(std::fmaf(std::fmaf(c[3], z, c[2]), z, c[1]), z, c[0]);
         const float w = std::fmin(std::fmax(std::fmaf(s, ctx->pp_negc, 1.0f), 0.0f), 1.0f);
         const float w2 = w * w;
-        g[i] = (h * w) * (w2 * w2);
+        g[i] = h * (w2 * w2);
     }
     return CUBE2_OK;
 }
@@ -771,9 +784,8 @@ extern "C" int cube2_pair_jacobian_f32(const cube2_ctx *ctx, const float *d, flo
         h = std::fmaf(h, z, c[0]);
         const float w = std::fmin(std::fmax(std::fmaf(s, ctx->pp_negc, 1.0f), 0.0f), 1.0f);
         const float w2 = w * w;
-        const float w4 = w2 * w2;
-        g[i] = (h * w) * w4;
-        gs[i] = 0.5f * (w4 * std::fmaf(hz * inv2e2, w, (10.0f * ctx->pp_negc) * h));
+        g[i] = h * (w2 * w2);
+        gs[i] = 0.5f * ((w2 * w) * std::fmaf(hz * inv2e2, w, (8.0f * ctx->pp_negc) * h));
     }
     return CUBE2_OK;
 }
