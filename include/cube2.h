@@ -41,8 +41,9 @@
  *
  * Errors.  Every call returns 0 (CUBE2_OK) or a negative code.  Argument
  * errors are detected on the host before anything is enqueued.  Device-side
- * conditions (a deposit accumulator that could overflow) set bits in the
- * device status word, which cube2_status() reports and clears.  Nothing is
+ * conditions (a deposit or codec accumulator that could overflow, a
+ * kick-drift that met a non-finite velocity) set bits in the device status
+ * word, which cube2_status() reports and clears.  Nothing is
  * printed and no exception crosses the ABI.
  */
 #ifndef CUBE2_H
