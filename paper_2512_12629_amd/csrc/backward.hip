@@ -51,8 +51,15 @@ __device__ __forceinline__ float fixed_scale(const unsigned int *amax_bits, floa
     return ldexpf(1.0f, min(41 - e, 100));
 }
 
+// rint(v) as a 64-bit two's-complement integer (half to even), |v| < 2^51:
+// v is exact in FP64, adding 1.5 * 2^52 rounds it to an integer and leaves
+// that integer in the low mantissa bits, and the exponent bits cancel in the
+// difference of the two bit patterns.  Four instructions instead of the
+// eleven of a float-to-int64 conversion; the same integer.
 __device__ __forceinline__ unsigned long long to_fixed(float v) {
-    return (unsigned long long)__float2ll_rn(v);
+    const double m = 6755399441055744.0;   // 1.5 * 2^52
+    const double t = (double)v + m;
+    return (unsigned long long)(__double_as_longlong(t) - __double_as_longlong(m));
 }
 
 // ---------------------------------------------------------------------------
@@ -69,10 +76,14 @@ constexpr int kAN3 = kAN * kAN * kAN;
 constexpr int kPhiBlock = 512;
 // IOS cells per axis whose particles reach the 20^3 nodes: [c0-2, c0+9) for
 // CIC, [c0-2, c0+10) for TSC (a particle in fine cell j feeds j-1 .. j+2)
+// LUT: staged particles whose box cell is looked up once per tile (not in
+// each of the three passes), as many as fit beside the rest at two
+// workgroups per CU
 template <int P> struct PhiGeo {
     static constexpr int AB = kTileIos + (P == 3 ? 4 : 3);   // 11 or 12
     static constexpr int SEGS = AB * AB * AB;
     static constexpr int SEG_PER_THREAD = (SEGS + kPhiBlock - 1) / kPhiBlock;
+    static constexpr int LUT = P == 3 ? 1984 : 3584;
 };
 
 template <int P>
@@ -86,6 +97,7 @@ __global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
     __shared__ uint32_t seg_src[kASegs];
     __shared__ unsigned long long A[kAN3];   // one component at a time, fixed point
     __shared__ uint32_t scan_sh[kPhiBlock / 64 + 1];
+    __shared__ uint16_t lut[PhiGeo<P>::LUT];   // box cell of each staged particle
     int tx, ty, tz;
     tile_of_block(blockIdx.x, nt, tx, ty, tz);
     const int tid = threadIdx.x;
@@ -118,6 +130,11 @@ __global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
         pre += cnt[k];
     }
     if (tid == 0) seg_pre[kASegs] = total;
+    // the box cell of every staged particle, searched once for the three passes
+    const bool use_lut = total <= (uint32_t)PhiGeo<P>::LUT;   // block-uniform
+    __syncthreads();
+    if (use_lut)
+        for (uint32_t v = tid; v < total; v += kPhiBlock) lut[v] = (uint16_t)seg_search(seg_pre, kASegs, v);
     const float S = fixed_scale(amax_bits, c), invS = 1.0f / S;
     const float cS = c * S;
     const float inv = 1.0f / 32768.0f;
@@ -139,7 +156,7 @@ __global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
                 const uint32_t v = v0 + k * kPhiBlock;
-                sg[k] = v < total ? seg_search(seg_pre, kASegs, v) : -1;
+                sg[k] = v >= total ? -1 : (use_lut ? (int)lut[v] : seg_search(seg_pre, kASegs, v));
             }
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
