@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
     const bool use_lut = total <= (uint32_t)PhiGeo<P>::LUT;   // block-uniform
     __syncthreads();
     if (use_lut)
-        for (uint32_t v = tid; v < total; v += kPhiBlock) lut[v] = (uint16_t)seg_search(seg_pre, kASegs, v);
+        for (uint32_t v = tid; v < total; v += kPhiBlock) lut[v] = (uint16_t)seg_search_n<kASegs>(seg_pre, v);
     const float S = fixed_scale(amax_bits, c), invS = 1.0f / S;
     const float cS = c * S;
     const float inv = 1.0f / 32768.0f;
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
                 const uint32_t v = v0 + k * kPhiBlock;
-                sg[k] = v >= total ? -1 : (use_lut ? (int)lut[v] : seg_search(seg_pre, kASegs, v));
+                sg[k] = v >= total ? -1 : (use_lut ? (int)lut[v] : seg_search_n<kASegs>(seg_pre, v));
             }
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
         int j[3] = {0, 0, 0};   // first footprint node, tile-footprint coordinates
         float w[3][P] = {}, ab[3] = {0.f, 0.f, 0.f};
         if (valid) {
-            const int u = seg_search(cst, kTileCells, p);
+            const int u = seg_search_n<kTileCells>(cst, p);
             const int uc[3] = {u & 7, (u >> 3) & 7, u >> 6};
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -464,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void xbar_gather_kernel(
     }
     __syncthreads();
     for (uint32_t p = cst[0] + tid; p < cst[kTileCells]; p += kBlock) {
-        const int u = seg_search(cst, kTileCells, p);
+        const int u = seg_search_n<kTileCells>(cst, p);
         const int uc[3] = {u & 7, (u >> 3) & 7, u >> 6};
         int jf[3], jc[3];
         float wf[3][P], dwf[3][P], wc[3][P], dwc[3][P], ab[3];

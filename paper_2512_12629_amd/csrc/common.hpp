@@ -163,6 +163,31 @@ __device__ __forceinline__ int seg_search(const uint32_t *pre, int cnt, uint32_t
     return lo;
 }
 
+// The same index for a count known at compile time: the last u in [0, CNT)
+// with pre[u] <= v, found bit by bit from the highest power of two below
+// CNT (pre non-decreasing, so pre[u] <= v holds exactly up to the answer).
+// Unrolled and branch-free: no loop control, and the LDS reads of
+// independent searches in one thread interleave.
+template <int CNT>
+__device__ __forceinline__ int seg_search_n(const uint32_t *pre, uint32_t v) {
+    static_assert(CNT >= 1, "empty range");
+    constexpr int TOP = [] {
+        int t = 1;
+        while (2 * t < CNT) t *= 2;
+        return CNT > 1 ? t : 0;
+    }();
+    int lo = 0;
+#pragma unroll
+    for (int step = TOP; step > 0; step >>= 1) {
+        if constexpr ((CNT & (CNT - 1)) == 0) {
+            if (pre[lo + step] <= v) lo += step;   // lo + step < CNT always
+        } else {
+            if (lo + step < CNT && pre[lo + step] <= v) lo += step;
+        }
+    }
+    return lo;
+}
+
 // Block-wide exclusive scan of one uint32 per thread (blockDim == BLOCK).
 template <int BLOCK = kBlock>
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh /*BLOCK/64+1*/,

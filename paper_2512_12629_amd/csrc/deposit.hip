@@ -317,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
                 const uint32_t v = w0 + k * kBlock + lane;
-                sg[k] = v < total ? seg_search(seg_pre, kSegs, v) : -1;
+                sg[k] = v < total ? seg_search_n<kSegs>(seg_pre, v) : -1;
             }
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {

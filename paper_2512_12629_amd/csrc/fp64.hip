@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kBlock) void pp64_kernel(
     __syncthreads();
     const uint32_t p0 = cst[0], p1 = cst[kTileCells];
     for (uint32_t p = p0 + threadIdx.x; p < p1; p += kBlock) {
-        const int u = seg_search(cst, kTileCells, p);
+        const int u = seg_search_n<kTileCells>(cst, p);
         const int c[3] = {tx * kTileIos + (u & 7), ty * kTileIos + ((u >> 3) & 7),
                           tz * kTileIos + (u >> 6)};
         int oi[3];

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
             const uint32_t p = pb + k * kBlock;
-            ub[k] = p < p1 ? seg_search(cst, kTileCells, p) : -1;
+            ub[k] = p < p1 ? seg_search_n<kTileCells>(cst, p) : -1;
         }
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kBlock) void kick_drift_kernel(
     const int cbase[3] = {tx * kTileIos, ty * kTileIos, tz * kTileIos};
     bool bad = false;
     for (uint32_t p = cst[0] + tid; p < cst[kTileCells]; p += kBlock) {
-        const int u = seg_search(cst, kTileCells, p);
+        const int u = seg_search_n<kTileCells>(cst, p);
         const int uc[3] = {u & 7, (u >> 3) & 7, u >> 6};
         int c[3];
 #pragma unroll

@@ -364,7 +364,7 @@ __global__ __launch_bounds__((PPGeo<ADJ, H>::BLOCK)) void pp_kernel(const uint16
             // own particles of the cells [z0*64, z1*64): a contiguous range
             const uint32_t q0 = cst[z0 * 64], q1 = cst[z1 * 64];
             for (uint32_t lp = q0 + tid; lp < q1; lp += kPPBlock) {
-                const int u = seg_search(cst, kTileCells, lp);
+                const int u = seg_search_n<kTileCells>(cst, lp);
                 const uint32_t p = p0 + lp;
                 const int bx = (u & 7) + H, by = ((u >> 3) & 7) + H, bz = (u >> 6) + H;
                 float xi, yi, zi;

@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void vel_bulk_kernel(
         uint32_t c = 0u;
         unsigned long long f[3] = {0ull, 0ull, 0ull};
         if (valid) {
-            const int u = seg_search(cst, kTileCells, p);
+            const int u = seg_search_n<kTileCells>(cst, p);
             uint32_t o[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) o[d] = pos[(int64_t)d * n + p];
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void vel_bulk_kernel(
     __syncthreads();
     float dmax = 0.0f;
     for (uint32_t p = p0 + tid; p < p1; p += kBlock) {
-        const int u = seg_search(cst, kTileCells, p);
+        const int u = seg_search_n<kTileCells>(cst, p);
         uint32_t o[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) o[d] = pos[(int64_t)d * n + p];
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void vel_code_kernel(
     if (ENCODE && blockIdx.x == 0 && tid == 0) v_scale_out[0] = s;
     const int64_t m3 = (int64_t)nb * nb * nb;
     for (uint32_t p = cst[0] + tid; p < cst[kTileCells]; p += kBlock) {
-        const int u = seg_search(cst, kTileCells, p);
+        const int u = seg_search_n<kTileCells>(cst, p);
         uint32_t o[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) o[d] = pos[(int64_t)d * n + p];
