@@ -291,7 +291,10 @@ __device__ __forceinline__ void stage_cell_starts(uint32_t *__restrict__ dst,
 // (wrapped) into LDS, x fastest.  Each wave copies 64/S whole x-rows per pass
 // (lane -> (row, x) fixed for the whole copy, so a row is one contiguous
 // read), the row's (y, z) is advanced incrementally, and the loads of one
-// thread are issued in batches (all in flight before the LDS stores).
+// thread are issued in batches (all in flight before the LDS stores).  A
+// block that does not wrap (most of them) is read through one base address
+// and a 32-bit offset advanced by constants; a wrapping one through the
+// wrapped node indices.
 template <int S, int BLOCK, typename T, int MAXB = 20>
 __device__ __forceinline__ void stage_block(T *__restrict__ dst, const T *__restrict__ mesh, int n,
                                             int x0, int y0, int z0) {
@@ -302,6 +305,10 @@ __device__ __forceinline__ void stage_block(T *__restrict__ dst, const T *__rest
     constexpr int PASSES = (ROWS + RPP - 1) / RPP;
     constexpr int BATCH = PASSES < MAXB ? PASSES : MAXB;
     constexpr int DY = RPP % S, DZ = RPP / S;
+    // every lane loads in every pass, also lanes whose value is not stored
+    // (rr == RPW, rows past ROWS): the rows it visits are r0 + j RPP <=
+    // PASSES RPP, so their z stays at most LZMAX
+    constexpr int LZMAX = (PASSES * RPP) / S;
     const int lane = (int)(threadIdx.x & 63u), w = (int)(threadIdx.x >> 6);
     const int rr = lane / S, lx = lane - rr * S;
     const bool act = rr < RPW;
@@ -309,20 +316,41 @@ __device__ __forceinline__ void stage_block(T *__restrict__ dst, const T *__rest
     const int m = n - 1;
     const int gx = (x0 + lx) & m;
     int ly = r0 % S, lz = r0 / S;       // (y, z) of this thread's current row
+    const bool inside = x0 >= 0 && y0 >= 0 && z0 >= 0 && x0 + S <= n && y0 + S <= n &&
+                        z0 + LZMAX < n;   // block-uniform
+    const T *__restrict__ base = mesh + ((size_t)(inside ? z0 : 0) * n + (inside ? y0 : 0)) * n +
+                                 (inside ? x0 : 0);
+    const uint32_t nn = (uint32_t)n * (uint32_t)n;
+    uint32_t off = (uint32_t)lz * nn + (uint32_t)ly * (uint32_t)n + (uint32_t)lx;
+    const uint32_t dstep = (uint32_t)DY * (uint32_t)n + (uint32_t)DZ * nn;
+    const uint32_t dwrap = nn - (uint32_t)S * (uint32_t)n;   // ly passed S: one z up
 #pragma unroll
     for (int p0 = 0; p0 < PASSES; p0 += BATCH) {
         T v[BATCH];
+        if (inside) {
 #pragma unroll
-        for (int k = 0; k < BATCH; ++k) {
-            // unconditional: the wrapped (y, z, x) is a node of the mesh for
-            // every lane, also those whose value is not stored
-            const uint32_t row = (uint32_t)((z0 + lz) & m) * (uint32_t)n + (uint32_t)((y0 + ly) & m);
-            v[k] = mesh[row * (uint32_t)n + (uint32_t)gx];
-            ly += DY;
-            lz += DZ;
-            if (ly >= S) {
-                ly -= S;
-                ++lz;
+            for (int k = 0; k < BATCH; ++k) {
+                v[k] = base[off];
+                ly += DY;
+                off += dstep;
+                if (ly >= S) {
+                    ly -= S;
+                    off += dwrap;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < BATCH; ++k) {
+                // the wrapped (y, z, x) is a node of the mesh for every lane
+                const uint32_t row =
+                    (uint32_t)((z0 + lz) & m) * (uint32_t)n + (uint32_t)((y0 + ly) & m);
+                v[k] = mesh[row * (uint32_t)n + (uint32_t)gx];
+                ly += DY;
+                lz += DZ;
+                if (ly >= S) {
+                    ly -= S;
+                    ++lz;
+                }
             }
         }
 #pragma unroll
