@@ -62,6 +62,11 @@ __device__ __forceinline__ unsigned long long to_fixed(float v) {
     return (unsigned long long)(__double_as_longlong(t) - __double_as_longlong(m));
 }
 
+// A fixed-point difference to FP32 through FP64: 5 instructions instead of
+// the 12 of a direct int64-to-float conversion, and the same float while
+// |d| < 2^53 (the FP64 step is then exact; node sums stay far below that).
+__device__ __forceinline__ float fixed_to_float(long long d) { return (float)(double)d; }
+
 // ---------------------------------------------------------------------------
 // fine level: phibar on a 16^3 node tile.  For each component d in turn, the
 // workgroup scatters c*abar_d with the CIC weights onto the nodes of the
@@ -209,7 +214,7 @@ __global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
             const int m = ((lz + 2) * kAN + ly + 2) * kAN + lx + 2;
             const long long d1 = (long long)(A[m + st] - A[m - st]);
             const long long d2 = (long long)(A[m + 2 * st] - A[m - 2 * st]);
-            out[k] += invS * ((2.0f / 3.0f) * (float)d1 - (1.0f / 12.0f) * (float)d2);
+            out[k] += invS * ((2.0f / 3.0f) * fixed_to_float(d1) - (1.0f / 12.0f) * fixed_to_float(d2));
         }
         __syncthreads();  // the next pass clears A
     }
@@ -344,7 +349,7 @@ __global__ void divergence_kernel(const unsigned long long *__restrict__ A, int 
     auto at = [&](int d, int xx, int yy, int zz) {
         return A[d * m3 + ((int64_t)wrapn(zz, n) * n + wrapn(yy, n)) * n + wrapn(xx, n)];
     };
-    auto dif = [](unsigned long long a, unsigned long long b) { return (float)(long long)(a - b); };
+    auto dif = [](unsigned long long a, unsigned long long b) { return fixed_to_float((long long)(a - b)); };
     float s = (2.0f / 3.0f) * dif(at(0, x + 1, y, z), at(0, x - 1, y, z)) -
               (1.0f / 12.0f) * dif(at(0, x + 2, y, z), at(0, x - 2, y, z));
     s += (2.0f / 3.0f) * dif(at(1, x, y + 1, z), at(1, x, y - 1, z)) -
