@@ -687,6 +687,10 @@ __global__ void add3_kernel(float *__restrict__ acc, const float *__restrict__ b
 // kernels take the freed workgroup slots, and the memory-bound PM and the
 // VALU-bound PP then overlap on the same CUs.
 constexpr float kPPConcurrentFrac = 0.75f;
+// The same for the PP adjoint beside the PM adjoint (1024-thread workgroups,
+// one per CU): measured on 512^3 particles, 5/8 of the CUs gave the shortest
+// force adjoint (106.0 ms; 3/4 107.6, 7/8 106.7, all 110.5, 9/16 110.6).
+constexpr float kPPAdjConcurrentFrac = 0.625f;
 
 }  // namespace
 
@@ -703,7 +707,7 @@ int launch_pp_concurrent(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs
     Lpp.scan_tmp = L.pp_scan;
     if (abar)
         return launch_pp_kernel<true>(ctx, pos, cs, n, abar, acc_pp, 0, work, Lpp, s,
-                                      kPPConcurrentFrac);
+                                      kPPAdjConcurrentFrac);
     return launch_pp_kernel<false>(ctx, pos, cs, n, nullptr, acc_pp, 0, work, Lpp, s,
                                    kPPConcurrentFrac);
 }
