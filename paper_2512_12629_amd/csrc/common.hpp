@@ -374,9 +374,15 @@ __device__ __forceinline__ void stage_block(T *__restrict__ dst, const T *__rest
 // Host entry points of the kernel files (return CUBE2_* codes).
 int launch_pack(cube2_ctx *ctx, const float *x, int64_t n, uint16_t *pos, uint32_t *cell_start,
                 int32_t *perm, unsigned char *work, const WorkLayout &L, hipStream_t s);
+// The stable sort by IOS cell of keys/vals (work) with the offsets of the
+// unsorted particles; with vel != NULL the final gather also forms the kicked
+// velocities vel_out[i] = vel[p] + kick acc[p] (FP64, separately rounded) of
+// the sorted particles, p = perm[i].
 int launch_sort_by_cell(cube2_ctx *ctx, int64_t n, const uint16_t *offs_in_unsorted,
                         uint16_t *pos, uint32_t *cell_start, int32_t *perm,
-                        unsigned char *work, const WorkLayout &L, hipStream_t s);
+                        unsigned char *work, const WorkLayout &L, hipStream_t s,
+                        const float *vel = nullptr, const float *acc = nullptr, double kick = 0.0,
+                        float *vel_out = nullptr);
 int launch_deposit(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, int64_t n,
                    float *rho_f, uint64_t *rho_f_fx, float *rho_c, uint64_t *rho_c_fx,
                    unsigned char *work, const WorkLayout &L, hipStream_t s);

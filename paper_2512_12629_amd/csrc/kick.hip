@@ -58,21 +58,6 @@ __global__ __launch_bounds__(kBlock) void kick_drift_kernel(
     if (bad) atomicOr(status, kStatusNonFinite);
 }
 
-__global__ void kick_gather(const int32_t *__restrict__ perm, const float *__restrict__ vel,
-                            const float *__restrict__ acc, int n, double kick,
-                            float *__restrict__ vout) {
-#pragma clang fp contract(off)
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int p = perm[i];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const int64_t o = (int64_t)d * n;
-        const double kv = kick * (double)acc[o + p];
-        vout[o + i] = (float)((double)vel[o + p] + kv);
-    }
-}
-
 constexpr int kRedBlocks = 1024;
 
 // Per-block partial sums in FP64 over a fixed grid-stride partition, then a
@@ -156,11 +141,9 @@ int launch_kick_drift(cube2_ctx *ctx, const uint16_t *pos_in, const uint32_t *cs
             offs, status_word(ctx));
         CUBE2_LAUNCH_CHECK();
     }
-    int r = launch_sort_by_cell(ctx, n, offs, pos_out, cs_out, perm_out, work, L, s);
-    if (r || n == 0) return r;
-    kick_gather<<<(n + 255) / 256, 256, 0, s>>>(perm_out, vel_in, acc, n, kick, vel_out);
-    CUBE2_LAUNCH_CHECK();
-    return CUBE2_OK;
+    // the re-sort's final gather also forms the kicked velocities
+    return launch_sort_by_cell(ctx, n, offs, pos_out, cs_out, perm_out, work, L, s, vel_in, acc,
+                               kick, vel_out);
 }
 
 int launch_reduce(cube2_ctx *ctx, const float *vel, const float *acc, int64_t n64, double *out8,

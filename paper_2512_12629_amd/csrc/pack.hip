@@ -220,6 +220,28 @@ __global__ void gather_offsets(const uint32_t *__restrict__ perm, const uint16_t
     if (perm_out) perm_out[i] = (int32_t)p;
 }
 
+// gather_offsets and the kick of the velocities in one pass over the
+// permutation: vout[i] = vel[p] + kick acc[p] in FP64 with separately rounded
+// operations (the value the kick-drift kernel drifted with), p = perm[i].
+__global__ void gather_offsets_kick(const uint32_t *__restrict__ perm,
+                                    const uint16_t *__restrict__ offs, int n,
+                                    uint16_t *__restrict__ pos, int32_t *__restrict__ perm_out,
+                                    const float *__restrict__ vel, const float *__restrict__ acc,
+                                    double kick, float *__restrict__ vout) {
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t p = perm[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t o = (int64_t)d * n;
+        pos[o + i] = offs[o + p];
+        const double kv = kick * (double)acc[o + p];
+        vout[o + i] = (float)((double)vel[o + p] + kv);
+    }
+    perm_out[i] = (int32_t)p;
+}
+
 // Tiles in dispatch order b (the XCD-slab order of tile_of_block), keyed by
 // how many thousand particles they own, largest first.
 __global__ void tile_keys_kernel(const uint32_t *__restrict__ cs, int nt, uint32_t *__restrict__ keys,
@@ -277,7 +299,8 @@ int launch_reset_tile_queue(cube2_ctx *ctx, unsigned char *work, const WorkLayou
 // keys/vals (work) and offs_tmp (work) hold the unsorted particles.
 int launch_sort_by_cell(cube2_ctx *ctx, int64_t n64, const uint16_t *offs, uint16_t *pos,
                         uint32_t *cell_start, int32_t *perm, unsigned char *work,
-                        const WorkLayout &L, hipStream_t s) {
+                        const WorkLayout &L, hipStream_t s, const float *vel, const float *acc,
+                        double kick, float *vel_out) {
     const int n = (int)n64;
     uint32_t *tmp = reinterpret_cast<uint32_t *>(work + L.scan_tmp);
     uint32_t *k0 = reinterpret_cast<uint32_t *>(work + L.keys);
@@ -308,7 +331,11 @@ int launch_sort_by_cell(cube2_ctx *ctx, int64_t n64, const uint16_t *offs, uint1
     // cell_start (n_cells + 1 entries, the last = n) from the sorted keys
     cell_starts_kernel<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(k0, n, ctx->n_cells, cell_start);
     CUBE2_LAUNCH_CHECK();
-    gather_offsets<<<(n + 255) / 256, 256, 0, s>>>(v0, offs, n, pos, perm);
+    if (vel)
+        gather_offsets_kick<<<(n + 255) / 256, 256, 0, s>>>(v0, offs, n, pos, perm, vel, acc, kick,
+                                                           vel_out);
+    else
+        gather_offsets<<<(n + 255) / 256, 256, 0, s>>>(v0, offs, n, pos, perm);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }
