@@ -340,9 +340,10 @@ def test_overflow_guard_sets_status():
 
 def test_nonfinite_kick_sets_status():
     import paper_2512_12629_amd as m
-    # A NaN and an infinite acceleration: those two particles keep their
-    # positions, every other particle moves exactly as in a run where the two
-    # accelerations are zero, and the status reports it once.
+    # A NaN and an infinite acceleration, and a finite velocity whose drift
+    # overflows the 64-bit position arithmetic: those three particles keep
+    # their positions, every other particle moves exactly as in a run where
+    # they stand still, and the status reports it once.
     rng = np.random.default_rng(11)
     n = 5000
     x = rng.random((3, n)).astype(np.float32)
@@ -350,14 +351,14 @@ def test_nonfinite_kick_sets_status():
     pos, cs, _ = c.pack(torch.from_numpy(x).cuda())
     vel = (0.2 * rng.standard_normal((3, n))).astype(np.float32)
     acc = rng.standard_normal((3, n)).astype(np.float32)
-    acc[:, 17] = 0.0
-    acc[:, 2500] = 0.0
-    vel[:, 17] = 0.0
-    vel[:, 2500] = 0.0
+    for i in (17, 300, 2500):
+        acc[:, i] = 0.0
+        vel[:, i] = 0.0
     ok = c.kick_drift(pos, cs, torch.from_numpy(vel).cuda(), torch.from_numpy(acc).cuda(), 0.05, 0.3)
     assert c.status() == 0
     acc[1, 17] = np.nan
     acc[2, 2500] = np.inf
+    vel[0, 300] = 3.0e38                 # finite, but 0.3 * 3e38 * 2^15 passes 2^62
     bad = c.kick_drift(pos, cs, torch.from_numpy(vel).cuda(), torch.from_numpy(acc).cuda(), 0.05, 0.3)
     assert c.status() == -7          # CUBE2_ENONFINITE
     assert c.status() == 0           # cleared by the read
@@ -365,9 +366,10 @@ def test_nonfinite_kick_sets_status():
         assert torch.equal(a, b)
     assert torch.equal(ok[3], bad[3])
     v_ok, v_bad, perm = _np(ok[2]), _np(bad[2]), _np(ok[3])
-    keep = (perm != 17) & (perm != 2500)
+    keep = (perm != 17) & (perm != 2500) & (perm != 300)
     assert np.array_equal(v_ok[:, keep], v_bad[:, keep])
-    assert not np.isfinite(v_bad[:, ~keep]).all()
+    assert not np.isfinite(v_bad[:, (perm == 17) | (perm == 2500)]).all()
+    assert v_bad[0, perm == 300][0] == np.float32(3.0e38)
 
 
 def test_empty_input():
