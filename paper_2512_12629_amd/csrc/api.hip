@@ -167,6 +167,9 @@ void cube2_destroy(cube2_ctx *ctx) {
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->ev_fork2) (void)hipEventDestroy(ctx->ev_fork2);
+    if (ctx->ev_join2) (void)hipEventDestroy(ctx->ev_join2);
+    if (ctx->side2) (void)hipStreamDestroy(ctx->side2);
     delete ctx;
 }
 
@@ -221,6 +224,21 @@ int cube2_init_tables(cube2_ctx *ctx, void *tables, size_t table_bytes, cube2_st
         ctx->ev_fork = fork;
         ctx->ev_join = join;
         ctx->side = side;
+    }
+    if (!ctx->side2) {
+        hipStream_t side = nullptr;
+        hipEvent_t fork = nullptr, join = nullptr;
+        if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+            if (join) (void)hipEventDestroy(join);
+            if (fork) (void)hipEventDestroy(fork);
+            if (side) (void)hipStreamDestroy(side);
+            return CUBE2_EHIP;
+        }
+        ctx->ev_fork2 = fork;
+        ctx->ev_join2 = join;
+        ctx->side2 = side;
     }
     // the no-allocation PP entry point's scratch address on this device
     const int sr = noalloc_setup(nullptr);

@@ -532,28 +532,39 @@ int launch_pm_backward_p(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs
     float *bf = reinterpret_cast<float *>(work + L.bar_f);
     float *bc = ctx->n_levels > 1 ? reinterpret_cast<float *>(work + L.bar_c) : nullptr;
     float2 *spec = reinterpret_cast<float2 *>(work + L.spec);
-    // forward potentials (recomputed)
-    int r = launch_deposit(ctx, pos, cs, n, rf, nullptr, rc, nullptr, work, L, s);
-    if (r) return r;
-    for (int l = 0; l < ctx->n_levels; ++l) {
-        float *m = l == 0 ? rf : rc;
-        r = launch_potential(ctx, l, m, m, spec, s);
-        if (r) return r;
-    }
-    // max |abar| for the fixed-point scale of the scatters
+    // The fine cotangent scatter (max |abar|, then phibar of the fine level)
+    // on the context's second stream, beside the recomputed forward
+    // potentials on s; they share no buffer (amax and bf against the
+    // deposit's regions, rf, rc and the spectrum), and s waits for the
+    // scatter before the spectrum is reused for rhobar.
+    hipStream_t s2 = ctx->side2;
+    CUBE2_CHECK_HIP(hipEventRecord(ctx->ev_fork2, s));
+    CUBE2_CHECK_HIP(hipStreamWaitEvent(s2, ctx->ev_fork2, 0));
     unsigned int *amax = reinterpret_cast<unsigned int *>(work + L.red);
-    set_u32<<<1, 1, 0, s>>>(amax, 0u);
+    set_u32<<<1, 1, 0, s2>>>(amax, 0u);
     CUBE2_LAUNCH_CHECK();
     if (n > 0) {
         const int64_t m3 = 3 * n;
         const unsigned gb = (unsigned)std::min<int64_t>(4096, (m3 + 255) / 256);
-        absmax_kernel<<<gb, 256, 0, s>>>(acc_bar, m3, amax);
+        absmax_kernel<<<gb, 256, 0, s2>>>(acc_bar, m3, amax);
         CUBE2_LAUNCH_CHECK();
     }
-    // phibar of the fine level, then rhobar = K phibar in place
-    fine_phibar_kernel<P><<<blocks, kPhiBlock, 0, s>>>(pos, cs, acc_bar, (int)n, ctx->n_f, nt,
-                                                    (float)gm, amax, bf);
+    fine_phibar_kernel<P><<<blocks, kPhiBlock, 0, s2>>>(pos, cs, acc_bar, (int)n, ctx->n_f, nt,
+                                                     (float)gm, amax, bf);
     CUBE2_LAUNCH_CHECK();
+    // forward potentials (recomputed); s joins the scatter whatever happens
+    int r = launch_deposit(ctx, pos, cs, n, rf, nullptr, rc, nullptr, work, L, s);
+    for (int l = 0; r == CUBE2_OK && l < ctx->n_levels; ++l) {
+        float *m = l == 0 ? rf : rc;
+        r = launch_potential(ctx, l, m, m, spec, s);
+    }
+    if (hipEventRecord(ctx->ev_join2, s2) != hipSuccess ||
+        hipStreamWaitEvent(s, ctx->ev_join2, 0) != hipSuccess) {
+        (void)hipStreamSynchronize(s2);
+        return r ? r : CUBE2_EHIP;
+    }
+    if (r) return r;
+    // rhobar = K phibar in place
     r = launch_potential(ctx, 0, bf, bf, spec, s);
     if (r) return r;
     float cc = 0.0f;

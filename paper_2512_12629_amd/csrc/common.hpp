@@ -74,6 +74,10 @@ struct cube2_ctx {
     unsigned char *tables = nullptr;   // device; set by cube2_init_tables
     hipStream_t side = nullptr;        // cube2_force's PP stream (default priority), made by cube2_init_tables
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // the PM adjoint's second stream (default priority) and its fork/join
+    // events: the cotangent scatter beside the recomputed forward potentials
+    hipStream_t side2 = nullptr;
+    hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;
 };
 
 namespace cube2 {
