@@ -387,7 +387,11 @@ int cube2_deposit_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *
  * real and even, so the operator is symmetric), the deposit adjoint, plus
  * the derivative of the interpolation weights.  The scatters sum in 64-bit
  * fixed point (scale 2^(41-e), 2^e > G m max|acc_bar| / H^2), so the result
- * is deterministic.  accumulate != 0 adds. */
+ * is deterministic.  accumulate != 0 adds.  The fine scatter runs on a second
+ * stream of the context (made by cube2_init_tables, default priority) beside
+ * the recomputed forward potentials on `stream`, which waits for it: the call
+ * is ordered on `stream` like every other, and calls that share a context
+ * must not overlap. */
 int cube2_pm_force_backward(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cell_start,
                             int64_t n, const float *acc_bar, float *x_bar, int accumulate,
                             void *work, size_t work_bytes, cube2_stream_t stream);
