@@ -687,10 +687,19 @@ __global__ void add3_kernel(float *__restrict__ acc, const float *__restrict__ b
 // kernels take the freed workgroup slots, and the memory-bound PM and the
 // VALU-bound PP then overlap on the same CUs.
 constexpr float kPPConcurrentFrac = 0.75f;
+// With the two-cell reach (b_f > 2) the PP has ~5x the pairs and the PM part
+// fits in what the PP leaves: the full grid (measured at b_f = 3.5 on 512^3
+// particles: 89.9 ms, against 91.9 at 7/8, 104.7 at 3/4 and 98.4 with PM and
+// PP one after the other).
+constexpr float kPPConcurrentFracH2 = 1.0f;
 // The same for the PP adjoint beside the PM adjoint (1024-thread workgroups,
 // one per CU): measured on 512^3 particles, 5/8 of the CUs gave the shortest
 // force adjoint (106.0 ms; 3/4 107.6, 7/8 106.7, all 110.5, 9/16 110.6).
 constexpr float kPPAdjConcurrentFrac = 0.625f;
+// ... and with the two-cell reach, 7/8 (measured at b_f = 3.5 on 512^3
+// particles: 212.5 ms, against 214.9 with the full grid, 280.0 at 5/8 and
+// 226.7 with PM and PP adjoints one after the other).
+constexpr float kPPAdjConcurrentFracH2 = 0.875f;
 
 }  // namespace
 
@@ -707,9 +716,10 @@ int launch_pp_concurrent(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs
     Lpp.scan_tmp = L.pp_scan;
     if (abar)
         return launch_pp_kernel<true>(ctx, pos, cs, n, abar, acc_pp, 0, work, Lpp, s,
-                                      kPPAdjConcurrentFrac);
+                                      ctx->pp_halo == 1 ? kPPAdjConcurrentFrac
+                                                        : kPPAdjConcurrentFracH2);
     return launch_pp_kernel<false>(ctx, pos, cs, n, nullptr, acc_pp, 0, work, Lpp, s,
-                                   kPPConcurrentFrac);
+                                   ctx->pp_halo == 1 ? kPPConcurrentFrac : kPPConcurrentFracH2);
 }
 
 int launch_add3(float *acc, const float *acc_pp, int64_t m, hipStream_t s) {
