@@ -118,8 +118,16 @@ constexpr int bitrev(int v, int bits) {
     return r;
 }
 
+__device__ __forceinline__ float fmac3(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmac3(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // In-register radix-2 DIT DFT of size R, natural order in and out.
-// SIGN = -1: forward (exp(-i...)), +1: inverse (unnormalised).
+// SIGN = -1: forward (exp(-i...)), +1: inverse (unnormalised).  A butterfly
+// with a general twiddle w = (wr, wi) factors out the larger component:
+// for |wr| >= |wi|, t w = wr (t.x - q t.y, t.y + q t.x) with q = wi / wr
+// (a compile-time constant, |q| <= 1), and u +- t w is then two FMAs per
+// component after one FMA for the bracket: 6 instructions instead of 8
+// (2 multiplies and 2 FMAs for t w, 4 adds); the other case uses q = wr / wi.
 template <int R, int SIGN, typename C>
 __device__ __forceinline__ void dft(C (&v)[R]) {
     using S = decltype(v[0].x);
@@ -147,9 +155,23 @@ __device__ __forceinline__ void dft(C (&v)[R]) {
                     t = SIGN < 0 ? cmk(t.y, -t.x) : cmk(-t.y, t.x);
                 } else {
                     const int k = j * (R / len);
-                    const S wr = (S)Roots<R>::t.re[k];
-                    const S wi = SIGN < 0 ? (S)Roots<R>::t.im[k] : (S)-Roots<R>::t.im[k];
-                    t = cmk(t.x * wr - t.y * wi, t.x * wi + t.y * wr);
+                    const double dr = Roots<R>::t.re[k];
+                    const double di = SIGN < 0 ? Roots<R>::t.im[k] : -Roots<R>::t.im[k];
+                    S m, a, b;
+                    if (dr * dr >= di * di) {  // t w = wr (t.x - q t.y, t.y + q t.x)
+                        const S q = (S)(di / dr);
+                        m = (S)dr;
+                        a = fmac3(-q, t.y, t.x);
+                        b = fmac3(q, t.x, t.y);
+                    } else {                   // t w = wi (q t.x - t.y, q t.y + t.x)
+                        const S q = (S)(dr / di);
+                        m = (S)di;
+                        a = fmac3(q, t.x, -t.y);
+                        b = fmac3(q, t.y, t.x);
+                    }
+                    v[i + j] = cmk(fmac3(m, a, u.x), fmac3(m, b, u.y));
+                    v[i + j + half] = cmk(fmac3(-m, a, u.x), fmac3(-m, b, u.y));
+                    continue;
                 }
                 v[i + j] = cadd(u, t);
                 v[i + j + half] = csub(u, t);

@@ -26,15 +26,31 @@ template <int P> struct InterpGeo {
     static constexpr int CSMAX = kTileFine / 2 + (P == 3 ? 7 : 5);
 };
 
-// FD force at the particle's two nodes along one axis, CIC-weighted.
-// p points at phi(node j) on that axis; st is the axis stride in LDS.
+// The FD force at the particle's two nodes along one axis, CIC-weighted
+// (w0 E(j) + w1 E(j+1)), is one 6-tap filter over phi(j-2..j+3); its taps
+// depend only on the axis weights, so they are formed once per particle and
+// axis.  With E(i) = -[c1 (phi(i+1) - phi(i-1)) - c2 (phi(i+2) - phi(i-2))],
+// c1 = 2/3, c2 = 1/12, the taps are
+//   -c2 w0, c1 w0 - c2 w1, c1 w1, -c1 w0, c2 w0 - c1 w1, c2 w1.
+template <typename T> struct Taps { T t[6]; };
+
 template <typename T>
-__device__ __forceinline__ T axis_force(const T *p, int st, T w0, T w1) {
-    const T pm2 = p[-2 * st], pm1 = p[-st], p0 = p[0], p1 = p[st], p2 = p[2 * st], p3 = p[3 * st];
+__device__ __forceinline__ Taps<T> axis_taps(T w0, T w1) {
     const T c1 = T(2.0 / 3.0), c2 = T(1.0 / 12.0);
-    const T e0 = -(c1 * (p1 - pm1) - c2 * (p2 - pm2));
-    const T e1 = -(c1 * (p2 - p0) - c2 * (p3 - pm1));
-    return w0 * e0 + w1 * e1;
+    const T a = c1 * w0, b = c2 * w0, c = c1 * w1, d = c2 * w1;
+    return Taps<T>{{-b, a - d, c, -a, b - c, d}};
+}
+
+// One line of the filter: p points at phi(j) on that axis, st is the axis
+// stride in LDS.
+template <typename T>
+__device__ __forceinline__ T axis_line(const T *p, int st, const Taps<T> &k) {
+    T r = p[-2 * st] * k.t[0];
+    r = fma(p[-st], k.t[1], r);
+    r = fma(p[0], k.t[2], r);
+    r = fma(p[st], k.t[3], r);
+    r = fma(p[2 * st], k.t[4], r);
+    return fma(p[3 * st], k.t[5], r);
 }
 
 // CIC-weighted force of a staged potential tile P (side S) at the particle
@@ -44,17 +60,19 @@ __device__ __forceinline__ void gather(const T *P, int S, int jx, int jy, int jz
                                        const T (&wx)[2], const T (&wy)[2], const T (&wz)[2],
                                        T &ax, T &ay, T &az) {
     const int SS = S * S;
+    const Taps<T> kx = axis_taps(wx[0], wx[1]), ky = axis_taps(wy[0], wy[1]),
+                  kz = axis_taps(wz[0], wz[1]);
     ax = ay = az = T(0);
 #pragma unroll
     for (int s1 = 0; s1 < 2; ++s1)
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2) {
             // x: nodes (jx.., jy+s1, jz+s2)
-            ax += wy[s1] * wz[s2] * axis_force(P + (jz + s2) * SS + (jy + s1) * S + jx, 1, wx[0], wx[1]);
+            ax = fma(wy[s1] * wz[s2], axis_line(P + (jz + s2) * SS + (jy + s1) * S + jx, 1, kx), ax);
             // y: nodes (jx+s1, jy.., jz+s2)
-            ay += wx[s1] * wz[s2] * axis_force(P + (jz + s2) * SS + jy * S + jx + s1, S, wy[0], wy[1]);
+            ay = fma(wx[s1] * wz[s2], axis_line(P + (jz + s2) * SS + jy * S + jx + s1, S, ky), ay);
             // z: nodes (jx+s1, jy+s2, jz..)
-            az += wx[s1] * wy[s2] * axis_force(P + jz * SS + (jy + s2) * S + jx + s1, SS, wz[0], wz[1]);
+            az = fma(wx[s1] * wy[s2], axis_line(P + jz * SS + (jy + s2) * S + jx + s1, SS, kz), az);
         }
 }
 
@@ -94,10 +112,12 @@ __device__ __forceinline__ void gather3(const T *P, int S, int nx, int ny, int n
 // At least two waves per SIMD: left alone, the compiler gives the two-level
 // TSC gather all 256 VGPRs and one wave per SIMD.  FINE = false gathers the
 // coarse level only (the tile+buffer mode computes the fine level per tile).
-template <bool TWO, int P, typename T, bool FINE = true>
+// HS > 0 fixes log2 of the coarse ratio at compile time (the coarse tile's
+// LDS strides then fold into immediate offsets); HS = 0 reads it from hshift.
+template <bool TWO, int P, typename T, bool FINE = true, int HS = 0>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void interp_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs, int n, int n_f, int nt,
-    const T *__restrict__ phi_f, const T *__restrict__ phi_c, int n_c, int hshift, T scale_f,
+    const T *__restrict__ phi_f, const T *__restrict__ phi_c, int n_c, int hshift_arg, T scale_f,
     T scale_c, T *__restrict__ acc, int accumulate) {
     constexpr int FS = InterpGeo<P>::FS, HLO = InterpGeo<P>::HLO, CSM = InterpGeo<P>::CSMAX;
     __shared__ T pf[FINE ? FS * FS * FS : 1];
@@ -107,6 +127,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     int tx, ty, tz;
     tile_of_block(blockIdx.x, nt, tx, ty, tz);
     const int tid = threadIdx.x;
+    const int hshift = HS > 0 ? HS : hshift_arg;
     const uint32_t key0 = (uint32_t)((tz * nt + ty) * nt + tx) * kTileCells;
     stage_cell_starts<kBlock>(cst, cs, key0);
     const int ax0 = tx * kTileFine, ay0 = ty * kTileFine, az0 = tz * kTileFine;
@@ -234,10 +255,9 @@ void launch_interp_kernel(cube2_ctx *ctx, unsigned blocks, const uint16_t *pos, 
             (T)(gm / ((double)C.H * C.H)), acc, accumulate);
     } else if (coarse) {
         const Level &C = ctx->lv[1];
-        interp_kernel<true, P, T><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, phi_f,
-                                                            phi_c, C.n, C.hshift, (T)gm,
-                                                            (T)(gm / ((double)C.H * C.H)), acc,
-                                                            accumulate);
+        auto *k = C.hshift == 2 ? interp_kernel<true, P, T, true, 2> : interp_kernel<true, P, T>;
+        k<<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, phi_f, phi_c, C.n, C.hshift,
+                                    (T)gm, (T)(gm / ((double)C.H * C.H)), acc, accumulate);
     } else {
         interp_kernel<false, P, T><<<blocks, kBlock, 0, s>>>(pos, cs, (int)n, ctx->n_f, nt, phi_f,
                                                              nullptr, 1, 0, (T)gm, T(0), acc,

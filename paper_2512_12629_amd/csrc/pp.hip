@@ -683,6 +683,15 @@ __global__ void add3_kernel(float *__restrict__ acc, const float *__restrict__ b
     if (i < m) acc[i] = acc[i] + b[i];
 }
 
+// The same sum four floats at a time (both arrays 16-byte aligned, m4 = m / 4).
+__global__ void add3_kernel4(float4 *__restrict__ acc, const float4 *__restrict__ b, int64_t m4) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m4) {
+        const float4 x = acc[i], y = b[i];
+        acc[i] = make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w);
+    }
+}
+
 // Share of the persistent PP grid when the PM force runs beside it: the PM
 // kernels take the freed workgroup slots, and the memory-bound PM and the
 // VALU-bound PP then overlap on the same CUs.
@@ -724,7 +733,16 @@ int launch_pp_concurrent(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs
 
 int launch_add3(float *acc, const float *acc_pp, int64_t m, hipStream_t s) {
     if (m <= 0) return CUBE2_OK;
-    add3_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(acc, acc_pp, m);
+    int64_t done = 0;
+    if ((((uintptr_t)acc | (uintptr_t)acc_pp) & 15u) == 0 && m >= 4) {
+        const int64_t m4 = m / 4;
+        add3_kernel4<<<(unsigned)((m4 + 255) / 256), 256, 0, s>>>(
+            reinterpret_cast<float4 *>(acc), reinterpret_cast<const float4 *>(acc_pp), m4);
+        done = 4 * m4;
+    }
+    if (m > done)
+        add3_kernel<<<(unsigned)((m - done + 255) / 256), 256, 0, s>>>(acc + done, acc_pp + done,
+                                                                       m - done);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }
