@@ -160,8 +160,11 @@ __global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
             float ab[kBatch];
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
-                const uint32_t v = v0 + k * kPhiBlock;
-                sg[k] = v >= total ? -1 : (use_lut ? (int)lut[v] : seg_search_n<kASegs>(seg_pre, v));
+                // looked up for every lane (past the end: the last particle,
+                // total >= 1 here) so that the lookups of the batch interleave
+                const uint32_t v = v0 + k * kPhiBlock, vv = v < total ? v : total - 1;
+                const int u = use_lut ? (int)lut[vv] : seg_search_n<kASegs>(seg_pre, vv);
+                sg[k] = v < total ? u : -1;
             }
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {

@@ -171,7 +171,10 @@ __device__ __forceinline__ int seg_search(const uint32_t *pre, int cnt, uint32_t
 // with pre[u] <= v, found bit by bit from the highest power of two below
 // CNT (pre non-decreasing, so pre[u] <= v holds exactly up to the answer).
 // Unrolled and branch-free: no loop control, and the LDS reads of
-// independent searches in one thread interleave.
+// independent searches in one thread interleave.  When CNT is not a power
+// of two, pre must hold CNT + 1 entries with pre[CNT] > v (the end of the
+// last segment): a candidate at or beyond CNT reads pre[CNT] instead, which
+// fails the test, so no step needs a branch.
 template <int CNT>
 __device__ __forceinline__ int seg_search_n(const uint32_t *pre, uint32_t v) {
     static_assert(CNT >= 1, "empty range");
@@ -183,10 +186,11 @@ __device__ __forceinline__ int seg_search_n(const uint32_t *pre, uint32_t v) {
     int lo = 0;
 #pragma unroll
     for (int step = TOP; step > 0; step >>= 1) {
-        if constexpr ((CNT & (CNT - 1)) == 0) {
-            if (pre[lo + step] <= v) lo += step;   // lo + step < CNT always
+        const int c = lo + step;
+        if (2 * TOP - step < CNT) {   // c < CNT whatever steps were taken (folds once unrolled)
+            if (pre[c] <= v) lo = c;
         } else {
-            if (lo + step < CNT && pre[lo + step] <= v) lo += step;
+            if (pre[c < CNT ? c : CNT] <= v) lo = c;
         }
     }
     return lo;

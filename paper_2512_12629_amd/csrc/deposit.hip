@@ -316,8 +316,12 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(
             uint32_t o[kBatch][3];
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
+                // searched for every lane (a lane past the end searches for the
+                // last particle, total >= 1 here), so that the kBatch searches
+                // interleave their LDS reads outside any branch
                 const uint32_t v = w0 + k * kBlock + lane;
-                sg[k] = v < total ? seg_search_n<kSegs>(seg_pre, v) : -1;
+                const int u = seg_search_n<kSegs>(seg_pre, v < total ? v : total - 1);
+                sg[k] = v < total ? u : -1;
             }
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
