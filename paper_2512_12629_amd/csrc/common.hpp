@@ -259,10 +259,34 @@ __device__ __forceinline__ bool claim_tile(const uint32_t *order, uint32_t *queu
 
 // Sums over the 64 lanes of a wave (butterfly; every lane must be active).
 // The order of the additions is fixed, so float sums are deterministic.
+// One DPP lane permutation within rows of 16 lanes, applied to both halves
+// of a 64-bit value.
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Sum of a 64-bit integer over the 64 lanes of a wave (every lane active),
+// returned to every lane.  Within each row of 16 lanes, DPP butterflies
+// (quad_perm [1,0,3,2] and [2,3,0,1], then the half-row and row mirrors)
+// leave the row's sum in all its lanes; the four row sums are then read from
+// lanes 0, 16, 32 and 48.  No LDS traffic; the integer sum is exact, so its
+// order does not matter.
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+    v += dpp_u64<0xB1>(v);
+    v += dpp_u64<0x4E>(v);
+    v += dpp_u64<0x141>(v);
+    v += dpp_u64<0x140>(v);
+    const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    unsigned long long s = 0;
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
+    for (int r = 0; r < 4; ++r)
+        s += ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)hi, 16 * r) << 32) |
+             (uint32_t)__builtin_amdgcn_readlane((int)lo, 16 * r);
+    return s;
 }
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll

@@ -154,8 +154,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         uint32_t ob[kBatch][3];
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
+            // searched for every lane (past the end: the last particle) so
+            // that the searches of the batch interleave outside any branch
             const uint32_t p = pb + k * kBlock;
-            ub[k] = p < p1 ? seg_search_n<kTileCells>(cst, p) : -1;
+            const int u = seg_search_n<kTileCells>(cst, p < p1 ? p : p1 - 1);
+            ub[k] = p < p1 ? u : -1;
         }
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
