@@ -199,11 +199,14 @@ __global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
                         const int nz = j[2] + sz, ny = j[1] + sy;
                         if ((unsigned)nz >= (unsigned)kAN || (unsigned)ny >= (unsigned)kAN) continue;
                         const float wyz = w[1][sy] * w[2][sz] * ab[k];
+                        // row of the node line, as two small products (24-bit
+                        // multiplies; a product of the sum is a 32-bit one)
+                        const int row = nz * (kAN * kAN) + ny * kAN;
 #pragma unroll
                         for (int sx = 0; sx < P; ++sx) {
                             const int nx = j[0] + sx;
                             if ((unsigned)nx >= (unsigned)kAN) continue;
-                            atomicAdd(&A[(nz * kAN + ny) * kAN + nx], to_fixed(wyz * w[0][sx]));
+                            atomicAdd(&A[row + nx], to_fixed(wyz * w[0][sx]));
                         }
                     }
             }
@@ -221,13 +224,15 @@ __global__ __launch_bounds__(kPhiBlock) void fine_phibar_kernel(
         }
         __syncthreads();  // the next pass clears A
     }
+    // node i = tid + k kPhiBlock: the same (x, y) for every k, z advancing by
+    // kPhiBlock / T^2 layers per k
+    static_assert(kPhiBlock % (T * T) == 0, "whole z-layers per step");
     const int a0x = tx * T, a0y = ty * T, a0z = tz * T;
+    const int lx = tid % T, ly = (tid / T) % T, lz = tid / (T * T);
+    float *dst = phibar + ((int64_t)(a0z + lz) * n_f + (a0y + ly)) * n_f + (a0x + lx);
+    const int64_t zstep = (int64_t)(kPhiBlock / (T * T)) * n_f * n_f;
 #pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-        const int i = tid + k * kPhiBlock;
-        const int lx = i % T, ly = (i / T) % T, lz = i / (T * T);
-        phibar[((int64_t)(a0z + lz) * n_f + (a0y + ly)) * n_f + (a0x + lx)] = out[k];
-    }
+    for (int k = 0; k < NPT; ++k) dst[k * zstep] = out[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -291,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void coarse_abar_kernel(
         const int key = valid ? (j[2] * NC + j[1]) * NC + j[0] : -1;
         const unsigned long long vm = __ballot(valid);
         const int lead = first_lane(vm);
-        const int key0 = __shfl(key, lead, 64);
+        const int key0 = __builtin_amdgcn_readlane(key, lead);
         const bool uniform = __ballot(valid && key != key0) == 0ull;
 #pragma unroll
         for (int sz = 0; sz < P; ++sz)

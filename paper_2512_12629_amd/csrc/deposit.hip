@@ -142,7 +142,7 @@ __device__ __forceinline__ void deposit_coarse_wave_tsc(bool own, const int (&b)
     }
     const int key = own ? (j[2] * NC + j[1]) * NC + j[0] : -1;
     const int lead = first_lane(om);
-    const int key0 = __shfl(key, lead, 64);
+    const int key0 = __builtin_amdgcn_readlane(key, lead);
     const bool uniform = __ballot(own && key != key0) == 0ull;
 #pragma unroll
     for (int sz = 0; sz < 3; ++sz)
@@ -185,7 +185,7 @@ __device__ __forceinline__ void deposit_coarse_wave(bool own, const int (&b)[3],
     }
     const int key = own ? (j[2] * NC + j[1]) * NC + j[0] : -1;
     const int lead = first_lane(om);
-    const int key0 = __shfl(key, lead, 64);
+    const int key0 = __builtin_amdgcn_readlane(key, lead);
     const bool uniform = __ballot(own && key != key0) == 0ull;
 #pragma unroll
     for (int sz = 0; sz < 2; ++sz)
