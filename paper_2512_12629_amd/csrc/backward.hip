@@ -434,13 +434,16 @@ __device__ __forceinline__ int axis_footprint(int j, int f, float (&w)[P], float
     }
 }
 
-template <bool WITH_E, bool TWO, int P>
+// HS > 0 fixes log2 of the coarse ratio at compile time (the coarse tiles'
+// LDS strides then fold into immediate offsets); HS = 0 reads it from hshift.
+template <bool WITH_E, bool TWO, int P, int HS = 0>
 __global__ __launch_bounds__(kBlock) void xbar_gather_kernel(
     const uint16_t *__restrict__ pos, const uint32_t *__restrict__ cs,
     const float *__restrict__ abar, int n, int n_f, int nt, const float *__restrict__ phi_f,
     const float *__restrict__ rb_f, float c_f, const float *__restrict__ phi_c,
-    const float *__restrict__ rb_c, float c_c, int n_c, int hshift, float *__restrict__ xbar,
+    const float *__restrict__ rb_c, float c_c, int n_c, int hshift_arg, float *__restrict__ xbar,
     int accumulate) {
+    const int hshift = HS > 0 ? HS : hshift_arg;
     using G = GatherGeo<P>;
     constexpr int kFS = G::FS, kRS = G::RS, kCSMax = G::CSMAX, kCRMax = G::CRMAX;
     __shared__ float pf[WITH_E ? kFS * kFS * kFS : 1];
@@ -593,9 +596,10 @@ int launch_pm_backward_p(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs
         CUBE2_LAUNCH_CHECK();
         r = launch_potential(ctx, 1, bc, bc, spec, s);
         if (r) return r;
-        xbar_gather_kernel<true, true, P><<<blocks, kBlock, 0, s>>>(
-            pos, cs, acc_bar, (int)n, ctx->n_f, nt, rf, bf, (float)gm, rc, bc, cc, C.n, C.hshift,
-            x_bar, accumulate);
+        auto *k = C.hshift == 2 ? xbar_gather_kernel<true, true, P, 2>
+                                : xbar_gather_kernel<true, true, P>;
+        k<<<blocks, kBlock, 0, s>>>(pos, cs, acc_bar, (int)n, ctx->n_f, nt, rf, bf, (float)gm, rc,
+                                    bc, cc, C.n, C.hshift, x_bar, accumulate);
     } else {
         xbar_gather_kernel<true, false, P><<<blocks, kBlock, 0, s>>>(
             pos, cs, acc_bar, (int)n, ctx->n_f, nt, rf, bf, (float)gm, nullptr, nullptr, 0.f, 1, 0,
