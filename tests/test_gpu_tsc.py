@@ -26,6 +26,8 @@ CASES = {
     "uniform_64": (64, 0, lambda: synthetic.uniform(32 ** 3, 301)),
     "clustered_64_two_level": (64, 4, lambda: synthetic.clustered(24, 0.25, 6, 512, 0.5 / 64, 302)),
     "zel_32_ragged": (32, 2, lambda: synthetic.zeldovich(13, 0.25, 303)),
+    # the largest coarse ratio the library takes (8: a coarse mesh of 8^3)
+    "clustered_64_ratio8": (64, 8, lambda: synthetic.clustered(24, 0.25, 6, 512, 0.5 / 64, 304)),
 }
 
 
