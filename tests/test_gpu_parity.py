@@ -262,6 +262,23 @@ def test_force_entry_equals_pm_then_pp(case):
         assert torch.equal(acc, ref)
 
 
+def test_force_entry_output_not_16_byte_aligned(case):
+    """cube2_force into an output that starts 4 bytes into its buffer (the
+    final PM + PP sum then takes its scalar path instead of 16-byte
+    accesses): the same floats as the separate entry points."""
+    import paper_2512_12629_amd as m
+    c, pos, cs = case["c"], case["pos"], case["cs"]
+    n = pos.shape[1]
+    ref = c.pp_force(pos, cs, c.pm_force(pos, cs))
+    buf = torch.full((3 * n + 1,), float("nan"), dtype=torch.float32, device="cuda")
+    acc = buf[1:].view(3, n)
+    assert acc.data_ptr() % 16 != 0
+    m.cube2_force(c.ctx, pos, cs, acc, c.work)
+    torch.cuda.synchronize()
+    assert torch.equal(acc, ref)
+    assert torch.isnan(buf[0])
+
+
 def test_force_backward_entry_equals_pm_then_pp(case):
     """cube2_force_backward (PP adjoint on the side stream beside the PM
     adjoint) against the two adjoint entry points in sequence: bit for bit,
