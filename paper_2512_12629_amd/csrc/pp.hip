@@ -159,6 +159,22 @@ __device__ __forceinline__ void pair_adjoint(float dx, float dy, float dz, float
 // they need are the contiguous box layers [z0, z1 + 2H), a contiguous slice of
 // the staged list.
 
+// The heaviest tiles are split: the first kSplitTiles entries of the
+// heaviest-first order are offered as kSplitParts work items each; a tile
+// with `own` particles uses min(kSplitParts, ceil(own / block)) of them,
+// each part staging the tile's box and taking every nparts-th block of its
+// own particles, and the other items end at once.  A tile where Plummer
+// spheres overlap holds several times the pairs of one sphere, and when a
+// workload has few tiles per workgroup such a tile would end the kernel
+// alone; each particle's sum is still formed by one thread in the same
+// order.  (Splitting four tiles per workgroup was slower: every part
+// stages the box again.)
+// The two-cell reach (b_f > 2) keeps whole tiles: it has ~5x the pairs per
+// tile, so its tiles are not few per workgroup, and the split's bookkeeping
+// would take it past 128 VGPRs (one workgroup per CU instead of two).
+constexpr int kSplitParts = 8, kSplitTiles = 128;
+template <int H> constexpr int split_parts() { return H == 1 ? kSplitParts : 1; }
+
 // ADJ = false: acc = G m sum_j g D (forward).  ADJ = true: out = G m sum_j
 // J(D) (abar_j - abar_i) for the cotangent abar (the adjoint), which stages
 // abar_j beside x_j and so holds half as many particles per chunk.
@@ -171,6 +187,7 @@ __global__ __launch_bounds__((PPGeo<ADJ, H>::BLOCK)) void pp_kernel(const uint16
                                                      float *__restrict__ acc, int accumulate,
                                                      const uint32_t *__restrict__ order,
                                                      uint32_t *__restrict__ queue, int ntiles,
+                                                     int nsplit,
                                                      const uint8_t *__restrict__ skip) {
     constexpr int CAP = PPGeo<ADJ, H>::CAP;
     constexpr int kPPBlock = PPGeo<ADJ, H>::BLOCK;
@@ -193,23 +210,36 @@ __global__ __launch_bounds__((PPGeo<ADJ, H>::BLOCK)) void pp_kernel(const uint16
     const float inv = 1.0f / 32768.0f;
     for (int i = tid; i < kSRows; i += kPPBlock) pair_srows[i] = table[i];
 
-    // Persistent workgroups: each takes the next tile of the heaviest-first
-    // order (claim_slot) until all are taken (the exit test is
-    // block-uniform).  Thread 0 claims the next tile while the current one
-    // is processed.
+    // Persistent workgroups: each takes the next work item of the
+    // heaviest-first order (claim_slot) until all are taken (the exit test
+    // is block-uniform).  Thread 0 claims the next item while the current
+    // one is processed.  Items [0, nsplit kSplitParts) are the parts of the
+    // nsplit heaviest tiles, the rest one whole tile each.
+    constexpr int kParts = split_parts<H>();
+    const int nitems = ntiles + nsplit * (kParts - 1);
+    const int split_items = nsplit * kParts;
     int next = 0;
-    if (tid == 0) next = claim_slot(queue, ntiles);
+    if (tid == 0) next = claim_slot(queue, nitems);
     for (;;) {
         if (tid == 0) {
             tile_sh = next;
             maxcnt_sh = 0u;
         }
         __syncthreads();
-        const int ti = tile_sh;
-        if (ti >= ntiles) break;
-        if (tid == 0) next = claim_slot(queue, ntiles);
+        const int item = __builtin_amdgcn_readfirstlane(tile_sh);   // block-uniform
+        if (item >= nitems) break;
+        if (tid == 0) next = claim_slot(queue, nitems);
+        const bool split = kParts > 1 && item < split_items;
+        const int ti = split ? item / kParts : item - split_items + nsplit;
+        const int part = split ? item % kParts : 0;
         const int t = (int)order[ti];
-        if (skip && skip[t]) {   // a tile whose pairs another level handles
+        int nparts = 1;
+        if (split) {
+            const uint32_t own = cs[(uint32_t)(t + 1) * kTileCells] - cs[(uint32_t)t * kTileCells];
+            nparts = (int)min((own + kPPBlock - 1) / kPPBlock, (uint32_t)kParts);
+            nparts = __builtin_amdgcn_readfirstlane(max(nparts, 1));
+        }
+        if ((skip && skip[t]) || part >= nparts) {   // another level's tile, or a spare part
             __syncthreads();     // every thread has read tile_sh
             continue;
         }
@@ -361,9 +391,11 @@ __global__ __launch_bounds__((PPGeo<ADJ, H>::BLOCK)) void pp_kernel(const uint16
                 }
             }
             __syncthreads();
-            // own particles of the cells [z0*64, z1*64): a contiguous range
+            // own particles of the cells [z0*64, z1*64): a contiguous range;
+            // part p of a split tile takes its blocks p, p + nparts, ...
             const uint32_t q0 = cst[z0 * 64], q1 = cst[z1 * 64];
-            for (uint32_t lp = q0 + tid; lp < q1; lp += kPPBlock) {
+            for (uint32_t lp = q0 + (uint32_t)(part * kPPBlock + tid); lp < q1;
+                 lp += (uint32_t)(kPPBlock * nparts)) {
                 const int u = seg_search_n<kTileCells>(cst, lp);
                 const uint32_t p = p0 + lp;
                 const int bx = (u & 7) + H, by = ((u >> 3) & 7) + H, bz = (u >> 6) + H;
@@ -656,12 +688,14 @@ int launch_pp_kernel_h(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs, 
     const uint32_t *order = tile_order_ptr(work, L);
     uint32_t *queue = tile_queue_ptr(ctx, work, L);
     auto k = pp_kernel<ADJ, H>;
+    const int nsplit = split_parts<H>() > 1 ? std::min(kSplitTiles, ntiles) : 0;
+    const int nitems = ntiles + nsplit * (split_parts<H>() - 1);
     const unsigned grid = std::max(
-        1u, (unsigned)((float)persistent_grid(k, PPGeo<ADJ, H>::BLOCK, ntiles) * grid_frac));
+        1u, (unsigned)((float)persistent_grid(k, PPGeo<ADJ, H>::BLOCK, nitems) * grid_frac));
     k<<<grid, PPGeo<ADJ, H>::BLOCK, 0, s>>>(
         pos, cs, (int)n, nt, table, ctx->pp_negc,
         (float)(ctx->cfg.g_newton * ctx->cfg.m_p), abar, out, accumulate, order, queue, ntiles,
-        skip);
+        nsplit, skip);
     CUBE2_LAUNCH_CHECK();
     return CUBE2_OK;
 }
