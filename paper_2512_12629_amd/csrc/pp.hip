@@ -730,6 +730,11 @@ __global__ void add3_kernel4(float4 *__restrict__ acc, const float4 *__restrict_
 // kernels take the freed workgroup slots, and the memory-bound PM and the
 // VALU-bound PP then overlap on the same CUs.
 constexpr float kPPConcurrentFrac = 0.75f;
+// ... on meshes of fewer than 64^3 tiles (256^3 particles on a 512^3 mesh),
+// where the PM part is a smaller share of the step and the PP has fewer
+// tiles per workgroup, the whole grid (measured: 7.08 ms, against 7.19 at
+// 7/8 and 7.46 at 3/4).
+constexpr int kPPConcurrentFullBelowNt = 64;
 // With the two-cell reach (b_f > 2) the PP has ~5x the pairs and the PM part
 // fits in what the PP leaves: the full grid (measured at b_f = 3.5 on 512^3
 // particles: 89.9 ms, against 91.9 at 7/8, 104.7 at 3/4 and 98.4 with PM and
@@ -761,8 +766,10 @@ int launch_pp_concurrent(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs
         return launch_pp_kernel<true>(ctx, pos, cs, n, abar, acc_pp, 0, work, Lpp, s,
                                       ctx->pp_halo == 1 ? kPPAdjConcurrentFrac
                                                         : kPPAdjConcurrentFracH2);
-    return launch_pp_kernel<false>(ctx, pos, cs, n, nullptr, acc_pp, 0, work, Lpp, s,
-                                   ctx->pp_halo == 1 ? kPPConcurrentFrac : kPPConcurrentFracH2);
+    const float frac = ctx->pp_halo != 1                  ? kPPConcurrentFracH2
+                       : ctx->nt < kPPConcurrentFullBelowNt ? 1.0f
+                                                            : kPPConcurrentFrac;
+    return launch_pp_kernel<false>(ctx, pos, cs, n, nullptr, acc_pp, 0, work, Lpp, s, frac);
 }
 
 int launch_add3(float *acc, const float *acc_pp, int64_t m, hipStream_t s) {
