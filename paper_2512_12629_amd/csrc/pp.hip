@@ -744,6 +744,10 @@ constexpr float kPPConcurrentFracH2 = 1.0f;
 // one per CU): measured on 512^3 particles, 5/8 of the CUs gave the shortest
 // force adjoint (106.0 ms; 3/4 107.6, 7/8 106.7, all 110.5, 9/16 110.6).
 constexpr float kPPAdjConcurrentFrac = 0.625f;
+// ... and on meshes of fewer than 64^3 tiles, 7/8 (measured on 256^3
+// particles: force adjoint 14.2 ms, against 14.3 with the whole grid and
+// 17.6 at 5/8).
+constexpr float kPPAdjConcurrentFracSmall = 0.875f;
 // ... and with the two-cell reach, 7/8 (measured at b_f = 3.5 on 512^3
 // particles: 212.5 ms, against 214.9 with the full grid, 280.0 at 5/8 and
 // 226.7 with PM and PP adjoints one after the other).
@@ -762,13 +766,15 @@ int launch_pp_concurrent(cube2_ctx *ctx, const uint16_t *pos, const uint32_t *cs
     Lpp.tile_order = L.pp_order;
     Lpp.hist = L.pp_hist;
     Lpp.scan_tmp = L.pp_scan;
+    const bool small = ctx->nt < kPPConcurrentFullBelowNt;
     if (abar)
         return launch_pp_kernel<true>(ctx, pos, cs, n, abar, acc_pp, 0, work, Lpp, s,
-                                      ctx->pp_halo == 1 ? kPPAdjConcurrentFrac
-                                                        : kPPAdjConcurrentFracH2);
-    const float frac = ctx->pp_halo != 1                  ? kPPConcurrentFracH2
-                       : ctx->nt < kPPConcurrentFullBelowNt ? 1.0f
-                                                            : kPPConcurrentFrac;
+                                      ctx->pp_halo != 1 ? kPPAdjConcurrentFracH2
+                                      : small           ? kPPAdjConcurrentFracSmall
+                                                        : kPPAdjConcurrentFrac);
+    const float frac = ctx->pp_halo != 1 ? kPPConcurrentFracH2
+                       : small           ? 1.0f
+                                         : kPPConcurrentFrac;
     return launch_pp_kernel<false>(ctx, pos, cs, n, nullptr, acc_pp, 0, work, Lpp, s, frac);
 }
 
