@@ -1,7 +1,7 @@
 """GPU parity of isolated boundary conditions (appendix A; context flag
-CUBE2_ISOLATED) against the oracle: a two-level 64^3 mesh whose coarse
-(untruncated) level carries the 1 - sinc(kL) factor, particles in the first
-half of the box.  Green's tables within one FP32 ulp of the oracle's;
+CUBE2_ISOLATED) against the oracle: a two-level 64^3 mesh (coarse ratio 4,
+and 8) whose coarse (untruncated) level carries the 1 - sinc(kL) factor,
+particles in the first half of the box.  Green's tables within one FP32 ulp of the oracle's;
 forces within the force bar, also for single pairs across the matching
 scales (the experiment of section 3.1, run by bench.py --pairwise)."""
 import numpy as np
@@ -15,10 +15,10 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def iso():
+@pytest.fixture(scope="module", params=[4, 8], ids=["ratio4", "ratio8"])
+def iso(request):
     import paper_2512_12629_amd as m
-    n_f, cr = 64, 4
+    n_f, cr = 64, request.param
     x = 0.5 * synthetic.clustered(12, 0.25, 4, 256, 0.5 / 32, 401)   # in [0, 1/2)^3
     c = m.Cube2(m.Config(n_fine=n_f, coarse_ratio=cr, flags=m.CUBE2_ISOLATED), n_max=x.shape[1])
     pos, cs, perm = c.pack(torch.from_numpy(np.ascontiguousarray(x)).cuda())
