@@ -27,6 +27,8 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 CASES = {
     "uniform_64": (64, 0, lambda: synthetic.uniform(32 ** 3, 101)),
     "clustered_64_two_level": (64, 4, lambda: synthetic.clustered(24, 0.25, 6, 512, 0.5 / 64, 102)),
+    # the largest coarse ratio the library takes (8: a coarse mesh of 8^3)
+    "clustered_64_ratio8": (64, 8, lambda: synthetic.clustered(24, 0.25, 6, 512, 0.5 / 64, 105)),
     "zel_32_ragged": (32, 2, lambda: synthetic.zeldovich(13, 0.25, 103)),
     # the single-level Zel'dovich workload at its stated size: 128^3 particles
     # (k^-2 field, rms 0.25 H_p), 256^3 mesh
